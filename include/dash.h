@@ -1,0 +1,218 @@
+/*
+ * dash.h -- C ABI of the MI355X (gfx950) dual-way streaming PARAFAC2 library.
+ *
+ * The operations follow "Fast and Accurate Dual-Way Streaming PARAFAC2 for
+ * Irregular Tensors" (DASH): an irregular tensor {X_k}, slices X_k of shape
+ * I_k x J sharing J columns, modelled as X_k ~ U_k S_k V^T with S_k diagonal
+ * (row k of W), V shared and U_k free (Sec. 2.1).  Updates bring new rows of
+ * existing slices and whole new slices (Problem 1, Sec. 2.2); each update
+ * solves Lemma 1 (new rows of U_k), Lemma 2 (S_k) and Lemma 3 (V) under a
+ * forgetting factor lambda (Sec. 3.1, eq. [new_loss]) without revisiting old
+ * rows (Algorithm 1).
+ *
+ * Conventions for every call:
+ *  - Matrices are dense row-major.  "device" pointers are HIP device memory of
+ *    the context's device; "host" pointers are ordinary CPU memory.
+ *  - Input buffers are borrowed: the library never frees them.  Device row
+ *    buffers handed to dash_ingest_rows / dash_ingest_slices must stay valid and
+ *    unmodified until the dash_update (or dash_wait) that consumes them returns.
+ *  - Output buffers are owned by the caller and sized from dash_get_dims.
+ *  - No call throws; every failure returns a dash_status and leaves a message
+ *    for dash_last_error.  A failed call leaves the context unchanged unless its
+ *    description says otherwise.
+ *  - A context is not thread-safe: serialise calls on one context.  Work is
+ *    enqueued on the context's HIP stream.
+ */
+#ifndef DASH_H
+#define DASH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dash_status {
+  DASH_OK = 0,
+  DASH_E_INVALID_ARG = 1,   /* bad argument; nothing changed                       */
+  DASH_E_OUT_OF_MEMORY = 2, /* device or pinned allocation failed                  */
+  DASH_E_BAD_STATE = 3,     /* call not allowed in the context's current state     */
+  DASH_E_CAPACITY = 4,      /* a capacity fixed at dash_create would be exceeded   */
+  DASH_E_NUMERIC = 5,       /* non-finite factors; the update was rolled back      */
+  DASH_E_DEVICE = 6,        /* a HIP runtime call failed                           */
+  DASH_E_IO = 7             /* checkpoint file could not be read or written        */
+} dash_status;
+
+enum { DASH_PREC_FP32 = 0, DASH_PREC_MIXED = 1 };
+enum { DASH_STATS_EXACT = 0, DASH_STATS_LAGGED = 1 };
+
+typedef struct dash_config {
+  int32_t J;                 /* columns shared by all slices, 1 <= J <= 256              */
+  int32_t R;                 /* target rank, 1 <= R <= 32                                */
+  double lambda;             /* forgetting factor, 0 < lambda <= 1 (Sec. 3.1)            */
+  int32_t n_iter;            /* ALS passes per update; 1 is Algorithm 1                  */
+  int32_t init_max_iter;     /* PARAFAC2-ALS iterations of dash_init (paper: 10)         */
+  double init_tol;           /* stop when |d loss| <= init_tol * loss                   */
+  int32_t precision;         /* DASH_PREC_FP32                                           */
+  int32_t stats_mode;        /* DASH_STATS_EXACT                                         */
+  int64_t max_slices;        /* capacity in slices (K never exceeds it)                  */
+  int64_t max_rows_per_update;   /* capacity in rows staged for one update               */
+  int64_t max_groups_per_update; /* capacity in row groups staged for one update         */
+  int64_t max_init_rows;     /* capacity of dash_init's initial tensor (rows)            */
+  int32_t device;            /* HIP device ordinal                                       */
+  void *stream;              /* hipStream_t to enqueue on; NULL: the library makes one   */
+} dash_config;
+
+typedef struct dash_ctx dash_ctx;
+
+typedef struct dash_update_report {
+  int64_t step;      /* 1-based index of the update this report describes           */
+  int64_t rows;      /* rows consumed by the update (sum of I_{k,new})              */
+  int32_t K;         /* slices after the update                                     */
+  int32_t committed; /* 1 if the update's state was committed                       */
+  double fit;        /* 1 - sqrt(loss)/sqrt(sum_n) after the update                 */
+  double loss;       /* eq. [new_loss] with compounding weights, closed form        */
+  double sum_n;      /* sum over slices of the forgetting-weighted squared norms    */
+} dash_update_report;
+
+typedef struct dash_init_report {
+  int32_t iters;     /* PARAFAC2-ALS iterations run                                 */
+  double loss;       /* loss of the initial decomposition                           */
+  double fit;
+} dash_init_report;
+
+typedef struct dash_dims {
+  int32_t J, R;
+  int32_t K;           /* committed slices                                           */
+  int32_t K_pending;   /* slices including those staged by dash_ingest_slices        */
+  int64_t step;        /* committed updates                                          */
+  int64_t m_last;      /* rows of the last committed update (rows of U_new)          */
+  int64_t rows_pending;
+  int32_t initialized;
+} dash_dims;
+
+/* Fill *cfg with defaults for the given J, R: lambda 0.7, n_iter 1,
+ * init_max_iter 10, init_tol 1e-10 (Sec. 4.1 hyperparameters), FP32 exact mode,
+ * capacities 65536 slices / 1M rows / 65536 groups / 4M initial rows, device 0. */
+void dash_config_default(dash_config *cfg, int32_t J, int32_t R);
+
+/* Create a context: validates cfg (J, R, lambda in (0,1], n_iter >= 1,
+ * capacities >= 1) and allocates every state buffer up front, so later calls
+ * allocate nothing on the device.  Errors: DASH_E_INVALID_ARG,
+ * DASH_E_OUT_OF_MEMORY, DASH_E_DEVICE.  On success *out owns the context. */
+dash_status dash_create(const dash_config *cfg, dash_ctx **out);
+
+/* Wait for outstanding work and free the context.  NULL is a no-op. */
+dash_status dash_destroy(dash_ctx *ctx);
+
+/* Initial decomposition of the initial tensor {X_k}_{k<K} (Sec. 3.2.1):
+ * PARAFAC2-ALS (V0 = top-R eigenvectors of sum_k X_k^T X_k unless V0 is given,
+ * H = I, S_k = I; then per iteration the Procrustes step Q_k = polar(X_k V S_k H^T)
+ * and a CP-ALS sweep H -> V -> W on Y_k = Q_k^T X_k), then the helper terms of
+ * eq. [updateC_init]-[updateG_init] in the exact form Y_k = U_k^T X_k,
+ * D_k = U_k^T U_k, n_k = ||X_k||^2 with U_k = Q_k H.
+ *   row_ptr  host int64[K+1], row_ptr[0] = 0, non-decreasing; slice k is rows
+ *            row_ptr[k] .. row_ptr[k+1]-1 of X (each slice needs >= 1 row).
+ *   X        device float[row_ptr[K] * J].
+ *   V0       device float[J*R] or NULL.
+ *   report   host, may be NULL.
+ * Blocking.  Errors: DASH_E_BAD_STATE if already initialised, DASH_E_CAPACITY,
+ * DASH_E_INVALID_ARG, DASH_E_NUMERIC (context stays uninitialised). */
+dash_status dash_init(dash_ctx *ctx, int32_t K, const int64_t *row_ptr, const float *X,
+                      const float *V0, dash_init_report *report);
+
+/* Helper terms from caller-given factors of the initial tensor
+ * (eq. [updateC_init]-[updateG_init]): Y_k = U_k^T X_k, D_k = U_k^T U_k,
+ * n_k = ||X_k||^2.  row_ptr/X as for dash_init; U device float[row_ptr[K]*R]
+ * (rows aligned with X), W device float[K*R], V device float[J*R].  Blocking. */
+dash_status dash_init_from_factors(dash_ctx *ctx, int32_t K, const int64_t *row_ptr,
+                                   const float *X, const float *U, const float *W,
+                                   const float *V);
+
+/* Stage new rows of existing slices (Problem 1, "Given" item 2).
+ *   n         number of row groups (n >= 0).
+ *   slice_id  host int32[n]; each in [0, K_pending) -- a slice created by a
+ *             staged dash_ingest_slices may be extended too.
+ *   row_ptr   host int64[n+1], non-decreasing; group g is rows
+ *             row_ptr[g] .. row_ptr[g+1]-1 of rows (empty groups are allowed).
+ *   rows      device float[row_ptr[n] * J], borrowed until the update returns.
+ * Rows of one slice are appended in ingest order.  Errors:
+ * DASH_E_INVALID_ARG, DASH_E_CAPACITY, DASH_E_BAD_STATE (not initialised). */
+dash_status dash_ingest_rows(dash_ctx *ctx, int32_t n, const int32_t *slice_id,
+                             const int64_t *row_ptr, const float *rows);
+
+/* Stage L new slices (Problem 1, "Given" item 1); they receive ids
+ * K_pending, K_pending+1, ... in order and *first_id (host) gets the first.
+ *   row_ptr host int64[L+1] with row_ptr[l+1] > row_ptr[l] (>= 1 row each).
+ *   rows    device float[row_ptr[L] * J], borrowed as for dash_ingest_rows. */
+dash_status dash_ingest_slices(dash_ctx *ctx, int32_t L, const int64_t *row_ptr,
+                               const float *rows, int32_t *first_id);
+
+/* Run one update (Algorithm 1 with Lemmas 1-3, n_iter ALS passes) on all
+ * staged data and wait for it.  No staged rows: no-op, DASH_OK, report->rows 0
+ * and no forgetting applied.  On non-finite factors the update is rolled back
+ * (staged data dropped, state as before) and DASH_E_NUMERIC is returned.
+ * report: host, may be NULL. */
+dash_status dash_update(dash_ctx *ctx, dash_update_report *report);
+
+/* Enqueue the update and return without waiting; staged pointers stay borrowed
+ * until dash_wait.  Several updates may be in flight.  If one of them fails
+ * numerically, it and every later in-flight update are discarded and dash_wait
+ * reports DASH_E_NUMERIC with the failing step in report->step. */
+dash_status dash_update_async(dash_ctx *ctx);
+
+/* Wait for all enqueued updates; *report (may be NULL) describes the last one. */
+dash_status dash_wait(dash_ctx *ctx, dash_update_report *report);
+
+/* Copy the current factors into caller-owned device buffers (any may be NULL):
+ *   V      float[J*R];  W float[K*R] (row k = diagonal of S_k);
+ *   U_new  float[m_last*R], the rows of U_{k,new} of the last committed update
+ *          in ingest order (new-slice groups and row groups interleaved exactly
+ *          as they were staged).  U_{k,old} is not retained (Sec. 3.2.2).
+ *   m_last host int64, may be NULL.
+ * Waits for outstanding updates first. */
+dash_status dash_get_factors(dash_ctx *ctx, float *V, float *W, float *U_new, int64_t *m_last);
+
+dash_status dash_get_dims(const dash_ctx *ctx, dash_dims *dims);
+
+/* Export / import the streaming state in float64 host arrays:
+ *   V [J*R], W [K*R], Y [K*R*J] (Y_k = sum lambda^age U_k^T X_k), D [K*R*R]
+ *   (D_k = sum lambda^age U_k^T U_k), n [K] (sum lambda^age ||x||^2).
+ * dash_get_state returns the values as of the last committed update (any
+ * pointer may be NULL).  dash_set_state replaces the whole state (marks the
+ * context initialised, K slices, step kept) -- it is how a checkpoint is
+ * restored and how tests start both implementations from one state. */
+dash_status dash_get_state(dash_ctx *ctx, double *V, double *W, double *Y, double *D, double *n);
+dash_status dash_set_state(dash_ctx *ctx, int32_t K, const double *V, const double *W,
+                           const double *Y, const double *D, const double *n);
+
+/* Checkpoint the committed state to a file and restore it.  The file holds the
+ * state exactly as the device keeps it (float32 Y_k, D_k, float64 n_k, W, V,
+ * and the update index at which each slice was last folded), so a restored
+ * context continues bit for bit like the one that was saved.  dash_load needs
+ * a context with the same J, R and lambda and enough max_slices; it replaces
+ * the state and the update counter.  Errors: DASH_E_IO, DASH_E_INVALID_ARG. */
+dash_status dash_save(dash_ctx *ctx, const char *path);
+dash_status dash_load(dash_ctx *ctx, const char *path);
+
+/* Per-kernel device time of the update path, measured with HIP events recorded
+ * around each launch on the context's stream.  dash_profile(ctx, 1) clears the
+ * counters and starts recording; dash_profile(ctx, 0) stops.  dash_profile_read
+ * waits for outstanding work and returns the sums since the last clear. */
+typedef struct dash_profile_stats {
+  int64_t updates;
+  int64_t pass_launches, reduce_launches, solve_launches, commit_launches, upload_launches;
+  double pass_ms, reduce_ms, solve_ms, commit_ms, upload_ms;
+} dash_profile_stats;
+
+dash_status dash_profile(dash_ctx *ctx, int32_t enable);
+dash_status dash_profile_read(dash_ctx *ctx, dash_profile_stats *out);
+
+const char *dash_status_string(dash_status s);
+const char *dash_last_error(const dash_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DASH_H */

@@ -1,0 +1,946 @@
+// Host core of libdash: the C ABI of include/dash.h.
+//
+// Owns every device buffer (allocated once in dash_create), validates and
+// stages ingested row groups (metadata on the host, rows left in the caller's
+// device buffers), builds the per-update descriptor block and enqueues the
+// kernel sequence of dash_kernels.hip.  Updates are transactional: kernels
+// write the next state beside the committed one and k_commit switches to it
+// only if the update's factors are finite.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dash.h"
+#include "dash_dev.h"
+
+using namespace dash;
+
+namespace {
+
+constexpr int kStages = 4;             // pinned descriptor blocks in rotation
+constexpr int kMaxChunks = 4096;       // bound on sweep chunks (partials memory)
+constexpr int kChunksPerRGroup = 16;   // first-level reduction fan-in
+
+struct PendingGroup {
+  int32_t slice;
+  const float *src;
+  int64_t nrows;
+  int64_t out_row;
+};
+
+struct InFlight {
+  int64_t step;
+  int32_t K_prev, K_after;
+  int64_t rows;
+  int slot;
+};
+
+}  // namespace
+
+struct dash_ctx {
+  dash_config cfg{};
+  int J = 0, R = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  int64_t K_cap = 0, M_cap = 0, G_cap = 0, N_init_cap = 0;
+  int64_t touched_cap = 0;
+  // device state
+  float *Y = nullptr;
+  float *D = nullptr;
+  double *n = nullptr;
+  uint8_t *cur = nullptr;
+  int32_t *tlast = nullptr;
+  double *W = nullptr;
+  char *vb = nullptr;
+  int64_t vb_stride = 0;
+  Ctl *ctl = nullptr;
+  float *U_out = nullptr;
+  double *partials = nullptr;
+  double *gpart = nullptr;
+  int64_t *d_rowptr = nullptr;
+  char *dstep = nullptr;
+  size_t off_tptr = 0, off_touched = 0, off_groups = 0, step_bytes = 0;
+  // pinned
+  char *hstage[kStages] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t stage_ev[kStages] = {nullptr, nullptr, nullptr, nullptr};
+  bool stage_used[kStages] = {false, false, false, false};
+  int stage_next = 0;
+  Report *hreport = nullptr;
+  Report *dreport = nullptr;
+  // host-side view of the state
+  bool initialized = false;
+  int32_t K = 0;          // committed slices
+  int64_t step = 0;       // committed updates
+  int64_t m_last = 0;     // rows of the last committed update
+  int32_t K_enq = 0;      // slices after the last enqueued update
+  int64_t step_enq = 0;
+  int32_t K_pending = 0;  // including staged new slices
+  std::vector<PendingGroup> pending;
+  int64_t rows_pending = 0;
+  std::deque<InFlight> inflight;
+  int chunk_override = 0;
+  std::vector<int> order;  // scratch
+  // profiling: event pairs around launches, folded into stats on read
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;  // kind per recorded pair
+  int ev_used = 0;           // pairs recorded since the last fold
+  dash_profile_stats prof{};
+};
+
+namespace {
+
+dash_status fail(dash_ctx *c, dash_status s, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIP_OR_FAIL(c, expr)                                                          \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((c), DASH_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_OR_FAIL(c, expr)                                                        \
+  do {                                                                                 \
+    int e_ = (expr);                                                                   \
+    if (e_ != 0)                                                                       \
+      return fail((c), DASH_E_DEVICE, "%s failed: %s", #expr,                          \
+                  hipGetErrorString((hipError_t)e_));                                  \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t bytes) {
+  return hipMalloc((void **)p, bytes < 256 ? 256 : bytes);
+}
+
+int choose_chunk(const dash_ctx *c, int K) {
+  if (c->chunk_override > 0) return c->chunk_override;
+  // ~2 workgroups per CU of 256 CUs, never more than kMaxChunks chunks
+  int ch = (K + 511) / 512;
+  if (ch < 1) ch = 1;
+  while ((K + ch - 1) / ch > kMaxChunks) ++ch;
+  return ch;
+}
+
+StepHeader *stage_header(char *blk) { return (StepHeader *)blk; }
+
+enum { kProfPass = 0, kProfReduce, kProfSolve, kProfCommit, kProfUpload };
+constexpr int kProfPairs = 1024;
+
+// Fold recorded event pairs into the stats (the stream must be idle).
+hipError_t prof_fold(dash_ctx *c) {
+  for (int i = 0; i < c->ev_used; ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    switch (c->ev_kind[i]) {
+      case kProfPass: c->prof.pass_launches++; c->prof.pass_ms += ms; break;
+      case kProfReduce: c->prof.reduce_launches++; c->prof.reduce_ms += ms; break;
+      case kProfSolve: c->prof.solve_launches++; c->prof.solve_ms += ms; break;
+      case kProfCommit: c->prof.commit_launches++; c->prof.commit_ms += ms; break;
+      default: c->prof.upload_launches++; c->prof.upload_ms += ms; break;
+    }
+  }
+  c->ev_used = 0;
+  return hipSuccess;
+}
+
+// Open / close a timed region around one launch (no-ops unless profiling).
+hipError_t prof_begin(dash_ctx *c, int kind) {
+  if (!c->profiling) return hipSuccess;
+  if (c->ev_used == kProfPairs) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = prof_fold(c);
+    if (e != hipSuccess) return e;
+  }
+  c->ev_kind[c->ev_used] = kind;
+  return hipEventRecord(c->ev[2 * c->ev_used], c->stream);
+}
+
+hipError_t prof_end(dash_ctx *c) {
+  if (!c->profiling) return hipSuccess;
+  hipError_t e = hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream);
+  c->ev_used++;
+  return e;
+}
+
+// Wait until a pinned descriptor block can be rewritten.
+hipError_t take_stage(dash_ctx *c, int *idx) {
+  const int s = c->stage_next;
+  c->stage_next = (c->stage_next + 1) % kStages;
+  if (c->stage_used[s]) {
+    hipError_t e = hipEventSynchronize(c->stage_ev[s]);
+    if (e != hipSuccess) return e;
+  }
+  *idx = s;
+  return hipSuccess;
+}
+
+// Fill the chunk table of a sweep over K slices with no touched slice.
+void fill_empty_tables(dash_ctx *c, char *blk, int n_chunks) {
+  int32_t *tptr = (int32_t *)(blk + c->off_tptr);
+  for (int i = 0; i <= n_chunks; ++i) tptr[i] = 0;
+}
+
+// Enqueue an evaluation sweep (F, G from the committed W) + fit.
+dash_status enqueue_eval(dash_ctx *c, int K) {
+  int s;
+  HIP_OR_FAIL(c, take_stage(c, &s));
+  char *blk = c->hstage[s];
+  StepHeader *h = stage_header(blk);
+  const int ch = choose_chunk(c, K);
+  const int nch = (K + ch - 1) / ch;
+  h->K = K;
+  h->K_prev = K;
+  h->n_touched = 0;
+  h->n_groups = 0;
+  h->n_chunks = nch;
+  h->chunk = ch;
+  h->chunks_per_rgroup = kChunksPerRGroup;
+  h->n_rgroups = (nch + kChunksPerRGroup - 1) / kChunksPerRGroup;
+  h->step = c->step;
+  h->M = 0;
+  h->report = nullptr;
+  fill_empty_tables(c, blk, nch);
+  const size_t bytes = c->off_tptr + sizeof(int32_t) * (nch + 1);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dstep, blk, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
+  c->stage_used[s] = true;
+  PassArgs a{};
+  a.J = c->J;
+  a.R = c->R;
+  a.lambda = c->cfg.lambda;
+  a.pass = 0;
+  a.write_u = 0;
+  a.mode = 1;
+  a.K_cap = c->K_cap;
+  a.hdr = (const StepHeader *)c->dstep;
+  a.chunk_tptr = (const int32_t *)(c->dstep + c->off_tptr);
+  a.touched = (const Touched *)(c->dstep + c->off_touched);
+  a.groups = (const Group *)(c->dstep + c->off_groups);
+  a.Y = c->Y;
+  a.D = c->D;
+  a.n = c->n;
+  a.cur = c->cur;
+  a.tlast = c->tlast;
+  a.W = c->W;
+  a.vb = c->vb;
+  a.vb_stride = c->vb_stride;
+  a.ctl = c->ctl;
+  a.U_out = c->U_out;
+  a.partials = c->partials;
+  const int plen = partial_len(c->J, c->R);
+  LAUNCH_OR_FAIL(c, launch_pass(a, nch, c->stream));
+  LAUNCH_OR_FAIL(c, launch_reduce(c->partials, c->gpart, a.hdr, plen, nch, h->n_rgroups,
+                                  kChunksPerRGroup, c->stream));
+  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, h->n_rgroups, c->vb, c->vb_stride, c->ctl,
+                                 2, c->stream));
+  return DASH_OK;
+}
+
+dash_status reset_device_state(dash_ctx *c, int32_t K, int32_t tl) {
+  HIP_OR_FAIL(c, hipMemsetAsync(c->cur, 0, (size_t)c->K_cap, c->stream));
+  std::vector<int32_t> t(std::max<int32_t>(K, 1), tl);
+  if (K > 0)
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->tlast, t.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice,
+                                  c->stream));
+  Ctl ctl{};
+  ctl.gcur = 0;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return DASH_OK;
+}
+
+dash_status validate_ptr(dash_ctx *c, const int64_t *ptr, int64_t n, bool nonempty) {
+  if (!ptr) return fail(c, DASH_E_INVALID_ARG, "row_ptr is NULL");
+  if (ptr[0] < 0) return fail(c, DASH_E_INVALID_ARG, "row_ptr[0] < 0");
+  for (int64_t i = 0; i < n; ++i) {
+    if (ptr[i + 1] < ptr[i]) return fail(c, DASH_E_INVALID_ARG, "row_ptr decreases at %lld", (long long)i);
+    if (nonempty && ptr[i + 1] == ptr[i])
+      return fail(c, DASH_E_INVALID_ARG, "group %lld has no rows", (long long)i);
+  }
+  return DASH_OK;
+}
+
+dash_status read_ctl(dash_ctx *c, Ctl *out) {
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  HIP_OR_FAIL(c, hipMemcpy(out, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  return DASH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dash_config_default(dash_config *cfg, int32_t J, int32_t R) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->J = J;
+  cfg->R = R;
+  cfg->lambda = 0.7;
+  cfg->n_iter = 1;
+  cfg->init_max_iter = 10;
+  cfg->init_tol = 1e-10;
+  cfg->precision = DASH_PREC_FP32;
+  cfg->stats_mode = DASH_STATS_EXACT;
+  cfg->max_slices = 65536;
+  cfg->max_rows_per_update = 1 << 20;
+  cfg->max_groups_per_update = 65536;
+  cfg->max_init_rows = 4 << 20;
+  cfg->device = 0;
+  cfg->stream = nullptr;
+}
+
+dash_status dash_profile(dash_ctx *c, int32_t enable) {
+  if (!c) return DASH_E_INVALID_ARG;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * kProfPairs, nullptr);
+    c->ev_kind.resize(kProfPairs, 0);
+    for (auto &e : c->ev) HIP_OR_FAIL(c, hipEventCreate(&e));
+  }
+  if (c->profiling) HIP_OR_FAIL(c, prof_fold(c));
+  c->ev_used = 0;
+  c->prof = dash_profile_stats{};
+  c->profiling = enable != 0;
+  return DASH_OK;
+}
+
+dash_status dash_profile_read(dash_ctx *c, dash_profile_stats *out) {
+  if (!c || !out) return DASH_E_INVALID_ARG;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  HIP_OR_FAIL(c, prof_fold(c));
+  *out = c->prof;
+  return DASH_OK;
+}
+
+const char *dash_status_string(dash_status s) {
+  switch (s) {
+    case DASH_OK: return "ok";
+    case DASH_E_INVALID_ARG: return "invalid argument";
+    case DASH_E_OUT_OF_MEMORY: return "out of memory";
+    case DASH_E_BAD_STATE: return "bad state";
+    case DASH_E_CAPACITY: return "capacity exceeded";
+    case DASH_E_NUMERIC: return "non-finite factors (update rolled back)";
+    case DASH_E_DEVICE: return "HIP runtime error";
+    case DASH_E_IO: return "checkpoint I/O error";
+  }
+  return "unknown status";
+}
+
+const char *dash_last_error(const dash_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
+  if (!cfg || !out) return DASH_E_INVALID_ARG;
+  *out = nullptr;
+  if (cfg->J < 1 || cfg->J > kMaxJ || cfg->R < 1 || cfg->R > kMaxR) return DASH_E_INVALID_ARG;
+  if (!(cfg->lambda > 0.0 && cfg->lambda <= 1.0) || cfg->n_iter < 1 || cfg->init_max_iter < 0)
+    return DASH_E_INVALID_ARG;
+  if (cfg->max_slices < 1 || cfg->max_slices > (int64_t)1 << 30 || cfg->max_rows_per_update < 1 ||
+      cfg->max_groups_per_update < 1 || cfg->max_init_rows < 0)
+    return DASH_E_INVALID_ARG;
+  if (cfg->precision != DASH_PREC_FP32 || cfg->stats_mode != DASH_STATS_EXACT)
+    return DASH_E_INVALID_ARG;
+  dash_ctx *c = new (std::nothrow) dash_ctx();
+  if (!c) return DASH_E_OUT_OF_MEMORY;
+  c->cfg = *cfg;
+  c->J = cfg->J;
+  c->R = cfg->R;
+  c->K_cap = cfg->max_slices;
+  c->M_cap = cfg->max_rows_per_update;
+  c->G_cap = cfg->max_groups_per_update + c->K_cap;  // new slices are groups too
+  c->N_init_cap = cfg->max_init_rows;
+  c->touched_cap = std::min<int64_t>(c->K_cap, c->G_cap);
+  if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
+  auto bail = [&](dash_status s) {
+    dash_destroy(c);
+    return s;
+  };
+  if (hipSetDevice(cfg->device) != hipSuccess) return bail(DASH_E_DEVICE);
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(DASH_E_DEVICE);
+    c->own_stream = true;
+  }
+  const int64_t J = c->J, R = c->R, Kc = c->K_cap;
+  const int64_t n_chunks_cap = std::min<int64_t>(Kc, kMaxChunks);
+  const int64_t plen = partial_len(c->J, c->R);
+  c->vb_stride = vb_bytes(c->J, c->R);
+  bool ok = dalloc(&c->Y, sizeof(float) * 2 * Kc * R * J) == hipSuccess &&
+            dalloc(&c->D, sizeof(float) * 2 * Kc * R * R) == hipSuccess &&
+            dalloc(&c->n, sizeof(double) * 2 * Kc) == hipSuccess &&
+            dalloc(&c->cur, (size_t)Kc) == hipSuccess &&
+            dalloc(&c->tlast, sizeof(int32_t) * Kc) == hipSuccess &&
+            dalloc(&c->W, sizeof(double) * 2 * Kc * R) == hipSuccess &&
+            dalloc(&c->vb, (size_t)(2 * c->vb_stride)) == hipSuccess &&
+            dalloc(&c->ctl, sizeof(Ctl)) == hipSuccess &&
+            dalloc(&c->U_out, sizeof(float) * c->M_cap * R) == hipSuccess &&
+            dalloc(&c->partials, sizeof(double) * n_chunks_cap * plen) == hipSuccess &&
+            dalloc(&c->gpart, sizeof(double) * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) == hipSuccess &&
+            dalloc(&c->d_rowptr, sizeof(int64_t) * (Kc + 1)) == hipSuccess;
+  if (!ok) return bail(DASH_E_OUT_OF_MEMORY);
+  c->off_tptr = align_up(sizeof(StepHeader), 64);
+  c->off_touched = align_up(c->off_tptr + sizeof(int32_t) * (n_chunks_cap + 1), 64);
+  c->off_groups = align_up(c->off_touched + sizeof(Touched) * c->touched_cap, 64);
+  c->step_bytes = align_up(c->off_groups + sizeof(Group) * c->G_cap, 256);
+  if (dalloc(&c->dstep, c->step_bytes) != hipSuccess) return bail(DASH_E_OUT_OF_MEMORY);
+  for (int s = 0; s < kStages; ++s) {
+    if (hipHostMalloc((void **)&c->hstage[s], c->step_bytes, hipHostMallocDefault) != hipSuccess)
+      return bail(DASH_E_OUT_OF_MEMORY);
+    if (hipEventCreateWithFlags(&c->stage_ev[s], hipEventDisableTiming) != hipSuccess)
+      return bail(DASH_E_DEVICE);
+  }
+  if (hipHostMalloc((void **)&c->hreport, sizeof(Report) * kReportRing, hipHostMallocMapped) != hipSuccess)
+    return bail(DASH_E_OUT_OF_MEMORY);
+  std::memset(c->hreport, 0, sizeof(Report) * kReportRing);
+  if (hipHostGetDevicePointer((void **)&c->dreport, c->hreport, 0) != hipSuccess) return bail(DASH_E_DEVICE);
+  if (hipMemsetAsync(c->cur, 0, (size_t)Kc, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * Kc, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(DASH_E_DEVICE);
+  c->pending.reserve(1024);
+  *out = c;
+  return DASH_OK;
+}
+
+dash_status dash_destroy(dash_ctx *c) {
+  if (!c) return DASH_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->Y);
+  (void)hipFree(c->D);
+  (void)hipFree(c->n);
+  (void)hipFree(c->cur);
+  (void)hipFree(c->tlast);
+  (void)hipFree(c->W);
+  (void)hipFree(c->vb);
+  (void)hipFree(c->ctl);
+  (void)hipFree(c->U_out);
+  (void)hipFree(c->partials);
+  (void)hipFree(c->gpart);
+  (void)hipFree(c->d_rowptr);
+  (void)hipFree(c->dstep);
+  for (int s = 0; s < kStages; ++s) {
+    if (c->hstage[s]) (void)hipHostFree(c->hstage[s]);
+    if (c->stage_ev[s]) (void)hipEventDestroy(c->stage_ev[s]);
+  }
+  if (c->hreport) (void)hipHostFree(c->hreport);
+  for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return DASH_OK;
+}
+
+dash_status dash_get_dims(const dash_ctx *c, dash_dims *d) {
+  if (!c || !d) return DASH_E_INVALID_ARG;
+  d->J = c->J;
+  d->R = c->R;
+  d->K = c->K;
+  d->K_pending = c->K_pending;
+  d->step = c->step;
+  d->m_last = c->m_last;
+  d->rows_pending = c->rows_pending;
+  d->initialized = c->initialized ? 1 : 0;
+  return DASH_OK;
+}
+
+dash_status dash_init_from_factors(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X,
+                                   const float *U, const float *W, const float *V) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (c->initialized) return fail(c, DASH_E_BAD_STATE, "context already initialised");
+  if (K < 1) return fail(c, DASH_E_INVALID_ARG, "K must be >= 1");
+  if (K > c->K_cap) return fail(c, DASH_E_CAPACITY, "K=%d exceeds max_slices", K);
+  if (!X || !U || !W || !V) return fail(c, DASH_E_INVALID_ARG, "NULL factor or data pointer");
+  if (dash_status s = validate_ptr(c, row_ptr, K, true)) return s;
+  if (row_ptr[0] != 0) return fail(c, DASH_E_INVALID_ARG, "row_ptr[0] must be 0");
+  if (dash_status s = reset_device_state(c, K, 0)) return s;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_rowptr, row_ptr, sizeof(int64_t) * (K + 1),
+                                hipMemcpyHostToDevice, c->stream));
+  LAUNCH_OR_FAIL(c, launch_accum_given_u(c->J, c->R, K, c->d_rowptr, X, U, c->Y, c->D, c->n, c->stream));
+  LAUNCH_OR_FAIL(c, launch_w_from_f32(c->R, K, W, c->W, c->stream));
+  LAUNCH_OR_FAIL(c, launch_v_from_f32(c->J, c->R, V, c->vb, c->stream));
+  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, 0, c->vb, c->vb_stride, c->ctl, 1, c->stream));
+  c->step = 0;
+  if (dash_status s = enqueue_eval(c, K)) return s;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->initialized = true;
+  c->K = c->K_enq = c->K_pending = K;
+  c->step = c->step_enq = 0;
+  c->m_last = 0;
+  c->pending.clear();
+  c->rows_pending = 0;
+  return DASH_OK;
+}
+
+dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
+                      dash_init_report *report) {
+  (void)K;
+  (void)row_ptr;
+  (void)X;
+  (void)V0;
+  (void)report;
+  return fail(c, DASH_E_BAD_STATE, "dash_init is not available in this build");
+}
+
+dash_status dash_ingest_rows(dash_ctx *c, int32_t n, const int32_t *slice_id, const int64_t *row_ptr,
+                             const float *rows) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (n < 0) return fail(c, DASH_E_INVALID_ARG, "n < 0");
+  if (n == 0) return DASH_OK;
+  if (!slice_id) return fail(c, DASH_E_INVALID_ARG, "slice_id is NULL");
+  if (dash_status s = validate_ptr(c, row_ptr, n, false)) return s;
+  const int64_t add = row_ptr[n] - row_ptr[0];
+  if (add > 0 && !rows) return fail(c, DASH_E_INVALID_ARG, "rows is NULL");
+  int64_t ng = 0;
+  for (int32_t g = 0; g < n; ++g) {
+    if (slice_id[g] < 0 || slice_id[g] >= c->K_pending)
+      return fail(c, DASH_E_INVALID_ARG, "slice_id[%d]=%d out of range [0,%d)", g, slice_id[g], c->K_pending);
+    if (row_ptr[g + 1] > row_ptr[g]) ++ng;
+  }
+  if (c->rows_pending + add > c->M_cap)
+    return fail(c, DASH_E_CAPACITY, "rows per update would exceed %lld", (long long)c->M_cap);
+  if ((int64_t)c->pending.size() + ng > c->G_cap)
+    return fail(c, DASH_E_CAPACITY, "row groups per update would exceed %lld", (long long)c->G_cap);
+  for (int32_t g = 0; g < n; ++g) {
+    const int64_t m = row_ptr[g + 1] - row_ptr[g];
+    if (m == 0) continue;
+    c->pending.push_back({slice_id[g], rows + row_ptr[g] * c->J, m, c->rows_pending});
+    c->rows_pending += m;
+  }
+  return DASH_OK;
+}
+
+dash_status dash_ingest_slices(dash_ctx *c, int32_t L, const int64_t *row_ptr, const float *rows,
+                               int32_t *first_id) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (L < 0) return fail(c, DASH_E_INVALID_ARG, "L < 0");
+  if (first_id) *first_id = c->K_pending;
+  if (L == 0) return DASH_OK;
+  if (dash_status s = validate_ptr(c, row_ptr, L, true)) return s;
+  if (!rows) return fail(c, DASH_E_INVALID_ARG, "rows is NULL");
+  const int64_t add = row_ptr[L] - row_ptr[0];
+  if ((int64_t)c->K_pending + L > c->K_cap)
+    return fail(c, DASH_E_CAPACITY, "slices would exceed max_slices=%lld", (long long)c->K_cap);
+  if (c->rows_pending + add > c->M_cap)
+    return fail(c, DASH_E_CAPACITY, "rows per update would exceed %lld", (long long)c->M_cap);
+  if ((int64_t)c->pending.size() + L > c->G_cap)
+    return fail(c, DASH_E_CAPACITY, "row groups per update would exceed %lld", (long long)c->G_cap);
+  for (int32_t l = 0; l < L; ++l) {
+    const int64_t m = row_ptr[l + 1] - row_ptr[l];
+    c->pending.push_back({c->K_pending + l, rows + row_ptr[l] * c->J, m, c->rows_pending});
+    c->rows_pending += m;
+  }
+  c->K_pending += L;
+  return DASH_OK;
+}
+
+dash_status dash_update_async(dash_ctx *c) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (c->rows_pending == 0) return DASH_OK;  // empty update: no-op, no forgetting
+  if ((int)c->inflight.size() >= kReportRing - 1) {
+    dash_status s = dash_wait(c, nullptr);
+    if (s != DASH_OK) return s;
+  }
+  const int K = c->K_pending, Kp = c->K_enq;
+  const int ch = choose_chunk(c, K);
+  const int nch = (K + ch - 1) / ch;
+  int s;
+  HIP_OR_FAIL(c, take_stage(c, &s));
+  char *blk = c->hstage[s];
+  StepHeader *h = stage_header(blk);
+  int32_t *tptr = (int32_t *)(blk + c->off_tptr);
+  Touched *tch = (Touched *)(blk + c->off_touched);
+  Group *grp = (Group *)(blk + c->off_groups);
+  // groups sorted by slice, ingest order kept within a slice
+  const int ng = (int)c->pending.size();
+  bool sorted = true;
+  for (int g = 1; g < ng; ++g)
+    if (c->pending[g].slice < c->pending[g - 1].slice) { sorted = false; break; }
+  c->order.resize(ng);
+  for (int g = 0; g < ng; ++g) c->order[g] = g;
+  if (!sorted)
+    std::stable_sort(c->order.begin(), c->order.end(),
+                     [&](int a, int b) { return c->pending[a].slice < c->pending[b].slice; });
+  int nt = 0;
+  for (int i = 0; i < ng; ++i) {
+    const PendingGroup &pg = c->pending[c->order[i]];
+    grp[i].src = pg.src;
+    grp[i].out_row = pg.out_row;
+    grp[i].nrows = (int32_t)pg.nrows;
+    grp[i].pad = 0;
+    if (nt == 0 || tch[nt - 1].slice != pg.slice) {
+      tch[nt].slice = pg.slice;
+      tch[nt].g_begin = i;
+      tch[nt].pad = 0;
+      ++nt;
+    }
+    tch[nt - 1].g_end = i + 1;
+  }
+  int t = 0;
+  for (int cidx = 0; cidx <= nch; ++cidx) {
+    const int first = cidx * ch;
+    while (t < nt && tch[t].slice < first) ++t;
+    tptr[cidx] = t;
+  }
+  const int64_t step = c->step_enq + 1;
+  const int slot = (int)(step % kReportRing);
+  h->K = K;
+  h->K_prev = Kp;
+  h->n_touched = nt;
+  h->n_groups = ng;
+  h->n_chunks = nch;
+  h->chunk = ch;
+  h->chunks_per_rgroup = kChunksPerRGroup;
+  h->n_rgroups = (nch + kChunksPerRGroup - 1) / kChunksPerRGroup;
+  h->step = step;
+  h->M = c->rows_pending;
+  h->report = (void *)(c->dreport + slot);
+  c->hreport[slot].done = 0;
+  const size_t bytes = c->off_groups + sizeof(Group) * ng;
+  HIP_OR_FAIL(c, prof_begin(c, kProfUpload));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dstep, blk, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, prof_end(c));
+  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
+  c->stage_used[s] = true;
+
+  PassArgs a{};
+  a.J = c->J;
+  a.R = c->R;
+  a.lambda = c->cfg.lambda;
+  a.K_cap = c->K_cap;
+  a.hdr = (const StepHeader *)c->dstep;
+  a.chunk_tptr = (const int32_t *)(c->dstep + c->off_tptr);
+  a.touched = (const Touched *)(c->dstep + c->off_touched);
+  a.groups = (const Group *)(c->dstep + c->off_groups);
+  a.Y = c->Y;
+  a.D = c->D;
+  a.n = c->n;
+  a.cur = c->cur;
+  a.tlast = c->tlast;
+  a.W = c->W;
+  a.vb = c->vb;
+  a.vb_stride = c->vb_stride;
+  a.ctl = c->ctl;
+  a.U_out = c->U_out;
+  a.partials = c->partials;
+  a.mode = 0;
+  const int plen = partial_len(c->J, c->R);
+  for (int p = 0; p < c->cfg.n_iter; ++p) {
+    a.pass = p;
+    a.write_u = (p == c->cfg.n_iter - 1) ? 1 : 0;
+    HIP_OR_FAIL(c, prof_begin(c, kProfPass));
+    LAUNCH_OR_FAIL(c, launch_pass(a, nch, c->stream));
+    HIP_OR_FAIL(c, prof_end(c));
+    HIP_OR_FAIL(c, prof_begin(c, kProfReduce));
+    LAUNCH_OR_FAIL(c, launch_reduce(c->partials, c->gpart, a.hdr, plen, nch, h->n_rgroups,
+                                    kChunksPerRGroup, c->stream));
+    HIP_OR_FAIL(c, prof_end(c));
+    HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
+    LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, h->n_rgroups, c->vb, c->vb_stride, c->ctl,
+                                   0, c->stream));
+    HIP_OR_FAIL(c, prof_end(c));
+  }
+  HIP_OR_FAIL(c, prof_begin(c, kProfCommit));
+  LAUNCH_OR_FAIL(c, launch_commit(a.hdr, a.touched, c->cur, c->tlast, c->ctl, nt, c->stream));
+  HIP_OR_FAIL(c, prof_end(c));
+  if (c->profiling) c->prof.updates++;
+  c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
+  c->K_enq = K;
+  c->step_enq = step;
+  c->pending.clear();
+  c->rows_pending = 0;
+  return DASH_OK;
+}
+
+dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
+  if (!c) return DASH_E_INVALID_ARG;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  dash_status st = DASH_OK;
+  bool failed = false;
+  int64_t failed_step = 0;
+  while (!c->inflight.empty()) {
+    const InFlight f = c->inflight.front();
+    c->inflight.pop_front();
+    const Report &r = c->hreport[f.slot];
+    if (!failed && r.committed) {
+      c->K = f.K_after;
+      c->step = f.step;
+      c->m_last = f.rows;
+      if (rep) {
+        rep->step = r.step;
+        rep->rows = r.rows;
+        rep->K = r.K;
+        rep->committed = 1;
+        rep->fit = r.fit;
+        rep->loss = r.loss;
+        rep->sum_n = r.sum_n;
+      }
+    } else if (!failed) {
+      failed = true;
+      failed_step = f.step;
+      if (rep) {
+        rep->step = f.step;
+        rep->rows = f.rows;
+        rep->K = f.K_prev;
+        rep->committed = 0;
+        rep->fit = r.fit;
+        rep->loss = r.loss;
+        rep->sum_n = r.sum_n;
+      }
+    }
+  }
+  if (failed) {
+    // discard the failed update and everything enqueued after it
+    Ctl ctl;
+    HIP_OR_FAIL(c, hipMemcpy(&ctl, c->ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    ctl.poison = 0;
+    HIP_OR_FAIL(c, hipMemcpy(c->ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice));
+    c->K_enq = c->K_pending = c->K;
+    c->step_enq = c->step;
+    c->m_last = 0;
+    c->pending.clear();
+    c->rows_pending = 0;
+    st = fail(c, DASH_E_NUMERIC, "update %lld produced non-finite factors; rolled back",
+              (long long)failed_step);
+  }
+  return st;
+}
+
+dash_status dash_update(dash_ctx *c, dash_update_report *rep) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (c->rows_pending == 0 && c->inflight.empty()) {
+    if (rep) {
+      Ctl ctl;
+      if (dash_status s = read_ctl(c, &ctl)) return s;
+      rep->step = c->step;
+      rep->rows = 0;
+      rep->K = c->K;
+      rep->committed = 1;
+      rep->fit = ctl.fit;
+      rep->loss = ctl.loss;
+      rep->sum_n = ctl.sum_n;
+    }
+    return DASH_OK;
+  }
+  if (dash_status s = dash_update_async(c)) return s;
+  return dash_wait(c, rep);
+}
+
+dash_status dash_get_factors(dash_ctx *c, float *V, float *W, float *U_new, int64_t *m_last) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  Ctl ctl;
+  if (dash_status s = read_ctl(c, &ctl)) return s;
+  const VBundleView v = vb_view(c->vb + (int64_t)ctl.gcur * c->vb_stride, c->J, c->R);
+  if (V) LAUNCH_OR_FAIL(c, launch_to_f32(v.V64, V, (int64_t)c->J * c->R, c->stream));
+  if (W) LAUNCH_OR_FAIL(c, launch_to_f32(c->W + (int64_t)ctl.gcur * c->K_cap * c->R, W, (int64_t)c->K * c->R, c->stream));
+  if (U_new && c->m_last > 0)
+    HIP_OR_FAIL(c, hipMemcpyAsync(U_new, c->U_out, sizeof(float) * c->m_last * c->R,
+                                  hipMemcpyDeviceToDevice, c->stream));
+  if (m_last) *m_last = c->m_last;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return DASH_OK;
+}
+
+dash_status dash_get_state(dash_ctx *c, double *V, double *W, double *Y, double *D, double *n) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  Ctl ctl;
+  if (dash_status s = read_ctl(c, &ctl)) return s;
+  const int64_t K = c->K, J = c->J, R = c->R;
+  const VBundleView v = vb_view(c->vb + (int64_t)ctl.gcur * c->vb_stride, c->J, c->R);
+  if (V) HIP_OR_FAIL(c, hipMemcpy(V, v.V64, sizeof(double) * J * R, hipMemcpyDeviceToHost));
+  if (W) HIP_OR_FAIL(c, hipMemcpy(W, c->W + (int64_t)ctl.gcur * c->K_cap * R, sizeof(double) * K * R, hipMemcpyDeviceToHost));
+  if (Y || D || n) {
+    double *dY = nullptr, *dD = nullptr, *dn = nullptr;
+    if (dalloc(&dY, sizeof(double) * K * R * J) != hipSuccess || dalloc(&dD, sizeof(double) * K * R * R) != hipSuccess ||
+        dalloc(&dn, sizeof(double) * K) != hipSuccess) {
+      hipFree(dY);
+      hipFree(dD);
+      hipFree(dn);
+      return fail(c, DASH_E_OUT_OF_MEMORY, "export buffers");
+    }
+    int e = launch_export_state(c->J, c->R, c->K, c->step, c->cfg.lambda, c->Y, c->D, c->n, c->cur, c->tlast,
+                                c->K_cap, dY, dD, dn, c->stream);
+    hipError_t he = (hipError_t)e;
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he == hipSuccess && Y) he = hipMemcpy(Y, dY, sizeof(double) * K * R * J, hipMemcpyDeviceToHost);
+    if (he == hipSuccess && D) he = hipMemcpy(D, dD, sizeof(double) * K * R * R, hipMemcpyDeviceToHost);
+    if (he == hipSuccess && n) he = hipMemcpy(n, dn, sizeof(double) * K, hipMemcpyDeviceToHost);
+    hipFree(dY);
+    hipFree(dD);
+    hipFree(dn);
+    if (he != hipSuccess) return fail(c, DASH_E_DEVICE, "state export: %s", hipGetErrorString(he));
+  }
+  return DASH_OK;
+}
+
+dash_status dash_set_state(dash_ctx *c, int32_t K, const double *V, const double *W, const double *Y,
+                           const double *D, const double *n) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (K < 1) return fail(c, DASH_E_INVALID_ARG, "K must be >= 1");
+  if (K > c->K_cap) return fail(c, DASH_E_CAPACITY, "K=%d exceeds max_slices", K);
+  if (!V || !W || !Y || !D || !n) return fail(c, DASH_E_INVALID_ARG, "NULL state array");
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  const int64_t J = c->J, R = c->R;
+  const int64_t tl = c->step;
+  if (dash_status s = reset_device_state(c, K, (int32_t)tl)) return s;
+  // the state is stored in float32 (Y, D) and float64 (n, W, V); the cast is the
+  // only host-side arithmetic
+  std::vector<float> f((size_t)std::max<int64_t>(K * R * J, K * R * R));
+  for (int64_t i = 0; i < K * R * J; ++i) f[i] = (float)Y[i];
+  HIP_OR_FAIL(c, hipMemcpy(c->Y, f.data(), sizeof(float) * K * R * J, hipMemcpyHostToDevice));
+  for (int64_t i = 0; i < K * R * R; ++i) f[i] = (float)D[i];
+  HIP_OR_FAIL(c, hipMemcpy(c->D, f.data(), sizeof(float) * K * R * R, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->n, n, sizeof(double) * K, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->W, W, sizeof(double) * K * R, hipMemcpyHostToDevice));
+  const VBundleView v = vb_view(c->vb, c->J, c->R);
+  HIP_OR_FAIL(c, hipMemcpy(v.V64, V, sizeof(double) * J * R, hipMemcpyHostToDevice));
+  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, 0, c->vb, c->vb_stride, c->ctl, 1, c->stream));
+  if (dash_status s = enqueue_eval(c, K)) return s;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->initialized = true;
+  c->K = c->K_enq = c->K_pending = K;
+  c->step_enq = c->step;
+  c->m_last = 0;
+  c->pending.clear();
+  c->rows_pending = 0;
+  return DASH_OK;
+}
+
+namespace {
+// Checkpoint file: header, then the raw committed state exactly as the device
+// holds it (float32 Y_k and D_k without the pending lambda^dt, float64 n_k,
+// W and V, int32 t_k), so that a restored context continues bit for bit.
+struct CkptHeader {
+  char magic[8];
+  int32_t J, R, K, pad;
+  int64_t step;
+  double lambda;
+};
+}  // namespace
+
+dash_status dash_save(dash_ctx *c, const char *path) {
+  if (!c || !path) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  Ctl ctl;
+  if (dash_status s = read_ctl(c, &ctl)) return s;
+  const int64_t K = c->K, J = c->J, R = c->R;
+  std::vector<float> Y(K * R * J), D(K * R * R);
+  std::vector<double> n(K), W(K * R), V(J * R);
+  std::vector<int32_t> tl(K);
+  float *dY = nullptr, *dD = nullptr;
+  double *dn = nullptr;
+  if (dalloc(&dY, sizeof(float) * K * R * J) != hipSuccess || dalloc(&dD, sizeof(float) * K * R * R) != hipSuccess ||
+      dalloc(&dn, sizeof(double) * K) != hipSuccess) {
+    (void)hipFree(dY);
+    (void)hipFree(dD);
+    (void)hipFree(dn);
+    return fail(c, DASH_E_OUT_OF_MEMORY, "checkpoint buffers");
+  }
+  hipError_t he = (hipError_t)launch_gather_state(c->J, c->R, c->K, c->Y, c->D, c->n, c->cur, c->K_cap, dY, dD, dn,
+                                                  c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (he == hipSuccess) he = hipMemcpy(Y.data(), dY, sizeof(float) * Y.size(), hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(D.data(), dD, sizeof(float) * D.size(), hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(n.data(), dn, sizeof(double) * n.size(), hipMemcpyDeviceToHost);
+  (void)hipFree(dY);
+  (void)hipFree(dD);
+  (void)hipFree(dn);
+  const VBundleView v = vb_view(c->vb + (int64_t)ctl.gcur * c->vb_stride, c->J, c->R);
+  if (he == hipSuccess) he = hipMemcpy(V.data(), v.V64, sizeof(double) * V.size(), hipMemcpyDeviceToHost);
+  if (he == hipSuccess)
+    he = hipMemcpy(W.data(), c->W + (int64_t)ctl.gcur * c->K_cap * R, sizeof(double) * W.size(), hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(tl.data(), c->tlast, sizeof(int32_t) * K, hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return fail(c, DASH_E_DEVICE, "checkpoint read-back: %s", hipGetErrorString(he));
+  FILE *fp = std::fopen(path, "wb");
+  if (!fp) return fail(c, DASH_E_IO, "cannot open %s", path);
+  CkptHeader h{};
+  std::memcpy(h.magic, "DASHCKP2", 8);
+  h.J = c->J;
+  h.R = c->R;
+  h.K = c->K;
+  h.step = c->step;
+  h.lambda = c->cfg.lambda;
+  bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(Y.data(), 4, Y.size(), fp) == Y.size() &&
+            std::fwrite(D.data(), 4, D.size(), fp) == D.size() && std::fwrite(n.data(), 8, n.size(), fp) == n.size() &&
+            std::fwrite(W.data(), 8, W.size(), fp) == W.size() && std::fwrite(V.data(), 8, V.size(), fp) == V.size() &&
+            std::fwrite(tl.data(), 4, tl.size(), fp) == tl.size();
+  ok = (std::fclose(fp) == 0) && ok;
+  return ok ? DASH_OK : fail(c, DASH_E_IO, "short write to %s", path);
+}
+
+dash_status dash_load(dash_ctx *c, const char *path) {
+  if (!c || !path) return DASH_E_INVALID_ARG;
+  FILE *fp = std::fopen(path, "rb");
+  if (!fp) return fail(c, DASH_E_IO, "cannot open %s", path);
+  CkptHeader h{};
+  if (std::fread(&h, sizeof h, 1, fp) != 1 || std::memcmp(h.magic, "DASHCKP2", 8) != 0) {
+    std::fclose(fp);
+    return fail(c, DASH_E_IO, "%s is not a checkpoint", path);
+  }
+  if (h.J != c->J || h.R != c->R || h.K < 1 || h.K > c->K_cap || h.lambda != c->cfg.lambda) {
+    std::fclose(fp);
+    return fail(c, DASH_E_INVALID_ARG, "checkpoint (J=%d R=%d K=%d lambda=%g) does not fit the context", h.J, h.R,
+                h.K, h.lambda);
+  }
+  const int64_t K = h.K, J = h.J, R = h.R;
+  std::vector<float> Y(K * R * J), D(K * R * R);
+  std::vector<double> n(K), W(K * R), V(J * R);
+  std::vector<int32_t> tl(K);
+  bool ok = std::fread(Y.data(), 4, Y.size(), fp) == Y.size() && std::fread(D.data(), 4, D.size(), fp) == D.size() &&
+            std::fread(n.data(), 8, n.size(), fp) == n.size() && std::fread(W.data(), 8, W.size(), fp) == W.size() &&
+            std::fread(V.data(), 8, V.size(), fp) == V.size() && std::fread(tl.data(), 4, tl.size(), fp) == tl.size();
+  std::fclose(fp);
+  if (!ok) return fail(c, DASH_E_IO, "short read from %s", path);
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  if (dash_status s = reset_device_state(c, (int32_t)K, 0)) return s;
+  HIP_OR_FAIL(c, hipMemcpy(c->Y, Y.data(), sizeof(float) * Y.size(), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->D, D.data(), sizeof(float) * D.size(), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->n, n.data(), sizeof(double) * n.size(), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->W, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->tlast, tl.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+  const VBundleView v = vb_view(c->vb, c->J, c->R);
+  HIP_OR_FAIL(c, hipMemcpy(v.V64, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice));
+  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, 0, c->vb, c->vb_stride, c->ctl, 1, c->stream));
+  c->step = h.step;
+  if (dash_status s = enqueue_eval(c, (int32_t)K)) return s;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->initialized = true;
+  c->K = c->K_enq = c->K_pending = (int32_t)K;
+  c->step_enq = c->step;
+  c->m_last = 0;
+  c->pending.clear();
+  c->rows_pending = 0;
+  return DASH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libdash (include/dash.h).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  PyTorch supplies device memory (input rows, output buffers) and the
+stream; host metadata (row pointers, slice ids) is passed as numpy arrays.
+The binding refuses to run without the built library -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdash.so")
+
+OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_BAD_STATE, E_CAPACITY, E_NUMERIC, E_DEVICE, E_IO = range(8)
+PREC_FP32, PREC_MIXED = 0, 1
+STATS_EXACT, STATS_LAGGED = 0, 1
+
+
+class DashConfig(C.Structure):
+    _fields_ = [
+        ("J", C.c_int32), ("R", C.c_int32), ("lam", C.c_double), ("n_iter", C.c_int32),
+        ("init_max_iter", C.c_int32), ("init_tol", C.c_double), ("precision", C.c_int32),
+        ("stats_mode", C.c_int32), ("max_slices", C.c_int64), ("max_rows_per_update", C.c_int64),
+        ("max_groups_per_update", C.c_int64), ("max_init_rows", C.c_int64), ("device", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class UpdateReport(C.Structure):
+    _fields_ = [("step", C.c_int64), ("rows", C.c_int64), ("K", C.c_int32), ("committed", C.c_int32),
+                ("fit", C.c_double), ("loss", C.c_double), ("sum_n", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class InitReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("loss", C.c_double), ("fit", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ProfileStats(C.Structure):
+    _fields_ = [("updates", C.c_int64), ("pass_launches", C.c_int64), ("reduce_launches", C.c_int64),
+                ("solve_launches", C.c_int64), ("commit_launches", C.c_int64), ("upload_launches", C.c_int64),
+                ("pass_ms", C.c_double), ("reduce_ms", C.c_double), ("solve_ms", C.c_double),
+                ("commit_ms", C.c_double), ("upload_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Dims(C.Structure):
+    _fields_ = [("J", C.c_int32), ("R", C.c_int32), ("K", C.c_int32), ("K_pending", C.c_int32),
+                ("step", C.c_int64), ("m_last", C.c_int64), ("rows_pending", C.c_int64),
+                ("initialized", C.c_int32)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "dash_config_default": (None, [C.POINTER(DashConfig), C.c_int32, C.c_int32]),
+    "dash_create": (C.c_int, [C.POINTER(DashConfig), C.POINTER(_P)]),
+    "dash_destroy": (C.c_int, [_P]),
+    "dash_init": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.POINTER(InitReport)]),
+    "dash_init_from_factors": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P]),
+    "dash_ingest_rows": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+    "dash_ingest_slices": (C.c_int, [_P, C.c_int32, _P, _P, C.POINTER(C.c_int32)]),
+    "dash_update": (C.c_int, [_P, C.POINTER(UpdateReport)]),
+    "dash_update_async": (C.c_int, [_P]),
+    "dash_wait": (C.c_int, [_P, C.POINTER(UpdateReport)]),
+    "dash_get_factors": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_int64)]),
+    "dash_get_dims": (C.c_int, [_P, C.POINTER(Dims)]),
+    "dash_get_state": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "dash_set_state": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P]),
+    "dash_save": (C.c_int, [_P, C.c_char_p]),
+    "dash_load": (C.c_int, [_P, C.c_char_p]),
+    "dash_profile": (C.c_int, [_P, C.c_int32]),
+    "dash_profile_read": (C.c_int, [_P, C.POINTER(ProfileStats)]),
+    "dash_status_string": (C.c_char_p, [C.c_int]),
+    "dash_last_error": (C.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdash.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2305_18376_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DashError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} [{lib().dash_status_string(status).decode()}]")
+        self.status = status
+
+
+def _ptr(t) -> int:
+    """Device pointer of a contiguous CUDA(HIP) tensor, or host pointer of a numpy array."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.flags["C_CONTIGUOUS"]
+        return t.ctypes.data
+    assert t.is_contiguous() and t.is_cuda, "expected a contiguous device tensor"
+    return t.data_ptr()
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class Dash:
+    """One streaming decomposition (one C context)."""
+
+    def __init__(self, J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20,
+                 max_groups=65536, max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10,
+                 device=0, stream=None):
+        import torch
+        L = lib()
+        cfg = DashConfig()
+        L.dash_config_default(C.byref(cfg), J, R)
+        cfg.lam = lam
+        cfg.n_iter = n_iter
+        cfg.max_slices = max_slices
+        cfg.max_rows_per_update = max_rows
+        cfg.max_groups_per_update = max_groups
+        cfg.max_init_rows = max_init_rows
+        cfg.init_max_iter = init_max_iter
+        cfg.init_tol = init_tol
+        cfg.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        cfg.stream = stream
+        h = _P()
+        st = L.dash_create(C.byref(cfg), C.byref(h))
+        if st != OK:
+            raise DashError(st, "dash_create failed")
+        self._h = h
+        self.J, self.R = J, R
+        self.device = device
+        self._borrowed = []
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, st, what):
+        if st != OK:
+            msg = lib().dash_last_error(self._h)
+            raise DashError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dash_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dims(self):
+        d = Dims()
+        self._check(lib().dash_get_dims(self._h, C.byref(d)), "dash_get_dims")
+        return d
+
+    # ---------------------------------------------------------------- init
+    def init_from_factors(self, row_ptr, X, U, W, V):
+        rp = _host(row_ptr, np.int64)
+        K = rp.shape[0] - 1
+        self._check(lib().dash_init_from_factors(self._h, K, _ptr(rp), _ptr(X), _ptr(U), _ptr(W), _ptr(V)),
+                    "dash_init_from_factors")
+
+    def init(self, row_ptr, X, V0=None):
+        rp = _host(row_ptr, np.int64)
+        rep = InitReport()
+        self._check(lib().dash_init(self._h, rp.shape[0] - 1, _ptr(rp), _ptr(X), _ptr(V0), C.byref(rep)),
+                    "dash_init")
+        return rep.as_dict()
+
+    # -------------------------------------------------------------- ingest
+    def ingest_rows(self, slice_id, row_ptr, rows):
+        sid = _host(slice_id, np.int32)
+        rp = _host(row_ptr, np.int64)
+        self._check(lib().dash_ingest_rows(self._h, sid.shape[0], _ptr(sid), _ptr(rp), _ptr(rows)),
+                    "dash_ingest_rows")
+        self._borrowed.append(rows)
+
+    def ingest_slices(self, row_ptr, rows):
+        rp = _host(row_ptr, np.int64)
+        first = C.c_int32()
+        self._check(lib().dash_ingest_slices(self._h, rp.shape[0] - 1, _ptr(rp), _ptr(rows), C.byref(first)),
+                    "dash_ingest_slices")
+        self._borrowed.append(rows)
+        return first.value
+
+    def update(self):
+        rep = UpdateReport()
+        st = lib().dash_update(self._h, C.byref(rep))
+        self._borrowed = []
+        self._check(st, "dash_update")
+        return rep.as_dict()
+
+    def update_async(self):
+        self._check(lib().dash_update_async(self._h), "dash_update_async")
+
+    def wait(self):
+        rep = UpdateReport()
+        st = lib().dash_wait(self._h, C.byref(rep))
+        self._borrowed = []
+        self._check(st, "dash_wait")
+        return rep.as_dict()
+
+    # ------------------------------------------------------------- outputs
+    def get_factors(self):
+        import torch
+        d = self.dims()
+        dev = torch.device("cuda", self.device)
+        V = torch.empty((self.J, self.R), dtype=torch.float32, device=dev)
+        W = torch.empty((max(d.K, 1), self.R), dtype=torch.float32, device=dev)
+        U = torch.empty((max(d.m_last, 1), self.R), dtype=torch.float32, device=dev)
+        m = C.c_int64()
+        self._check(lib().dash_get_factors(self._h, _ptr(V), _ptr(W), _ptr(U), C.byref(m)), "dash_get_factors")
+        return V, W[: d.K], U[: m.value]
+
+    def get_state(self):
+        d = self.dims()
+        K, J, R = d.K, self.J, self.R
+        V = np.empty((J, R))
+        W = np.empty((K, R))
+        Y = np.empty((K, R, J))
+        D = np.empty((K, R, R))
+        n = np.empty((K,))
+        self._check(lib().dash_get_state(self._h, _ptr(V), _ptr(W), _ptr(Y), _ptr(D), _ptr(n)), "dash_get_state")
+        return dict(V=V, W=W, Y=Y, D=D, n=n)
+
+    def set_state(self, V, W, Y, D, n):
+        V, W, Y, D, n = (_host(a, np.float64) for a in (V, W, Y, D, n))
+        K = W.shape[0]
+        assert Y.shape == (K, self.R, self.J) and D.shape == (K, self.R, self.R) and n.shape == (K,)
+        self._check(lib().dash_set_state(self._h, K, _ptr(V), _ptr(W), _ptr(Y), _ptr(D), _ptr(n)), "dash_set_state")
+
+    def profile(self, enable=True):
+        self._check(lib().dash_profile(self._h, 1 if enable else 0), "dash_profile")
+
+    def profile_read(self):
+        st = ProfileStats()
+        self._check(lib().dash_profile_read(self._h, C.byref(st)), "dash_profile_read")
+        return st.as_dict()
+
+    def save(self, path):
+        self._check(lib().dash_save(self._h, str(path).encode()), "dash_save")
+
+    def load(self, path):
+        self._check(lib().dash_load(self._h, str(path).encode()), "dash_load")

@@ -1,0 +1,70 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad configurations before touching a device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2305_18376_amd import dash as D
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dash.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dash_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_problem_calls():
+    names = declared_functions()
+    for call in ("dash_init", "dash_ingest_rows", "dash_ingest_slices", "dash_update", "dash_get_factors"):
+        assert call in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(D.LIB_PATH):
+        pytest.fail("libdash.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", D.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (dash_[a-z_]+)\b", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = D.lib()
+    for n in declared_functions():
+        assert getattr(L, n) is not None
+
+
+def test_config_defaults_and_status_strings():
+    L = D.lib()
+    cfg = D.DashConfig()
+    L.dash_config_default(C.byref(cfg), 88, 10)
+    assert (cfg.J, cfg.R, cfg.n_iter, cfg.init_max_iter) == (88, 10, 1, 10)
+    assert cfg.lam == pytest.approx(0.7)
+    for s in range(8):
+        assert L.dash_status_string(s)
+    assert b"unknown" in L.dash_status_string(99)
+
+
+@pytest.mark.parametrize("field,value", [("J", 0), ("J", 257), ("R", 0), ("R", 33), ("lam", 0.0),
+                                         ("lam", 1.5), ("n_iter", 0), ("max_slices", 0),
+                                         ("max_rows_per_update", 0), ("precision", 7), ("stats_mode", 9)])
+def test_create_rejects_bad_config_without_a_device(field, value):
+    L = D.lib()
+    cfg = D.DashConfig()
+    L.dash_config_default(C.byref(cfg), 16, 4)
+    setattr(cfg, field, value)
+    h = C.c_void_p()
+    assert L.dash_create(C.byref(cfg), C.byref(h)) == D.E_INVALID_ARG
+    assert not h.value
+
+
+def test_null_arguments():
+    L = D.lib()
+    assert L.dash_create(None, None) == D.E_INVALID_ARG
+    assert L.dash_destroy(None) == D.OK
+    assert L.dash_update(None, None) == D.E_INVALID_ARG
+    assert L.dash_get_dims(None, None) == D.E_INVALID_ARG
+    assert L.dash_last_error(None) == b""
