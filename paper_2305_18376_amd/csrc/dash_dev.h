@@ -15,31 +15,33 @@ constexpr double kPivotRel = 1e-12;   // Cholesky pivot threshold relative to ma
 constexpr double kEigCutoff = 1e-12;  // pseudo-inverse / inverse-sqrt eigenvalue cutoff
 constexpr double kWCutoff = 1e-12;    // 1/w := 0 below this fraction of max|w|
 constexpr int kReportRing = 64;       // pinned report slots (updates in flight)
+constexpr int kMaxChunks = 4096;      // bound on sweep chunks (partials memory)
+constexpr int kChunksPerRGroup = 16;  // first-level reduction fan-in
 
 // Per-update descriptor block, written by the host into pinned memory and
-// copied to the device once per update (one hipMemcpyAsync).
+// copied to the device once per update (one hipMemcpyAsync):
+//   StepHeader | int32 chunk_gptr[n_chunks+1] | Group groups[n_groups]
+// Groups are sorted by slice (ingest order within a slice); chunk c covers
+// slices [c*chunk, (c+1)*chunk) and its groups start at chunk_gptr[c].
 struct StepHeader {
   int32_t K;          // slices after the update
   int32_t K_prev;     // slices before it (ids >= K_prev are new)
-  int32_t n_touched;  // slices that received rows
-  int32_t n_groups;   // row groups (ingest calls x groups), sorted by slice
-  int32_t n_chunks;   // slice chunks of the sweep
+  int32_t n_groups;   // row groups, sorted by slice
+  int32_t n_chunks;   // slice chunks of the sweep (one workgroup each)
   int32_t chunk;      // slices per chunk
   int32_t n_rgroups;  // first-level reduction groups of chunk partials
   int32_t chunks_per_rgroup;
-  int64_t step;       // 1-based index of this update
+  int32_t pad;
+  int64_t step;       // 1-based index of this update (the committed index for evaluations)
   int64_t M;          // rows in the update
   void *report;       // device-visible pointer to this update's pinned report slot
-};
-
-struct Touched {      // one slice that received rows; its groups are [g_begin, g_end)
-  int32_t slice, g_begin, g_end, pad;
 };
 
 struct Group {        // contiguous rows of one slice, in the caller's buffer
   const float *src;   // nrows x J, row-major
   int64_t out_row;    // first row of U_new (ingest order)
-  int32_t nrows, pad;
+  int32_t nrows;
+  int32_t slice;
 };
 
 // Device-resident control block.
@@ -85,46 +87,55 @@ __host__ __device__ inline VBundleView vb_view(char *base, int J, int R) {
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Floats per slice of the Y state: R*J rounded up to whole wave64 rows (the
+// padding stays zero), so wave-wide loads and stores need no bounds checks.
+__host__ __device__ inline int y_stride(int J, int R) { return (R * J + 63) / 64 * 64; }
+
 // Size of one sweep partial: F^T (R*J), G (R*R), sum n.
 __host__ __device__ inline int partial_len(int J, int R) { return R * J + R * R + 1; }
 
-// Arguments of the fused pass kernel (by value).
+// Arguments of the pass kernels (by value).
 struct PassArgs {
   int J, R;
-  double lambda;
+  int ys;              // floats per slice of Y (y_stride)
+  double lambda, log2_lambda;
   int pass;            // 0-based ALS pass within the update
-  int write_u;         // write U_new rows (last pass)
-  int mode;            // 0: update pass, 1: evaluate F/G with current W (no solve, no writes)
+  int last_pass;       // this pass writes U_new and commits
+  int mode;            // 0: update pass, 1: evaluate the committed state (fit only)
   int64_t K_cap;
   const StepHeader *hdr;
-  const int32_t *chunk_tptr;   // [n_chunks+1] first touched entry per chunk
-  const Touched *touched;
+  const int32_t *chunk_gptr;   // [n_chunks+1]
   const Group *groups;
-  float *Y;            // [2][K_cap][R][J]
+  float *Y;            // [2][K_cap][ys]: R x J row-major, zero padded
   float *D;            // [2][K_cap][R][R]
   double *n;           // [2][K_cap]
-  uint8_t *cur;        // [K_cap] committed buffer of Y/D/n per slice
-  int32_t *tlast;      // [K_cap] step of the last commit of the slice
+  uint8_t *cur;        // [2][K_cap] buffer of Y/D/n holding each slice (by gcur)
+  int32_t *tlast;      // [2][K_cap] update index of the slice's last fold (by gcur)
   double *W;           // [2][K_cap][R]
   char *vb;            // 2 V bundles
   int64_t vb_stride;
   Ctl *ctl;
   float *U_out;        // [M_cap][R]
   double *partials;    // [n_chunks][partial_len]
+  double *gpart;       // [n_rgroups][partial_len]
+  int32_t *counters;   // [n_rgroups_cap + 1] arrival tickets, zero between launches
 };
 
+// Kernel variants of the sweep.
+enum { kPassWave = 0, kPassBlock = 1 };
+
 // Launchers (dash_kernels.hip).
-int launch_pass(const PassArgs &a, int n_chunks, hipStream_t s);
-int launch_reduce(const double *partials, double *gpart, const StepHeader *hdr, int plen,
-                  int n_chunks, int n_rgroups, int chunks_per_rgroup, hipStream_t s);
-// mode 0: reduce + V = F G^{-1} + prep of next bundle + fit; mode 1: prep bundle from V64 of
-// the committed bundle (init/set_state); mode 2: fit only (F, G from partials, V committed).
-int launch_solve(int J, int R, const double *gpart, int n_rgroups, char *vb, int64_t vb_stride,
-                 Ctl *ctl, int mode, hipStream_t s);
-int launch_commit(const StepHeader *hdr, const Touched *touched, uint8_t *cur, int32_t *tlast,
-                  Ctl *ctl, int n_touched, hipStream_t s);
+// Choose the sweep variant for (J, R); returns kPassWave or kPassBlock.
+int pass_variant(int J, int R);
+// Slices per workgroup for a variant and slice count.
+int pass_chunk(int variant, int K);
+int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s);
+// Final phase of a pass (one workgroup): mode 0 after an update sweep (Lemma 3,
+// next-pass operands, commit on the last pass), 1 builds the committed V bundle
+// from its V64, 2 evaluates the fit after an evaluation sweep.
+int launch_finish(const PassArgs &a, int mode, hipStream_t s);
 int launch_accum_given_u(int J, int R, int K, const int64_t *row_ptr_dev, const float *X,
-                         const float *U, float *Y, float *D, double *n, hipStream_t s);
+                         const float *U, float *Y, float *D, double *n, hipStream_t s);  // Y stride y_stride
 int launch_v_from_f32(int J, int R, const float *V, char *vb_committed, hipStream_t s);
 int launch_w_from_f32(int R, int K, const float *W, double *Wc, hipStream_t s);
 int launch_export_state(int J, int R, int K, int64_t step, double lambda, const float *Y,

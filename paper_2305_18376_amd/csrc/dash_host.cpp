@@ -27,8 +27,6 @@ using namespace dash;
 namespace {
 
 constexpr int kStages = 4;             // pinned descriptor blocks in rotation
-constexpr int kMaxChunks = 4096;       // bound on sweep chunks (partials memory)
-constexpr int kChunksPerRGroup = 16;   // first-level reduction fan-in
 
 struct PendingGroup {
   int32_t slice;
@@ -53,7 +51,6 @@ struct dash_ctx {
   bool own_stream = false;
   std::string err;
   int64_t K_cap = 0, M_cap = 0, G_cap = 0, N_init_cap = 0;
-  int64_t touched_cap = 0;
   // device state
   float *Y = nullptr;
   float *D = nullptr;
@@ -67,9 +64,11 @@ struct dash_ctx {
   float *U_out = nullptr;
   double *partials = nullptr;
   double *gpart = nullptr;
+  int32_t *counters = nullptr;
   int64_t *d_rowptr = nullptr;
   char *dstep = nullptr;
-  size_t off_tptr = 0, off_touched = 0, off_groups = 0, step_bytes = 0;
+  size_t off_gptr = 0, off_groups = 0, step_bytes = 0;
+  int variant = kPassWave;
   // pinned
   char *hstage[kStages] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t stage_ev[kStages] = {nullptr, nullptr, nullptr, nullptr};
@@ -133,12 +132,12 @@ hipError_t dalloc(T **p, size_t bytes) {
 }
 
 int choose_chunk(const dash_ctx *c, int K) {
-  if (c->chunk_override > 0) return c->chunk_override;
-  // ~2 workgroups per CU of 256 CUs, never more than kMaxChunks chunks
-  int ch = (K + 511) / 512;
-  if (ch < 1) ch = 1;
-  while ((K + ch - 1) / ch > kMaxChunks) ++ch;
-  return ch;
+  if (c->chunk_override > 0) {
+    int ch = c->chunk_override;
+    while ((K + ch - 1) / ch > kMaxChunks) ++ch;
+    return ch;
+  }
+  return pass_chunk(c->variant, K);
 }
 
 StepHeader *stage_header(char *blk) { return (StepHeader *)blk; }
@@ -195,47 +194,16 @@ hipError_t take_stage(dash_ctx *c, int *idx) {
   return hipSuccess;
 }
 
-// Fill the chunk table of a sweep over K slices with no touched slice.
-void fill_empty_tables(dash_ctx *c, char *blk, int n_chunks) {
-  int32_t *tptr = (int32_t *)(blk + c->off_tptr);
-  for (int i = 0; i <= n_chunks; ++i) tptr[i] = 0;
-}
-
-// Enqueue an evaluation sweep (F, G from the committed W) + fit.
-dash_status enqueue_eval(dash_ctx *c, int K) {
-  int s;
-  HIP_OR_FAIL(c, take_stage(c, &s));
-  char *blk = c->hstage[s];
-  StepHeader *h = stage_header(blk);
-  const int ch = choose_chunk(c, K);
-  const int nch = (K + ch - 1) / ch;
-  h->K = K;
-  h->K_prev = K;
-  h->n_touched = 0;
-  h->n_groups = 0;
-  h->n_chunks = nch;
-  h->chunk = ch;
-  h->chunks_per_rgroup = kChunksPerRGroup;
-  h->n_rgroups = (nch + kChunksPerRGroup - 1) / kChunksPerRGroup;
-  h->step = c->step;
-  h->M = 0;
-  h->report = nullptr;
-  fill_empty_tables(c, blk, nch);
-  const size_t bytes = c->off_tptr + sizeof(int32_t) * (nch + 1);
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->dstep, blk, bytes, hipMemcpyHostToDevice, c->stream));
-  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
-  c->stage_used[s] = true;
+PassArgs base_args(const dash_ctx *c) {
   PassArgs a{};
   a.J = c->J;
   a.R = c->R;
+  a.ys = y_stride(c->J, c->R);
   a.lambda = c->cfg.lambda;
-  a.pass = 0;
-  a.write_u = 0;
-  a.mode = 1;
+  a.log2_lambda = std::log2(c->cfg.lambda);
   a.K_cap = c->K_cap;
   a.hdr = (const StepHeader *)c->dstep;
-  a.chunk_tptr = (const int32_t *)(c->dstep + c->off_tptr);
-  a.touched = (const Touched *)(c->dstep + c->off_touched);
+  a.chunk_gptr = (const int32_t *)(c->dstep + c->off_gptr);
   a.groups = (const Group *)(c->dstep + c->off_groups);
   a.Y = c->Y;
   a.D = c->D;
@@ -248,23 +216,61 @@ dash_status enqueue_eval(dash_ctx *c, int K) {
   a.ctl = c->ctl;
   a.U_out = c->U_out;
   a.partials = c->partials;
-  const int plen = partial_len(c->J, c->R);
-  LAUNCH_OR_FAIL(c, launch_pass(a, nch, c->stream));
-  LAUNCH_OR_FAIL(c, launch_reduce(c->partials, c->gpart, a.hdr, plen, nch, h->n_rgroups,
-                                  kChunksPerRGroup, c->stream));
-  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, h->n_rgroups, c->vb, c->vb_stride, c->ctl,
-                                 2, c->stream));
+  a.gpart = c->gpart;
+  a.counters = c->counters;
+  return a;
+}
+
+// Enqueue an evaluation sweep of the committed state (F, G with the committed
+// W) and its fit, over K slices.
+dash_status enqueue_eval(dash_ctx *c, int K) {
+  int s;
+  HIP_OR_FAIL(c, take_stage(c, &s));
+  char *blk = c->hstage[s];
+  StepHeader *h = stage_header(blk);
+  const int ch = choose_chunk(c, K);
+  const int nch = (K + ch - 1) / ch;
+  std::memset(h, 0, sizeof *h);
+  h->K = K;
+  h->K_prev = K;
+  h->n_groups = 0;
+  h->n_chunks = nch;
+  h->chunk = ch;
+  h->chunks_per_rgroup = kChunksPerRGroup;
+  h->n_rgroups = (nch + kChunksPerRGroup - 1) / kChunksPerRGroup;
+  h->step = c->step;
+  h->M = 0;
+  h->report = nullptr;
+  int32_t *gptr = (int32_t *)(blk + c->off_gptr);
+  for (int i = 0; i <= nch; ++i) gptr[i] = 0;
+  const size_t bytes = c->off_gptr + sizeof(int32_t) * (nch + 1);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dstep, blk, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
+  c->stage_used[s] = true;
+  PassArgs a = base_args(c);
+  a.pass = 0;
+  a.last_pass = 0;
+  a.mode = 1;
+  LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
+  LAUNCH_OR_FAIL(c, launch_finish(a, 2, c->stream));
   return DASH_OK;
 }
 
+dash_status enqueue_prep(dash_ctx *c) {
+  PassArgs a = base_args(c);
+  LAUNCH_OR_FAIL(c, launch_finish(a, 1, c->stream));
+  return DASH_OK;
+}
+
+// Committed-buffer index 0 for everything; slices [0, K) last folded at update tl.
 dash_status reset_device_state(dash_ctx *c, int32_t K, int32_t tl) {
-  HIP_OR_FAIL(c, hipMemsetAsync(c->cur, 0, (size_t)c->K_cap, c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->cur, 0, (size_t)(2 * c->K_cap), c->stream));
   std::vector<int32_t> t(std::max<int32_t>(K, 1), tl);
   if (K > 0)
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->tlast, t.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice,
-                                  c->stream));
+    HIP_OR_FAIL(c, hipMemcpy(c->tlast, t.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
   Ctl ctl{};
   ctl.gcur = 0;
+  ctl.ok = 1;
   HIP_OR_FAIL(c, hipMemcpyAsync(c->ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   return DASH_OK;
@@ -369,7 +375,7 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->M_cap = cfg->max_rows_per_update;
   c->G_cap = cfg->max_groups_per_update + c->K_cap;  // new slices are groups too
   c->N_init_cap = cfg->max_init_rows;
-  c->touched_cap = std::min<int64_t>(c->K_cap, c->G_cap);
+  c->variant = pass_variant(cfg->J, cfg->R);
   if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
   auto bail = [&](dash_status s) {
     dash_destroy(c);
@@ -386,22 +392,23 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   const int64_t n_chunks_cap = std::min<int64_t>(Kc, kMaxChunks);
   const int64_t plen = partial_len(c->J, c->R);
   c->vb_stride = vb_bytes(c->J, c->R);
-  bool ok = dalloc(&c->Y, sizeof(float) * 2 * Kc * R * J) == hipSuccess &&
+  const int64_t YS = y_stride(c->J, c->R);
+  bool ok = dalloc(&c->Y, sizeof(float) * 2 * Kc * YS) == hipSuccess &&
             dalloc(&c->D, sizeof(float) * 2 * Kc * R * R) == hipSuccess &&
             dalloc(&c->n, sizeof(double) * 2 * Kc) == hipSuccess &&
-            dalloc(&c->cur, (size_t)Kc) == hipSuccess &&
-            dalloc(&c->tlast, sizeof(int32_t) * Kc) == hipSuccess &&
+            dalloc(&c->cur, (size_t)(2 * Kc)) == hipSuccess &&
+            dalloc(&c->tlast, sizeof(int32_t) * 2 * Kc) == hipSuccess &&
             dalloc(&c->W, sizeof(double) * 2 * Kc * R) == hipSuccess &&
             dalloc(&c->vb, (size_t)(2 * c->vb_stride)) == hipSuccess &&
             dalloc(&c->ctl, sizeof(Ctl)) == hipSuccess &&
             dalloc(&c->U_out, sizeof(float) * c->M_cap * R) == hipSuccess &&
             dalloc(&c->partials, sizeof(double) * n_chunks_cap * plen) == hipSuccess &&
             dalloc(&c->gpart, sizeof(double) * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) == hipSuccess &&
+            dalloc(&c->counters, sizeof(int32_t) * (kMaxChunks + 1)) == hipSuccess &&
             dalloc(&c->d_rowptr, sizeof(int64_t) * (Kc + 1)) == hipSuccess;
   if (!ok) return bail(DASH_E_OUT_OF_MEMORY);
-  c->off_tptr = align_up(sizeof(StepHeader), 64);
-  c->off_touched = align_up(c->off_tptr + sizeof(int32_t) * (n_chunks_cap + 1), 64);
-  c->off_groups = align_up(c->off_touched + sizeof(Touched) * c->touched_cap, 64);
+  c->off_gptr = align_up(sizeof(StepHeader), 64);
+  c->off_groups = align_up(c->off_gptr + sizeof(int32_t) * (n_chunks_cap + 1), 64);
   c->step_bytes = align_up(c->off_groups + sizeof(Group) * c->G_cap, 256);
   if (dalloc(&c->dstep, c->step_bytes) != hipSuccess) return bail(DASH_E_OUT_OF_MEMORY);
   for (int s = 0; s < kStages; ++s) {
@@ -414,11 +421,17 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
     return bail(DASH_E_OUT_OF_MEMORY);
   std::memset(c->hreport, 0, sizeof(Report) * kReportRing);
   if (hipHostGetDevicePointer((void **)&c->dreport, c->hreport, 0) != hipSuccess) return bail(DASH_E_DEVICE);
-  if (hipMemsetAsync(c->cur, 0, (size_t)Kc, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * Kc, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->stream) != hipSuccess ||
+  if (hipMemsetAsync(c->Y, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->cur, 0, (size_t)(2 * Kc), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * 2 * Kc, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->counters, 0, sizeof(int32_t) * (kMaxChunks + 1), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(DASH_E_DEVICE);
+  {
+    Ctl ctl{};
+    ctl.ok = 1;
+    if (hipMemcpy(c->ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice) != hipSuccess) return bail(DASH_E_DEVICE);
+  }
   c->pending.reserve(1024);
   *out = c;
   return DASH_OK;
@@ -438,6 +451,7 @@ dash_status dash_destroy(dash_ctx *c) {
   (void)hipFree(c->U_out);
   (void)hipFree(c->partials);
   (void)hipFree(c->gpart);
+  (void)hipFree(c->counters);
   (void)hipFree(c->d_rowptr);
   (void)hipFree(c->dstep);
   for (int s = 0; s < kStages; ++s) {
@@ -480,7 +494,7 @@ dash_status dash_init_from_factors(dash_ctx *c, int32_t K, const int64_t *row_pt
   LAUNCH_OR_FAIL(c, launch_accum_given_u(c->J, c->R, K, c->d_rowptr, X, U, c->Y, c->D, c->n, c->stream));
   LAUNCH_OR_FAIL(c, launch_w_from_f32(c->R, K, W, c->W, c->stream));
   LAUNCH_OR_FAIL(c, launch_v_from_f32(c->J, c->R, V, c->vb, c->stream));
-  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, 0, c->vb, c->vb_stride, c->ctl, 1, c->stream));
+  if (dash_status s = enqueue_prep(c)) return s;
   c->step = 0;
   if (dash_status s = enqueue_eval(c, K)) return s;
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
@@ -572,45 +586,39 @@ dash_status dash_update_async(dash_ctx *c) {
   HIP_OR_FAIL(c, take_stage(c, &s));
   char *blk = c->hstage[s];
   StepHeader *h = stage_header(blk);
-  int32_t *tptr = (int32_t *)(blk + c->off_tptr);
-  Touched *tch = (Touched *)(blk + c->off_touched);
+  int32_t *gptr = (int32_t *)(blk + c->off_gptr);
   Group *grp = (Group *)(blk + c->off_groups);
   // groups sorted by slice, ingest order kept within a slice
   const int ng = (int)c->pending.size();
   bool sorted = true;
   for (int g = 1; g < ng; ++g)
-    if (c->pending[g].slice < c->pending[g - 1].slice) { sorted = false; break; }
+    if (c->pending[g].slice < c->pending[g - 1].slice) {
+      sorted = false;
+      break;
+    }
   c->order.resize(ng);
   for (int g = 0; g < ng; ++g) c->order[g] = g;
   if (!sorted)
     std::stable_sort(c->order.begin(), c->order.end(),
-                     [&](int a, int b) { return c->pending[a].slice < c->pending[b].slice; });
-  int nt = 0;
+                     [&](int x, int y) { return c->pending[x].slice < c->pending[y].slice; });
   for (int i = 0; i < ng; ++i) {
     const PendingGroup &pg = c->pending[c->order[i]];
     grp[i].src = pg.src;
     grp[i].out_row = pg.out_row;
     grp[i].nrows = (int32_t)pg.nrows;
-    grp[i].pad = 0;
-    if (nt == 0 || tch[nt - 1].slice != pg.slice) {
-      tch[nt].slice = pg.slice;
-      tch[nt].g_begin = i;
-      tch[nt].pad = 0;
-      ++nt;
-    }
-    tch[nt - 1].g_end = i + 1;
+    grp[i].slice = pg.slice;
   }
-  int t = 0;
+  int gi = 0;
   for (int cidx = 0; cidx <= nch; ++cidx) {
     const int first = cidx * ch;
-    while (t < nt && tch[t].slice < first) ++t;
-    tptr[cidx] = t;
+    while (gi < ng && grp[gi].slice < first) ++gi;
+    gptr[cidx] = gi;
   }
   const int64_t step = c->step_enq + 1;
   const int slot = (int)(step % kReportRing);
+  std::memset(h, 0, sizeof *h);
   h->K = K;
   h->K_prev = Kp;
-  h->n_touched = nt;
   h->n_groups = ng;
   h->n_chunks = nch;
   h->chunk = ch;
@@ -627,46 +635,18 @@ dash_status dash_update_async(dash_ctx *c) {
   HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
   c->stage_used[s] = true;
 
-  PassArgs a{};
-  a.J = c->J;
-  a.R = c->R;
-  a.lambda = c->cfg.lambda;
-  a.K_cap = c->K_cap;
-  a.hdr = (const StepHeader *)c->dstep;
-  a.chunk_tptr = (const int32_t *)(c->dstep + c->off_tptr);
-  a.touched = (const Touched *)(c->dstep + c->off_touched);
-  a.groups = (const Group *)(c->dstep + c->off_groups);
-  a.Y = c->Y;
-  a.D = c->D;
-  a.n = c->n;
-  a.cur = c->cur;
-  a.tlast = c->tlast;
-  a.W = c->W;
-  a.vb = c->vb;
-  a.vb_stride = c->vb_stride;
-  a.ctl = c->ctl;
-  a.U_out = c->U_out;
-  a.partials = c->partials;
+  PassArgs a = base_args(c);
   a.mode = 0;
-  const int plen = partial_len(c->J, c->R);
   for (int p = 0; p < c->cfg.n_iter; ++p) {
     a.pass = p;
-    a.write_u = (p == c->cfg.n_iter - 1) ? 1 : 0;
+    a.last_pass = (p == c->cfg.n_iter - 1) ? 1 : 0;
     HIP_OR_FAIL(c, prof_begin(c, kProfPass));
-    LAUNCH_OR_FAIL(c, launch_pass(a, nch, c->stream));
-    HIP_OR_FAIL(c, prof_end(c));
-    HIP_OR_FAIL(c, prof_begin(c, kProfReduce));
-    LAUNCH_OR_FAIL(c, launch_reduce(c->partials, c->gpart, a.hdr, plen, nch, h->n_rgroups,
-                                    kChunksPerRGroup, c->stream));
+    LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
     HIP_OR_FAIL(c, prof_end(c));
     HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
-    LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, h->n_rgroups, c->vb, c->vb_stride, c->ctl,
-                                   0, c->stream));
+    LAUNCH_OR_FAIL(c, launch_finish(a, 0, c->stream));
     HIP_OR_FAIL(c, prof_end(c));
   }
-  HIP_OR_FAIL(c, prof_begin(c, kProfCommit));
-  LAUNCH_OR_FAIL(c, launch_commit(a.hdr, a.touched, c->cur, c->tlast, c->ctl, nt, c->stream));
-  HIP_OR_FAIL(c, prof_end(c));
   if (c->profiling) c->prof.updates++;
   c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
   c->K_enq = K;
@@ -782,21 +762,22 @@ dash_status dash_get_state(dash_ctx *c, double *V, double *W, double *Y, double 
     double *dY = nullptr, *dD = nullptr, *dn = nullptr;
     if (dalloc(&dY, sizeof(double) * K * R * J) != hipSuccess || dalloc(&dD, sizeof(double) * K * R * R) != hipSuccess ||
         dalloc(&dn, sizeof(double) * K) != hipSuccess) {
-      hipFree(dY);
-      hipFree(dD);
-      hipFree(dn);
+      (void)hipFree(dY);
+      (void)hipFree(dD);
+      (void)hipFree(dn);
       return fail(c, DASH_E_OUT_OF_MEMORY, "export buffers");
     }
-    int e = launch_export_state(c->J, c->R, c->K, c->step, c->cfg.lambda, c->Y, c->D, c->n, c->cur, c->tlast,
+    int e = launch_export_state(c->J, c->R, c->K, c->step, c->cfg.lambda, c->Y, c->D, c->n,
+                                c->cur + (int64_t)ctl.gcur * c->K_cap, c->tlast + (int64_t)ctl.gcur * c->K_cap,
                                 c->K_cap, dY, dD, dn, c->stream);
     hipError_t he = (hipError_t)e;
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he == hipSuccess && Y) he = hipMemcpy(Y, dY, sizeof(double) * K * R * J, hipMemcpyDeviceToHost);
     if (he == hipSuccess && D) he = hipMemcpy(D, dD, sizeof(double) * K * R * R, hipMemcpyDeviceToHost);
     if (he == hipSuccess && n) he = hipMemcpy(n, dn, sizeof(double) * K, hipMemcpyDeviceToHost);
-    hipFree(dY);
-    hipFree(dD);
-    hipFree(dn);
+    (void)hipFree(dY);
+    (void)hipFree(dD);
+    (void)hipFree(dn);
     if (he != hipSuccess) return fail(c, DASH_E_DEVICE, "state export: %s", hipGetErrorString(he));
   }
   return DASH_OK;
@@ -816,14 +797,15 @@ dash_status dash_set_state(dash_ctx *c, int32_t K, const double *V, const double
   // only host-side arithmetic
   std::vector<float> f((size_t)std::max<int64_t>(K * R * J, K * R * R));
   for (int64_t i = 0; i < K * R * J; ++i) f[i] = (float)Y[i];
-  HIP_OR_FAIL(c, hipMemcpy(c->Y, f.data(), sizeof(float) * K * R * J, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy2D(c->Y, sizeof(float) * y_stride(c->J, c->R), f.data(), sizeof(float) * R * J,
+                             sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
   for (int64_t i = 0; i < K * R * R; ++i) f[i] = (float)D[i];
   HIP_OR_FAIL(c, hipMemcpy(c->D, f.data(), sizeof(float) * K * R * R, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->n, n, sizeof(double) * K, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->W, W, sizeof(double) * K * R, hipMemcpyHostToDevice));
   const VBundleView v = vb_view(c->vb, c->J, c->R);
   HIP_OR_FAIL(c, hipMemcpy(v.V64, V, sizeof(double) * J * R, hipMemcpyHostToDevice));
-  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, 0, c->vb, c->vb_stride, c->ctl, 1, c->stream));
+  if (dash_status s = enqueue_prep(c)) return s;
   if (dash_status s = enqueue_eval(c, K)) return s;
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->initialized = true;
@@ -866,7 +848,8 @@ dash_status dash_save(dash_ctx *c, const char *path) {
     (void)hipFree(dn);
     return fail(c, DASH_E_OUT_OF_MEMORY, "checkpoint buffers");
   }
-  hipError_t he = (hipError_t)launch_gather_state(c->J, c->R, c->K, c->Y, c->D, c->n, c->cur, c->K_cap, dY, dD, dn,
+  hipError_t he = (hipError_t)launch_gather_state(c->J, c->R, c->K, c->Y, c->D, c->n,
+                                                  c->cur + (int64_t)ctl.gcur * c->K_cap, c->K_cap, dY, dD, dn,
                                                   c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   if (he == hipSuccess) he = hipMemcpy(Y.data(), dY, sizeof(float) * Y.size(), hipMemcpyDeviceToHost);
@@ -879,7 +862,8 @@ dash_status dash_save(dash_ctx *c, const char *path) {
   if (he == hipSuccess) he = hipMemcpy(V.data(), v.V64, sizeof(double) * V.size(), hipMemcpyDeviceToHost);
   if (he == hipSuccess)
     he = hipMemcpy(W.data(), c->W + (int64_t)ctl.gcur * c->K_cap * R, sizeof(double) * W.size(), hipMemcpyDeviceToHost);
-  if (he == hipSuccess) he = hipMemcpy(tl.data(), c->tlast, sizeof(int32_t) * K, hipMemcpyDeviceToHost);
+  if (he == hipSuccess)
+    he = hipMemcpy(tl.data(), c->tlast + (int64_t)ctl.gcur * c->K_cap, sizeof(int32_t) * K, hipMemcpyDeviceToHost);
   if (he != hipSuccess) return fail(c, DASH_E_DEVICE, "checkpoint read-back: %s", hipGetErrorString(he));
   FILE *fp = std::fopen(path, "wb");
   if (!fp) return fail(c, DASH_E_IO, "cannot open %s", path);
@@ -923,14 +907,15 @@ dash_status dash_load(dash_ctx *c, const char *path) {
   if (!ok) return fail(c, DASH_E_IO, "short read from %s", path);
   if (dash_status s = dash_wait(c, nullptr)) return s;
   if (dash_status s = reset_device_state(c, (int32_t)K, 0)) return s;
-  HIP_OR_FAIL(c, hipMemcpy(c->Y, Y.data(), sizeof(float) * Y.size(), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy2D(c->Y, sizeof(float) * y_stride(c->J, c->R), Y.data(), sizeof(float) * R * J,
+                             sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->D, D.data(), sizeof(float) * D.size(), hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->n, n.data(), sizeof(double) * n.size(), hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->W, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->tlast, tl.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
   const VBundleView v = vb_view(c->vb, c->J, c->R);
   HIP_OR_FAIL(c, hipMemcpy(v.V64, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice));
-  LAUNCH_OR_FAIL(c, launch_solve(c->J, c->R, c->gpart, 0, c->vb, c->vb_stride, c->ctl, 1, c->stream));
+  if (dash_status s = enqueue_prep(c)) return s;
   c->step = h.step;
   if (dash_status s = enqueue_eval(c, (int32_t)K)) return s;
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));

@@ -1,14 +1,10 @@
 // gfx950 kernels of the streaming PARAFAC2 update (DASH).
 //
-// One update = per ALS pass: k_pass (fused Lemma 1 + Lemma 2 + slice sweep),
-// k_reduce + k_solve (Lemma 3 and the next pass's V-derived operands), then
-// k_commit.  See dash_dev.h for layouts.
-//
-// Thread mapping used for every R x J per-slice matrix (Y_k, its increment and
-// the F^T accumulator): wave w of the 4 waves owns rows r = w, w+4, w+8, ...
-// (RW of them) and lane l owns columns j = l, l+64, ... (JW of them), so a row
-// of Y_k is a coalesced 64-float access per wave and diag(Y_k V) is a wave
-// reduction.  R x R matrices use a flat mapping q = tid + 256 i.
+// One update = one launch per ALS pass.  Every workgroup sweeps a chunk of
+// slices (Lemma 1 on their new rows, the forgetting-factor fold, Lemma 2) and
+// writes an F/G/n partial; the last workgroup to arrive reduces the partials in
+// a fixed order, solves Lemma 3 and prepares the next pass's V operands, and
+// on the last pass commits the update.  See dash_dev.h for layouts.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -19,10 +15,29 @@ namespace dash {
 // ---------------------------------------------------------------------------
 // wave / block helpers
 // ---------------------------------------------------------------------------
+// Order LDS accesses of one wave.  The LDS executes a wave's instructions in
+// issue order, so only the compiler must not move accesses across this point
+// (wavefront-scope fences emit no wait on outstanding global memory traffic).
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over c in [c0, c1) of src[c * stride + e], in ascending c, with the loads
+// issued in batches of 8 so their latencies overlap.
+__device__ __forceinline__ double ordered_sum(const double *src, int64_t stride, int e, int c0, int c1) {
+  double s = 0.0;
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = src[(int64_t)(c + i) * stride + e];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[i];
+  }
+  for (; c < c1; ++c) s += src[(int64_t)c * stride + e];
+  return s;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -35,6 +50,78 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Solve M x = b for an SPD n x n matrix (n <= RM) held by one wave in
+// registers: lane i owns row i of M in m[] and b_i in b.  Cholesky with the
+// pivots and factor columns broadcast by readlane; the factor is transposed
+// once through LDS (`scratch`, n*n doubles) for the back substitution.
+// Returns false, uniformly, when a pivot is not above kPivotRel times the
+// largest diagonal entry (the oracle's acceptance rule); m and b are then
+// undefined.
+template <int RM>
+__device__ bool wave_chol_solve_reg(double (&m)[RM], double &b, int n, double *scratch) {
+  const int lane = threadIdx.x & 63;
+  double dmax = 0.0;
+#pragma unroll
+  for (int p = 0; p < RM; ++p)
+    if (p < n) dmax = fmax(dmax, readlane_d(m[p], p));
+  if (!(dmax > 0.0)) return false;
+  const double thr = kPivotRel * dmax;
+#pragma unroll
+  for (int p = 0; p < RM; ++p) {
+    if (p < n) {
+      const double piv = readlane_d(m[p], p);
+      if (!(piv > thr)) return false;
+      const double lp = sqrt(piv);
+      const double lip = (lane > p) ? m[p] / lp : (lane == p ? lp : 0.0);
+      m[p] = lip;   // column p of L (rows >= p)
+#pragma unroll
+      for (int q = p + 1; q < RM; ++q) {
+        if (q < n) {
+          const double lqp = readlane_d(lip, q);
+          if (lane >= q) m[q] -= lip * lqp;
+        }
+      }
+    }
+  }
+  // forward: L y = b
+#pragma unroll
+  for (int p = 0; p < RM; ++p) {
+    if (p < n) {
+      const double yp = readlane_d(b, p) / readlane_d(m[p], p);
+      if (lane == p) b = yp;
+      else if (lane > p) b -= m[p] * yp;
+    }
+  }
+  // transpose: lane i gets column i of L (lt[q] = L[q][i])
+  if (lane < n) {
+#pragma unroll
+    for (int q = 0; q < RM; ++q)
+      if (q < n) scratch[lane * n + q] = (q <= lane) ? m[q] : 0.0;
+  }
+  wave_sync();
+  double lt[RM];
+#pragma unroll
+  for (int q = 0; q < RM; ++q) lt[q] = (q < n && lane < n) ? scratch[q * n + lane] : 0.0;
+  // backward: L^T x = y
+#pragma unroll
+  for (int p = RM - 1; p >= 0; --p) {
+    if (p < n) {
+      const double xp = readlane_d(b, p) / readlane_d(lt[p], p);
+      if (lane == p) b = xp;
+      else if (lane < p) b -= lt[p] * xp;
+    }
+  }
+  wave_sync();
+  return true;
 }
 
 // Cholesky factorisation of the n x n SPD matrix M (row-major, LDS) by one
@@ -180,14 +267,659 @@ __device__ void wave_pinv_apply(double *M, double *x, int n, double *Z, double *
 }
 
 // ---------------------------------------------------------------------------
-// LDS plan of the pass / accumulate kernels
+// Final phase of a pass, run by the last workgroup to arrive (any block size).
+//   mode 0: F, G, n from the group partials; Lemma 3: V = F G^{-1} into the
+//           spare bundle with V^T V, B = (V^T V)^{-1}, P = V B, V^T; loss and
+//           fit; on the last pass the commit (switch of touched slices and of
+//           the W / V buffers) and the pinned report.
+//   mode 1: build the committed bundle from its V64 (no reduction, no fit).
+//   mode 2: loss and fit of the committed V with F, G from the partials.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline size_t finish_lds_bytes(int J, int R) {
+  return (size_t)(R * J + 5 * R * R + 96) * 8 + 68 * 4;
+}
+// with a copy of V (J x R, FP64) kept in LDS as well
+__host__ __device__ inline size_t finish_lds_bytes_v(int J, int R) {
+  return finish_lds_bytes(J, R) + (size_t)J * R * 8;
+}
+
+// Solve L L^T x = b in place for one right-hand side held by the calling thread
+// (x in LDS or global memory, stride `inc`), L from wave_cholesky.
+__device__ __forceinline__ void chol_solve_thread(const double *L, double *x, int inc, int n) {
+  for (int p = 0; p < n; ++p) {
+    double s = x[p * inc];
+    for (int q = 0; q < p; ++q) s -= L[p * n + q] * x[q * inc];
+    x[p * inc] = s / L[p * n + p];
+  }
+  for (int p = n - 1; p >= 0; --p) {
+    double s = x[p * inc];
+    for (int q = p + 1; q < n; ++q) s -= L[q * n + p] * x[q * inc];
+    x[p * inc] = s / L[p * n + p];
+  }
+}
+
+// pinv(A) of a symmetric PSD n x n matrix into Out (LDS), the whole block
+// taking part; A is destroyed (wave 0 diagonalises it, eigenvectors in Z).
+__device__ void block_pinv(double *A, double *Z, double *Out, int n, double *rot, int *pair) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if ((tid >> 6) == 0) wave_jacobi(A, Z, n, rot, pair);
+  __syncthreads();
+  double top = 0.0;
+  for (int i = 0; i < n; ++i) top = fmax(top, fabs(A[i * n + i]));
+  for (int q = tid; q < n * n; q += nt) {
+    const int r = q / n, c = q - r * n;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double li = A[i * n + i];
+      if (top > 0.0 && li > kEigCutoff * top) acc += Z[r * n + i] * Z[c * n + i] / li;
+    }
+    Out[q] = acc;
+  }
+  __syncthreads();
+}
+
+__device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroups, int mode,
+                            unsigned char *smem, size_t lds_avail) {
+  const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
+  const int J = a.J, R = a.R, RR = R * R, RJ = R * J;
+  const int plen = partial_len(J, R);
+  double *sF = (double *)smem;   // F^T, R x J
+  double *sG = sF + RJ;
+  double *sL = sG + RR;
+  double *sB = sL + RR;
+  double *sVtV = sB + RR;
+  double *sZ = sVtV + RR;
+  double *sRot = sZ + RR;        // 64
+  double *sRed = sRot + 64;      // 32
+  int *sPair = (int *)(sRed + 32);
+  int *sFlag = sPair + 64;       // [0]: Cholesky ok, [1]: non-finite seen
+  // V (J x R) in LDS when the workgroup has room, else worked on in V64 directly
+  double *sVl = (double *)(smem + finish_lds_bytes(J, R));
+  const bool v_lds = lds_avail >= finish_lds_bytes_v(J, R);
+  const int gcur = a.ctl->gcur;
+  const int out = (mode == 0) ? 1 - gcur : gcur;
+  const VBundleView vo = vb_view(a.vb + (int64_t)out * a.vb_stride, J, R);
+  double *Vw = v_lds ? sVl : vo.V64;   // V, row-major J x R
+  if (tid == 0) sFlag[1] = 0;
+  double sum_n = 0.0;
+  if (mode != 1) {
+    for (int e = tid; e < plen; e += nt) {
+      const double s = ordered_sum(a.gpart, plen, e, 0, n_rgroups);
+      if (e < RJ + RR) sF[e] = s;   // sF and sG are contiguous
+      else sRed[31] = s;
+    }
+  }
+  __syncthreads();
+  if (mode != 1) sum_n = sRed[31];
+  double vf = 0.0;
+  if (mode == 0) {
+    // Lemma 3: V = F G^{-1}, i.e. G v_j^T = f_j^T for every row j
+    if (wv == 0) {
+      for (int q = lane; q < RR; q += 64) sL[q] = sG[q];
+      wave_sync();
+      const bool okc = wave_cholesky(sL, R);
+      if (lane == 0) sFlag[0] = okc ? 1 : 0;
+    }
+    __syncthreads();
+    const bool chol = sFlag[0] != 0;
+    if (!chol) {
+      for (int q = tid; q < RR; q += nt) sL[q] = sG[q];
+      __syncthreads();
+      block_pinv(sL, sZ, sB, R, sRot, sPair);   // sB = pinv(G)
+    }
+    for (int j = tid; j < J; j += nt) {
+      double *v = Vw + (size_t)j * R;
+      if (chol) {
+        for (int r = 0; r < R; ++r) v[r] = sF[r * J + j];
+        chol_solve_thread(sL, v, 1, R);
+      } else {
+        for (int r = 0; r < R; ++r) {
+          double acc = 0.0;
+          for (int c = 0; c < R; ++c) acc += sB[r * R + c] * sF[c * J + j];
+          v[r] = acc;
+        }
+      }
+      for (int r = 0; r < R; ++r) {
+        const double x = v[r];
+        if (v_lds) vo.V64[(int64_t)j * R + r] = x;
+        vf += x * sF[r * J + j];
+        if (!isfinite(x)) sFlag[1] = 1;
+      }
+    }
+  } else {
+    for (int e = tid; e < J * R; e += nt) {
+      const double x = vo.V64[e];
+      if (v_lds) sVl[e] = x;
+      if (mode == 2) {
+        const int j = e / R, r = e - j * R;
+        vf += x * sF[r * J + j];
+      }
+    }
+  }
+  vf = wave_sum(vf);
+  if (lane == 0) sRed[wv] = vf;
+  __syncthreads();
+  double VF = 0.0;
+  for (int w = 0; w < nwv; ++w) VF += sRed[w];
+
+  if (mode != 2) {
+    // next pass operands: V^T V, B = (V^T V)^{-1}, P = V B, V^T in float32
+    for (int q = tid; q < RR; q += nt) {
+      const int r = q / R, c = q - r * R;
+      double acc = 0.0;
+      for (int j = 0; j < J; ++j) acc += Vw[(size_t)j * R + r] * Vw[(size_t)j * R + c];
+      sVtV[q] = acc;
+      vo.VtV[q] = acc;
+    }
+    for (int e = tid; e < RJ; e += nt) {
+      const int r = e / J, j = e - r * J;
+      vo.Vt32[e] = (float)Vw[(size_t)j * R + r];
+    }
+    __syncthreads();
+    if (wv == 0) {
+      for (int q = lane; q < RR; q += 64) sL[q] = sVtV[q];
+      wave_sync();
+      const bool okc = wave_cholesky(sL, R);
+      if (lane == 0) sFlag[0] = okc ? 1 : 0;
+    }
+    __syncthreads();
+    if (sFlag[0]) {
+      for (int col = tid; col < R; col += nt) {
+        for (int p = 0; p < R; ++p) sB[p * R + col] = (p == col) ? 1.0 : 0.0;
+        chol_solve_thread(sL, sB + col, R, R);
+      }
+      __syncthreads();
+    } else {
+      for (int q = tid; q < RR; q += nt) sL[q] = sVtV[q];
+      __syncthreads();
+      block_pinv(sL, sZ, sB, R, sRot, sPair);
+    }
+    for (int e = tid; e < J * R; e += nt) {
+      const int j = e / R, c = e - j * R;
+      double acc = 0.0;
+      for (int r = 0; r < R; ++r) acc += Vw[(size_t)j * R + r] * sB[r * R + c];
+      vo.P32[e] = (float)acc;
+    }
+  } else {
+    for (int q = tid; q < RR; q += nt) sVtV[q] = vo.VtV[q];
+    __syncthreads();
+  }
+  if (mode == 1) return;
+  __syncthreads();
+  double vg = 0.0;
+  for (int q = 0; q < RR; ++q) vg += sVtV[q] * sG[q];
+  const double loss = sum_n - 2.0 * VF + vg;
+  const double fit = sum_n > 0.0 ? 1.0 - sqrt(fmax(0.0, loss)) / sqrt(sum_n) : 1.0;
+  const bool ok = isfinite(loss) && !sFlag[1];
+  if (tid == 0) {
+    a.ctl->loss = loss;
+    a.ctl->fit = fit;
+    a.ctl->sum_n = sum_n;
+  }
+  if (mode != 0) return;
+  // every pass of an update must be finite for it to commit
+  if (tid == 0 && !ok) a.ctl->ok = 0;
+  if (!a.last_pass) return;
+  __syncthreads();
+  // the sweep wrote the next state beside the committed one (Y, D, n per slice,
+  // the slice bookkeeping, W, the V bundle): committing switches buffers
+  const bool commit = ok && a.ctl->ok && !a.ctl->poison;
+  if (tid == 0) {
+    Report *rep = (Report *)h->report;
+    rep->step = h->step;
+    rep->rows = h->M;
+    rep->K = h->K;
+    rep->committed = commit ? 1 : 0;
+    rep->fit = fit;
+    rep->loss = loss;
+    rep->sum_n = sum_n;
+    if (commit)
+      a.ctl->gcur = 1 - gcur;
+    else
+      a.ctl->poison = 1;
+    a.ctl->ok = 1;  // reset for the next update
+    rep->done = 1;  // visible to the host once the kernel has completed
+  }
+}
+
+// Arrival of a workgroup whose chunk partial is written: the last of each group
+// of kChunksPerRGroup chunks to arrive sums the group's partials in chunk order
+// into gpart (a first reduction level inside the sweep launch; k_finish does the
+// second).  The group's ticket is reset by that workgroup, so all tickets are
+// zero again when the launch ends.
+__device__ void arrive(const PassArgs &a, const StepHeader *h, int chunk, int *sflag) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int plen = partial_len(a.J, a.R);
+  const int cpr = h->chunks_per_rgroup;
+  const int rg = chunk / cpr;
+  const int c0 = rg * cpr, c1 = min(h->n_chunks, c0 + cpr);
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const int old = atomicAdd(&a.counters[rg], 1);
+    *sflag = (old == c1 - c0 - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!*sflag) return;
+  __threadfence();
+  for (int e = tid; e < plen; e += nt) a.gpart[(int64_t)rg * plen + e] = ordered_sum(a.partials, plen, e, c0, c1);
+  if (tid == 0) a.counters[rg] = 0;
+}
+
+// Final phase of a pass as its own single-workgroup launch (modes as finish_pass).
+__host__ __device__ inline size_t finish_launch_lds(int J, int R) {
+  const size_t with_v = finish_lds_bytes_v(J, R);
+  return with_v <= 150 * 1024 ? with_v : finish_lds_bytes(J, R);
+}
+
+__global__ __launch_bounds__(1024) void k_finish(PassArgs a, int mode) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const StepHeader *h = a.hdr;
+  finish_pass(a, h, mode == 1 ? 0 : h->n_rgroups, mode, smem, finish_launch_lds(a.J, a.R));
+}
+
+// ---------------------------------------------------------------------------
+// Sweep variant 1: one wave per slice ("wave" variant, R*J <= 2048, J <= 128).
+// 8 waves per workgroup; wave w handles slices k0+w, k0+w+8, ... of the chunk.
+// A slice's R x J state is spread flat over the wave: lane l holds elements
+// e = l + 64 i (i < EPT) of the contiguous row-major Y_k, so every load and
+// store of Y_k is one coalesced access with a single base address.
+// Per slice, within the wave only (no block barriers):
+//   new rows (16-row blocks staged in the wave's LDS):
+//     u = (x P) * (1/w_k)  (Lemma 1; 4 lanes per row, R/4 outputs per lane)
+//     dY += u^T x, dD += u^T u, dn += ||x||^2
+//   fold:    Y_k = lambda^dt Y_k,stored + dY  (touched), else the stored Y_k
+//   Lemma 2: c = diag(Y_k V) (products transposed through LDS, FP64 row sums);
+//            (V^T V * D_k) w = c by FP64 Cholesky (pseudo-inverse fallback)
+//   sweep:   F^T += sigma w_k Y_k, G += sigma w_k w_k^T * D_k, sum n
+// Untouched slices solve on their stored (undecayed) Y_k, D_k -- w_k does not
+// depend on the common factor lambda^dt -- and enter F, G with sigma = lambda^dt.
+// ---------------------------------------------------------------------------
+constexpr int kWaveRows = 16;   // rows per staged block
+constexpr int kWaveWarps = 8;   // waves per workgroup
+
+struct WaveLds {
+  int XS;
+  size_t oP, oVt, oVtV, oWave, wave_bytes, oSmall, oX, oU, oM, oZ, oRot, oTmp, oPair, oProd, oDcur, bytes;
+};
+
+__host__ __device__ inline WaveLds wave_lds(int J, int R) {
+  WaveLds L;
+  L.XS = J | 1;
+  size_t o = 0;
+  L.oP = o;   o += (size_t)J * R * 4;
+  L.oVt = o;  o += (size_t)y_stride(J, R) * 4;
+  o = align_up(o, 8);
+  L.oVtV = o; o += (size_t)R * R * 8;
+  o = align_up(o, 16);
+  L.oWave = o;
+  // per-wave region: small vectors, then a union of the row block, the
+  // products of diag(Y_k V), and the solve scratch
+  size_t w = 0;
+  L.oSmall = w; w += (size_t)(R + 1) * 8 * 3 + (size_t)R * 4;   // sW, sC, sC2 (f64, R+1), sWinv (f32)
+  w = align_up(w, 16);
+  const size_t blk = w;
+  L.oX = blk;
+  L.oU = blk + (size_t)kWaveRows * L.XS * 4;
+  const size_t rows_end = L.oU + (size_t)kWaveRows * (R + 1) * 4;
+  L.oProd = blk;
+  const size_t prod_end = blk + (size_t)y_stride(J, R) * 4;
+  L.oDcur = blk;
+  L.oM = blk + align_up((size_t)R * R * 4, 16);
+  L.oZ = L.oM + (size_t)R * R * 8;
+  L.oRot = L.oZ + (size_t)R * R * 8;
+  L.oTmp = L.oRot + 64 * 8;
+  L.oPair = L.oTmp + 64 * 8;
+  size_t end = L.oPair + 64 * 4;
+  if (rows_end > end) end = rows_end;
+  if (prod_end > end) end = prod_end;
+  L.wave_bytes = align_up(end, 16);
+  o += L.wave_bytes * kWaveWarps;
+  const size_t comb = (size_t)partial_len(J, R) * 8;
+  L.bytes = align_up(o > comb ? o : comb, 16);
+  return L;
+}
+
+template <int EPT, int DQ>
+__global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
+  constexpr int RC = DQ == 1 ? 8 : DQ == 2 ? 12 : DQ == 4 ? 16 : DQ == 8 ? 24 : 32;  // R <= RC
+  constexpr int RPL = RC / 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sflag;
+  const StepHeader *h = a.hdr;
+  const int chunk = blockIdx.x;
+  if (chunk >= h->n_chunks) return;
+  const int J = a.J, R = a.R, RR = R * R, RJ = R * J, YS = a.ys;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int K = h->K, Kp = h->K_prev;
+  const int64_t step = h->step;
+  const int gcur = a.ctl->gcur;
+  const int win = (a.pass == 0) ? gcur : 1 - gcur;
+  const int wout = 1 - gcur;
+  const VBundleView vb = vb_view(a.vb + (int64_t)win * a.vb_stride, J, R);
+  const WaveLds L = wave_lds(J, R);
+  float *sP = (float *)(smem + L.oP);
+  float *sVt = (float *)(smem + L.oVt);
+  double *sVtV = (double *)(smem + L.oVtV);
+  unsigned char *wbase = smem + L.oWave + (size_t)wv * L.wave_bytes;
+  double *sW = (double *)(wbase + L.oSmall);
+  double *sC = sW + (R + 1);
+  double *sC2 = sC + (R + 1);
+  float *sWinv = (float *)(sC2 + (R + 1));
+  float *sX = (float *)(wbase + L.oX);
+  float *sU = (float *)(wbase + L.oU);
+  float *sProd = (float *)(wbase + L.oProd);
+  double *sM = (double *)(wbase + L.oM);
+  double *sZ = (double *)(wbase + L.oZ);
+  double *sRot = (double *)(wbase + L.oRot);
+  double *sTmp = (double *)(wbase + L.oTmp);
+  int *sPair = (int *)(wbase + L.oPair);
+  const int XS = L.XS;
+  const float invJ = 1.0f / (float)J;   // e / J below is exact: e < 2^11, J <= 128
+  constexpr int NB = kWaveRows * 2;     // staged floats per lane for a 16 x 128 row block
+
+  for (int e = tid; e < J * R; e += 512) sP[e] = vb.P32[e];
+  for (int e = tid; e < YS; e += 512) sVt[e] = (e < RJ) ? vb.Vt32[e] : 0.f;
+  for (int e = tid; e < RR; e += 512) sVtV[e] = vb.VtV[e];
+  __syncthreads();
+
+  float facc[EPT];   // this wave's F^T partial (one slice per wave up to 4096 slices)
+  double gacc[DQ];
+  double nacc = 0.0;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) facc[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < DQ; ++i) gacc[i] = 0.0;
+
+  const int k0 = chunk * h->chunk;
+  const int k1 = min(K, k0 + h->chunk);
+  const int g0 = a.chunk_gptr[chunk], g1 = a.chunk_gptr[chunk + 1];
+
+  for (int k = k0 + wv; k < k1; k += kWaveWarps) {
+    const bool is_new = k >= Kp;
+    // issue every load of the slice's state first so their latencies overlap;
+    // slice-level values are wave-uniform
+    const int b = __builtin_amdgcn_readfirstlane((int)a.cur[(int64_t)gcur * a.K_cap + k]);
+    const int tl = __builtin_amdgcn_readfirstlane(a.tlast[(int64_t)gcur * a.K_cap + k]);
+    double w = 0.0;
+    if (lane < R) w = (is_new && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + lane];
+    const float *Yst = a.Y + ((int64_t)b * a.K_cap + k) * YS;
+    const float *Dst = a.D + ((int64_t)b * a.K_cap + k) * RR;
+    float dold[DQ];
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) {
+      const int q = lane + 64 * i;
+      dold[i] = (q < RR && !is_new) ? Dst[q] : 0.f;
+    }
+    const double nold = (lane == 0 && !is_new) ? a.n[(int64_t)b * a.K_cap + k] : 0.0;
+    // groups of slice k: contiguous run inside [g0, g1)
+    int gb = -1, ge = -1;
+    for (int base = g0; base < g1; base += 64) {
+      const int g = base + lane;
+      const int sl = (g < g1) ? a.groups[g].slice : -1;
+      const unsigned long long m = __ballot(sl == k);
+      if (m) {
+        const int first = base + __ffsll((long long)m) - 1;
+        const int last = base + 63 - __clzll((long long)m);
+        if (gb < 0) gb = first;
+        ge = last + 1;
+      } else if (gb >= 0) {
+        break;
+      }
+    }
+    const bool touched = gb >= 0;
+    {
+      if (lane < R) sW[lane] = w;
+      const double top = wave_max(fabs(w));
+      if (lane < R) sWinv[lane] = (fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
+      if (lane == 0) sC[R] = 0.0;   // weight of the padding elements of Y_k
+    }
+    wave_sync();
+
+    float dD[DQ];
+    double dn = 0.0;
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) dD[i] = 0.f;
+    // dY = U_new^T X_new as an R x J register tile: lane = column j (two
+    // 64-column halves), RC rows
+    float dy[RC][2];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) dy[r][0] = dy[r][1] = 0.f;
+    const int j0 = min(lane, J - 1), j1 = min(lane + 64, J - 1);
+
+    if (touched && a.mode == 0) {
+      for (int g = gb; g < ge; ++g) {
+        const Group *gp = a.groups + g;
+        const int nrows = __builtin_amdgcn_readfirstlane(gp->nrows);
+        const int64_t out_row = ((int64_t)__builtin_amdgcn_readfirstlane((int)(gp->out_row >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)gp->out_row);
+        const uint64_t srcbits = (uint64_t)gp->src;
+        const float *gsrc = (const float *)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(srcbits >> 32)) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readfirstlane((int)srcbits));
+        for (int r0 = 0; r0 < nrows; r0 += kWaveRows) {
+          const int m = min(kWaveRows, nrows - r0);
+          const int tot = m * J;
+          const float *src = gsrc + (int64_t)r0 * J;
+          wave_sync();  // the previous block's readers are done
+          for (int i0 = 0; i0 < NB; i0 += 8) {
+            if (64 * i0 >= tot) break;
+            float buf[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int e = lane + 64 * (i0 + i);
+              buf[i] = (e < tot) ? src[e] : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const int e = lane + 64 * (i0 + i);
+              if (e < tot) {
+                const int row = (int)(((float)e + 0.5f) * invJ);
+                sX[row * XS + (e - row * J)] = buf[i];
+                dn += (double)buf[i] * (double)buf[i];
+              }
+            }
+          }
+          wave_sync();
+          {
+            const int row = lane >> 2, rq = lane & 3;
+            if (row < m) {
+              float t[RPL];
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) t[i] = 0.f;
+              const float *xr = sX + row * XS;
+#pragma unroll 4
+              for (int j = 0; j < J; ++j) {
+                const float xv = xr[j];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                  const int r = rq + 4 * i;
+                  if (r < R) t[i] = fmaf(xv, sP[j * R + r], t[i]);
+                }
+              }
+#pragma unroll
+              for (int i = 0; i < RPL; ++i) {
+                const int r = rq + 4 * i;
+                if (r < R) {
+                  const float u = t[i] * sWinv[r];
+                  sU[row * (R + 1) + r] = u;
+                  if (a.last_pass) a.U_out[(out_row + r0 + row) * R + r] = u;
+                }
+              }
+            }
+          }
+          wave_sync();
+#pragma unroll 2
+          for (int row = 0; row < m; ++row) {
+            const float x0 = sX[row * XS + j0], x1 = sX[row * XS + j1];
+            const float *ur = sU + row * (R + 1);
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+              if (r < R) {
+                const float u = ur[r];
+                dy[r][0] = fmaf(u, x0, dy[r][0]);
+                dy[r][1] = fmaf(u, x1, dy[r][1]);
+              }
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < DQ; ++i) {
+            const int q = lane + 64 * i;
+            if (q < RR) {
+              const int r = q / R, s = q - r * R;
+              float acc = dD[i];
+#pragma unroll 4
+              for (int row = 0; row < m; ++row) acc = fmaf(sU[row * (R + 1) + r], sU[row * (R + 1) + s], acc);
+              dD[i] = acc;
+            }
+          }
+        }
+      }
+      dn = wave_sum(dn);
+    }
+    // hand dY to the flat layout through LDS (zero on the padding)
+    wave_sync();
+    float *sDY = sProd;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      if (r < R) {
+        if (lane < J) sDY[r * J + lane] = dy[r][0];
+        if (lane + 64 < J) sDY[r * J + lane + 64] = dy[r][1];
+      }
+    }
+    if (RJ + lane < YS) sDY[RJ + lane] = 0.f;
+    wave_sync();
+
+    const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
+    const float s_old_f = (float)s_old;
+    wave_sync();  // the row block is dead: the product buffer may overwrite it
+    float yc[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      yc[i] = 0.f;
+      if (64 * i >= YS) continue;   // uniform: the slice has YS / 64 flat blocks
+      const int e = lane + 64 * i;
+      const float yo = is_new ? 0.f : Yst[e];
+      yc[i] = touched ? fmaf(s_old_f, yo, sDY[e]) : yo;
+      sProd[e] = yc[i] * sVt[e];   // same element as sDY[e]: read before written
+    }
+    wave_sync();
+    // c_r = sum_j Y_k[r][j] V[j][r]: lane r sums row r of the products in FP64
+    double cr = 0.0;
+    if (lane < R) {
+      const float *pr = sProd + lane * J;
+#pragma unroll 8
+      for (int j = 0; j < J; ++j) cr += (double)pr[j];
+    }
+    wave_sync();  // products consumed: the buffer takes the current D_k
+    float *sDcur = (float *)(wbase + L.oDcur);
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) {
+      const int q = lane + 64 * i;
+      if (q < RR) {
+        const float dc = touched ? fmaf(s_old_f, dold[i], dD[i]) : dold[i];
+        dD[i] = dc;
+        sDcur[q] = dc;
+      }
+    }
+    wave_sync();
+    if (lane < R) {
+      sC[lane] = cr;
+      sC2[lane] = cr;
+    }
+    if (a.mode == 0) {
+      // Lemma 2: (V^T V * D_k) w = c, FP64 Cholesky in the wave's LDS
+      for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * (double)sDcur[q];
+      wave_sync();
+      if (wave_cholesky(sM, R)) {
+        wave_chol_apply(sM, sC, R);
+      } else {
+        for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * (double)sDcur[q];
+        if (lane < R) sC[lane] = sC2[lane];
+        wave_sync();
+        wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
+      }
+      if (lane < R) a.W[((int64_t)wout * a.K_cap + k) * R + lane] = sC[lane];
+    } else {
+      if (lane < R) sC[lane] = sW[lane];
+    }
+    wave_sync();
+    const double sigma = touched ? 1.0 : s_old;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      if (64 * i >= YS) continue;
+      const int e = lane + 64 * i;
+      const int r = min((int)(((float)e + 0.5f) * invJ), R);
+      facc[i] = fmaf((float)(sigma * sC[r]), yc[i], facc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) {
+      const int q = lane + 64 * i;
+      if (q < RR) {
+        const int r = q / R, s = q - r * R;
+        gacc[i] += sigma * sC[r] * sC[s] * (double)dD[i];
+      }
+    }
+    if (lane == 0) {
+      const double ncur = s_old * nold + dn;
+      nacc += ncur;
+      if (touched && a.mode == 0) a.n[(int64_t)(1 - b) * a.K_cap + k] = ncur;
+      if (a.mode == 0) {
+        // slice bookkeeping of the next state (made current by the commit)
+        a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(touched ? 1 - b : b);
+        a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = touched ? (int32_t)step : tl;
+      }
+    }
+    if (touched && a.mode == 0) {
+      float *Ynx = a.Y + ((int64_t)(1 - b) * a.K_cap + k) * YS;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        if (64 * i < YS) Ynx[lane + 64 * i] = yc[i];
+      float *Dnx = a.D + ((int64_t)(1 - b) * a.K_cap + k) * RR;
+#pragma unroll
+      for (int i = 0; i < DQ; ++i) {
+        const int q = lane + 64 * i;
+        if (q < RR) Dnx[q] = dD[i];
+      }
+    }
+  }
+
+  // combine the waves' accumulators in wave order, write the chunk partial
+  __syncthreads();
+  double *sComb = (double *)smem;
+  const int plen = partial_len(J, R);
+  for (int w = 0; w < kWaveWarps; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = lane + 64 * i;
+        if (e < RJ) sComb[e] = (w == 0 ? 0.0 : sComb[e]) + (double)facc[i];
+      }
+#pragma unroll
+      for (int i = 0; i < DQ; ++i) {
+        const int q = lane + 64 * i;
+        if (q < RR) sComb[RJ + q] = (w == 0 ? 0.0 : sComb[RJ + q]) + gacc[i];
+      }
+      if (lane == 0) sComb[RJ + RR] = (w == 0 ? 0.0 : sComb[RJ + RR]) + nacc;
+    }
+    __syncthreads();
+  }
+  double *part = a.partials + (int64_t)chunk * plen;
+  for (int e = tid; e < plen; e += 512) part[e] = sComb[e];
+  arrive(a, h, chunk, &sflag);
+}
+
+// ---------------------------------------------------------------------------
+// Sweep variant 2: one workgroup per slice ("block" variant, any R <= 32,
+// J <= 256), for slices whose R x J state does not fit one wave's registers.
+// Same arithmetic as the wave variant; the 4 waves split the R x J matrices by
+// rows (wave w owns r = w, w+4, ...) and lanes own columns.
 // ---------------------------------------------------------------------------
 struct PassLds {
   int XS, MB;
   size_t oP, oVt, oX, oU, oW, oWinv, oC, oC2, oM, oDc, oVtV, oZ, oTmp, oRot, oPair, bytes;
 };
 
-__host__ __device__ inline PassLds pass_lds(int J, int R) {
+__host__ __device__ inline PassLds pass_lds(int J, int R, bool with_finish = true) {
   PassLds L;
   L.XS = J | 1;
   L.MB = (J <= 128) ? 64 : 32;
@@ -210,12 +942,12 @@ __host__ __device__ inline PassLds pass_lds(int J, int R) {
   L.oTmp = o;  o += (size_t)64 * 8;
   L.oRot = o;  o += (size_t)64 * 8;
   L.oPair = o; o += (size_t)64 * 4;
+  (void)with_finish;
   L.bytes = align_up(o, 16);
   return L;
 }
 
-// Accumulate one block of m (<= MB) rows already staged in sX (stride XS) and
-// their U rows in sU (stride R+1): dY += U^T X, dD += U^T U.
+// dY += U^T X and dD += U^T U for one staged block of m rows (block variant).
 template <int RW, int JW>
 __device__ __forceinline__ void accum_block(const float *sX, const float *sU, int XS, int m, int J,
                                             int R, float (&dY)[RW][JW], float (&dD)[4]) {
@@ -247,22 +979,10 @@ __device__ __forceinline__ void accum_block(const float *sX, const float *sU, in
   }
 }
 
-// ---------------------------------------------------------------------------
-// k_pass: one ALS pass over a chunk of slices.
-//   for each slice k of the chunk (ascending id):
-//     new rows x (if any):  u = (x P) * (1/w_k)          Lemma 1, P = V (V^T V)^{-1}
-//                           dY += u^T x, dD += u^T u, dn += ||x||^2
-//     fold:   Y_k = lambda^dt Y_k,stored + dY   (touched slices; dt = step - t_k)
-//     Lemma 2: c = diag(Y_k V), (V^T V * D_k) w_k = c     (FP64 Cholesky, pinv fallback)
-//     sweep:  F^T += sigma w_k * Y_k, G += sigma diag(w_k) D_k diag(w_k), sum n
-//   then one F/G/n partial per chunk (reduced in fixed order by k_reduce/k_solve).
-// Untouched slices are solved from their stored (undecayed) Y_k, D_k -- the
-// solution w_k is invariant to the common factor lambda^dt -- and enter F, G
-// with sigma = lambda^dt.
-// ---------------------------------------------------------------------------
 template <int RW, int JW>
-__global__ __launch_bounds__(256) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sflag;
   const StepHeader *h = a.hdr;
   const int chunk = blockIdx.x;
   if (chunk >= h->n_chunks) return;
@@ -307,14 +1027,16 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
 
   const int k0 = chunk * h->chunk;
   const int k1 = min(K, k0 + h->chunk);
-  int t = a.chunk_tptr[chunk];
-  const int tend = a.chunk_tptr[chunk + 1];
+  int g = a.chunk_gptr[chunk];
+  const int gend = a.chunk_gptr[chunk + 1];
   const int plen = partial_len(J, R);
 
   for (int k = k0; k < k1; ++k) {
-    const bool touched = (t < tend) && (a.touched[t].slice == k);
+    const int gb = g;
+    while (g < gend && a.groups[g].slice == k) ++g;
+    const bool touched = g > gb;
     const bool is_new = k >= Kp;
-    __syncthreads();  // LDS of the previous slice is free
+    __syncthreads();
     if (tid < R) {
       const double w = (is_new && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + tid];
       sW[tid] = w;
@@ -336,9 +1058,8 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
       for (int jj = 0; jj < JW; ++jj) dY[rr][jj] = 0.f;
 
     if (touched && a.mode == 0) {
-      const Touched te = a.touched[t];
-      for (int g = te.g_begin; g < te.g_end; ++g) {
-        const Group gr = a.groups[g];
+      for (int gi = gb; gi < g; ++gi) {
+        const Group gr = a.groups[gi];
         for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
           const int m = min(MB, gr.nrows - r0);
           __syncthreads();
@@ -369,7 +1090,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
               if (r < R) {
                 const float u = tacc[rr] * sWinv[r];
                 sU[lane * (R + 1) + r] = u;
-                if (a.write_u) a.U_out[(gr.out_row + r0 + lane) * R + r] = u;
+                if (a.last_pass) a.U_out[(gr.out_row + r0 + lane) * R + r] = u;
               }
             }
             if (wv == 0) dn += (double)nx;
@@ -381,10 +1102,11 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
       if (wv == 0) dn = wave_sum(dn);
     }
 
-    const int b = a.cur[k];
-    const double s_old = is_new ? 0.0 : pow(a.lambda, (double)(step - a.tlast[k]));
+    const int b = a.cur[(int64_t)gcur * a.K_cap + k];
+    const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
+    const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
     const float s_old_f = (float)s_old;
-    const float *Yst = a.Y + ((int64_t)b * a.K_cap + k) * R * J;
+    const float *Yst = a.Y + ((int64_t)b * a.K_cap + k) * a.ys;
     float yv[RW][JW];
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
@@ -396,7 +1118,6 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         yv[rr][jj] = touched ? fmaf(s_old_f, yo, dY[rr][jj]) : yo;
       }
     }
-    // c_r = sum_j Y_k[r][j] V[j][r]  (wave reduction, FP64)
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
       const int r = wv + 4 * rr;
@@ -464,9 +1185,13 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
       const double ncur = s_old * nold + dn;
       nacc += ncur;
       if (touched && a.mode == 0) a.n[(int64_t)(1 - b) * a.K_cap + k] = ncur;
+      if (a.mode == 0) {
+        a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(touched ? 1 - b : b);
+        a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = touched ? (int32_t)step : tl;
+      }
     }
     if (touched && a.mode == 0) {
-      float *Ynx = a.Y + ((int64_t)(1 - b) * a.K_cap + k) * R * J;
+      float *Ynx = a.Y + ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
 #pragma unroll
       for (int rr = 0; rr < RW; ++rr) {
         const int r = wv + 4 * rr;
@@ -483,7 +1208,6 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         if (q < RR) Dnx[q] = sDc[q];
       }
     }
-    if (touched) ++t;
   }
 
   double *part = a.partials + (int64_t)chunk * plen;
@@ -502,240 +1226,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     if (q < RR) part[R * J + q] = gacc[i];
   }
   if (tid == 0) part[R * J + RR] = nacc;
-}
-
-// ---------------------------------------------------------------------------
-// k_reduce: first level of the fixed-order reduction of chunk partials.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce(const double *partials, double *gpart,
-                                                const StepHeader *h, int plen) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int g = blockIdx.y;
-  if (e >= plen || g >= h->n_rgroups) return;
-  const int c0 = g * h->chunks_per_rgroup;
-  const int c1 = min(h->n_chunks, c0 + h->chunks_per_rgroup);
-  double s = 0.0;
-  for (int c = c0; c < c1; ++c) s += partials[(int64_t)c * plen + e];
-  gpart[(int64_t)g * plen + e] = s;
-}
-
-// ---------------------------------------------------------------------------
-// k_solve: Lemma 3 and the V-derived operands of the next pass (one workgroup).
-//   mode 0: F, G, n from the group partials; V = F G^{-1} into the spare bundle;
-//           V^T V, B = (V^T V)^{-1}, P = V B; loss / fit; ok flag.
-//   mode 1: bundle of the committed buffer from its V64 (V^T V, V^T, P).
-//   mode 2: loss / fit of the committed V with F, G from the partials.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_solve(int J, int R, const double *gpart, int n_rgroups,
-                                               char *vbase, int64_t vb_stride, Ctl *ctl, int mode) {
-  __shared__ double sG[kMaxR * kMaxR];
-  __shared__ double sL[kMaxR * kMaxR];
-  __shared__ double sB[kMaxR * kMaxR];
-  __shared__ double sVtV[kMaxR * kMaxR];
-  __shared__ double sZ[kMaxR * kMaxR];
-  __shared__ double sRot[64];
-  __shared__ int sPair[64];
-  __shared__ double sRed[kWaves];
-  __shared__ double sSumN;
-  __shared__ int sFlag;
-  __shared__ int sBad;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int RR = R * R, RJ = R * J;
-  const int plen = partial_len(J, R);
-  const int gcur = ctl->gcur;
-  const int out = (mode == 0) ? 1 - gcur : gcur;
-  const VBundleView vo = vb_view(vbase + (int64_t)out * vb_stride, J, R);
-  if (tid == 0) sBad = 0;
-  if (mode != 1) {
-    for (int q = tid; q < RR; q += 256) {
-      double s = 0.0;
-      for (int g = 0; g < n_rgroups; ++g) s += gpart[(int64_t)g * plen + RJ + q];
-      sG[q] = s;
-      sL[q] = s;
-    }
-    if (tid == 0) {
-      double s = 0.0;
-      for (int g = 0; g < n_rgroups; ++g) s += gpart[(int64_t)g * plen + RJ + RR];
-      sSumN = s;
-    }
-  }
-  __syncthreads();
-  double vf = 0.0;  // <V, F>
-  if (mode == 0) {
-    if (wv == 0) {
-      const bool okc = wave_cholesky(sL, R);
-      if (lane == 0) sFlag = okc ? 1 : 0;
-      if (!okc) {
-        for (int q = lane; q < RR; q += 64) sL[q] = sG[q];
-        wave_sync();
-        wave_jacobi(sL, sZ, R, sRot, sPair);  // eigenvalues on the diagonal of sL
-      }
-    }
-    __syncthreads();
-    double top = 0.0;
-    if (!sFlag)
-      for (int i = 0; i < R; ++i) top = fmax(top, fabs(sL[i * R + i]));
-    for (int j = tid; j < J; j += 256) {
-      double f[kMaxR], v[kMaxR];
-      for (int r = 0; r < R; ++r) {
-        double s = 0.0;
-        for (int g = 0; g < n_rgroups; ++g) s += gpart[(int64_t)g * plen + r * J + j];
-        f[r] = s;
-      }
-      if (sFlag) {
-        // v = G^{-1} f (G symmetric): L y = f, L^T v = y
-        for (int p = 0; p < R; ++p) {
-          double s = f[p];
-          for (int q = 0; q < p; ++q) s -= sL[p * R + q] * v[q];
-          v[p] = s / sL[p * R + p];
-        }
-        for (int p = R - 1; p >= 0; --p) {
-          double s = v[p];
-          for (int q = p + 1; q < R; ++q) s -= sL[q * R + p] * v[q];
-          v[p] = s / sL[p * R + p];
-        }
-      } else {
-        double tmp[kMaxR];
-        for (int i = 0; i < R; ++i) {
-          double d = 0.0;
-          for (int r = 0; r < R; ++r) d += sZ[r * R + i] * f[r];
-          const double li = sL[i * R + i];
-          tmp[i] = (top > 0.0 && li > kEigCutoff * top) ? d / li : 0.0;
-        }
-        for (int r = 0; r < R; ++r) {
-          double s = 0.0;
-          for (int i = 0; i < R; ++i) s += sZ[r * R + i] * tmp[i];
-          v[r] = s;
-        }
-      }
-      for (int r = 0; r < R; ++r) {
-        vo.V64[(int64_t)j * R + r] = v[r];
-        vf += v[r] * f[r];
-        if (!isfinite(v[r])) sBad = 1;
-      }
-    }
-  } else if (mode == 2) {
-    for (int j = tid; j < J; j += 256)
-      for (int r = 0; r < R; ++r) {
-        double s = 0.0;
-        for (int g = 0; g < n_rgroups; ++g) s += gpart[(int64_t)g * plen + r * J + j];
-        vf += vo.V64[(int64_t)j * R + r] * s;
-      }
-  }
-  vf = wave_sum(vf);
-  if (lane == 0) sRed[wv] = vf;
-  __syncthreads();
-  const double VF = sRed[0] + sRed[1] + sRed[2] + sRed[3];
-
-  if (mode != 2) {
-    // V^T V and V^T (float)
-    for (int q = tid; q < RR; q += 256) {
-      const int r = q / R, s = q - r * R;
-      double acc = 0.0;
-      for (int j = 0; j < J; ++j) acc += vo.V64[(int64_t)j * R + r] * vo.V64[(int64_t)j * R + s];
-      sVtV[q] = acc;
-      sL[q] = acc;
-      vo.VtV[q] = acc;
-    }
-    for (int e = tid; e < RJ; e += 256) {
-      const int r = e / J, j = e - r * J;
-      vo.Vt32[e] = (float)vo.V64[(int64_t)j * R + r];
-    }
-    __syncthreads();
-    // B = (V^T V)^{-1}
-    if (wv == 0) {
-      const bool okc = wave_cholesky(sL, R);
-      if (lane == 0) sFlag = okc ? 1 : 0;
-      if (!okc) {
-        for (int q = lane; q < RR; q += 64) sL[q] = sVtV[q];
-        wave_sync();
-        wave_jacobi(sL, sZ, R, sRot, sPair);
-      }
-    }
-    __syncthreads();
-    if (sFlag) {
-      if (tid < R) {
-        double col[kMaxR];
-        for (int p = 0; p < R; ++p) {
-          double s = (p == tid) ? 1.0 : 0.0;
-          for (int q = 0; q < p; ++q) s -= sL[p * R + q] * col[q];
-          col[p] = s / sL[p * R + p];
-        }
-        for (int p = R - 1; p >= 0; --p) {
-          double s = col[p];
-          for (int q = p + 1; q < R; ++q) s -= sL[q * R + p] * col[q];
-          col[p] = s / sL[p * R + p];
-        }
-        for (int p = 0; p < R; ++p) sB[p * R + tid] = col[p];
-      }
-    } else {
-      double top = 0.0;
-      for (int i = 0; i < R; ++i) top = fmax(top, fabs(sL[i * R + i]));
-      for (int q = tid; q < RR; q += 256) {
-        const int r = q / R, s = q - r * R;
-        double acc = 0.0;
-        for (int i = 0; i < R; ++i) {
-          const double li = sL[i * R + i];
-          if (top > 0.0 && li > kEigCutoff * top) acc += sZ[r * R + i] * sZ[s * R + i] / li;
-        }
-        sB[q] = acc;
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < J * R; e += 256) {
-      const int j = e / R, s = e - j * R;
-      double acc = 0.0;
-      for (int r = 0; r < R; ++r) acc += vo.V64[(int64_t)j * R + r] * sB[r * R + s];
-      vo.P32[e] = (float)acc;
-    }
-  } else {
-    for (int q = tid; q < RR; q += 256) sVtV[q] = vo.VtV[q];
-    __syncthreads();
-  }
-  if (mode != 1 && tid == 0) {
-    double vg = 0.0;
-    for (int q = 0; q < RR; ++q) vg += sVtV[q] * sG[q];
-    const double sn = sSumN;
-    const double loss = sn - 2.0 * VF + vg;
-    const double fit = sn > 0.0 ? 1.0 - sqrt(fmax(0.0, loss)) / sqrt(sn) : 1.0;
-    ctl->loss = loss;
-    ctl->fit = fit;
-    ctl->sum_n = sn;
-    ctl->ok = (isfinite(loss) && !sBad) ? 1 : 0;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_commit: make the update's state current if every pass produced finite
-// factors and no earlier in-flight update failed; write the pinned report.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_commit(const StepHeader *h, const Touched *touched,
-                                                uint8_t *cur, int32_t *tlast, Ctl *ctl) {
-  const bool ok = ctl->ok && !ctl->poison;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (ok) {
-    for (int t = i; t < h->n_touched; t += gridDim.x * 256) {
-      const int k = touched[t].slice;
-      cur[k] ^= (uint8_t)1;
-      tlast[k] = (int32_t)h->step;
-    }
-  }
-  if (i == 0) {
-    Report *rep = (Report *)h->report;
-    rep->step = h->step;
-    rep->rows = h->M;
-    rep->K = h->K;
-    rep->committed = ok ? 1 : 0;
-    rep->fit = ctl->fit;
-    rep->loss = ctl->loss;
-    rep->sum_n = ctl->sum_n;
-    if (ok)
-      ctl->gcur ^= 1;
-    else
-      ctl->poison = 1;
-    __threadfence_system();
-    rep->done = 1;
-  }
+  arrive(a, h, chunk, &sflag);
 }
 
 // ---------------------------------------------------------------------------
@@ -750,7 +1241,7 @@ __global__ __launch_bounds__(256) void k_accum_given_u(int J, int R, const int64
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const PassLds L = pass_lds(J, R);
+  const PassLds L = pass_lds(J, R, false);
   float *sX = (float *)(smem + L.oX);
   float *sU = (float *)(smem + L.oU);
   const int XS = L.XS, MB = L.MB;
@@ -778,7 +1269,7 @@ __global__ __launch_bounds__(256) void k_accum_given_u(int J, int R, const int64
     __syncthreads();
     accum_block<RW, JW>(sX, sU, XS, m, J, R, dY, dD);
   }
-  float *Yk = Y + (int64_t)k * R * J;
+  float *Yk = Y + (int64_t)k * y_stride(J, R);
 #pragma unroll
   for (int rr = 0; rr < RW; ++rr) {
     const int r = wv + 4 * rr;
@@ -793,7 +1284,6 @@ __global__ __launch_bounds__(256) void k_accum_given_u(int J, int R, const int64
     const int q = tid + 256 * i;
     if (q < R * R) D[(int64_t)k * R * R + q] = dD[i];
   }
-  // block reduction of dn (fixed order)
   __shared__ double red[kWaves];
   dn = wave_sum(dn);
   if (lane == 0) red[wv] = dn;
@@ -827,9 +1317,9 @@ __global__ void k_export_state(int J, int R, int K, int64_t step, double lambda,
   if (k >= K) return;
   const int b = cur[k];
   const double s = pow(lambda, (double)(step - tlast[k]));
-  const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R;
+  const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R, YS = y_stride(J, R);
   for (int e = threadIdx.x; e < RJ; e += 256)
-    Yo[k * RJ + e] = s * (double)Y[((int64_t)b * K_cap + k) * RJ + e];
+    Yo[k * RJ + e] = s * (double)Y[((int64_t)b * K_cap + k) * YS + e];
   for (int e = threadIdx.x; e < RR; e += 256)
     Do[k * RR + e] = s * (double)D[((int64_t)b * K_cap + k) * RR + e];
   if (threadIdx.x == 0) no[k] = s * n[(int64_t)b * K_cap + k];
@@ -841,8 +1331,8 @@ __global__ void k_gather_state(int J, int R, int K, const float *Y, const float 
   const int k = blockIdx.x;
   if (k >= K) return;
   const int b = cur[k];
-  const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R;
-  for (int e = threadIdx.x; e < RJ; e += 256) Yo[k * RJ + e] = Y[((int64_t)b * K_cap + k) * RJ + e];
+  const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R, YS = y_stride(J, R);
+  for (int e = threadIdx.x; e < RJ; e += 256) Yo[k * RJ + e] = Y[((int64_t)b * K_cap + k) * YS + e];
   for (int e = threadIdx.x; e < RR; e += 256) Do[k * RR + e] = D[((int64_t)b * K_cap + k) * RR + e];
   if (threadIdx.x == 0) no[k] = n[(int64_t)b * K_cap + k];
 }
@@ -853,34 +1343,91 @@ __global__ void k_gather_state(int J, int R, int K, const float *Y, const float 
 static inline int rw_of(int R) { return (R + 3) / 4; }
 static inline int jw_of(int J) { return (J + 63) / 64; }
 
-// Kernels whose dynamic LDS exceeds 64 KB must opt in once.
+// Kernels whose dynamic LDS exceeds 64 KB must opt in.
 template <typename F>
 static int allow_lds(F *fn, size_t bytes) {
   if (bytes <= 65536) return 0;
   return (int)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+static inline int ept_of(int J, int R) {
+  const int e = (R * J + 63) / 64;
+  if (e <= 4) return 4;
+  if (e <= 8) return 8;
+  if (e <= 16) return 16;
+  if (e <= 24) return 24;
+  return 32;
+}
+
+static inline int dq_of(int R) {
+  const int q = (R * R + 63) / 64;
+  if (q <= 1) return 1;
+  if (q <= 2) return 2;
+  if (q <= 4) return 4;
+  if (q <= 8) return 8;
+  return 16;
+}
+
+int pass_variant(int J, int R) {
+  if (J <= 128 && R * J <= 2048 && wave_lds(J, R).bytes <= 150 * 1024) return kPassWave;
+  return kPassBlock;
+}
+
+int pass_chunk(int variant, int K) {
+  int ch;
+  if (variant == kPassWave) {
+    // one slice per wave while that leaves >= ~2 workgroups per CU; more otherwise
+    const int per = (K + 8 * 512 - 1) / (8 * 512);
+    ch = 8 * (per < 1 ? 1 : per);
+  } else {
+    ch = (K + 511) / 512;
+    if (ch < 1) ch = 1;
+  }
+  while ((K + ch - 1) / ch > kMaxChunks) ++ch;
+  return ch;
+}
+
+template <int EPT, int DQ>
+static int launch_wave_t(const PassArgs &a, int n_chunks, hipStream_t s) {
+  const WaveLds L = wave_lds(a.J, a.R);
+  if (int e = allow_lds(k_pass_wave<EPT, DQ>, L.bytes)) return e;
+  hipLaunchKernelGGL((k_pass_wave<EPT, DQ>), dim3(n_chunks), dim3(512), L.bytes, s, a);
+  return (int)hipGetLastError();
+}
+
 template <int RW, int JW>
-static int launch_pass_t(const PassArgs &a, int n_chunks, hipStream_t s) {
+static int launch_block_t(const PassArgs &a, int n_chunks, hipStream_t s) {
   const PassLds L = pass_lds(a.J, a.R);
-  if (int e = allow_lds(k_pass<RW, JW>, L.bytes)) return e;
-  hipLaunchKernelGGL((k_pass<RW, JW>), dim3(n_chunks), dim3(256), L.bytes, s, a);
+  if (int e = allow_lds(k_pass_block<RW, JW>, L.bytes)) return e;
+  hipLaunchKernelGGL((k_pass_block<RW, JW>), dim3(n_chunks), dim3(256), L.bytes, s, a);
   return (int)hipGetLastError();
 }
 
 template <int RW, int JW>
 static int launch_accum_t(int J, int R, int K, const int64_t *rp, const float *X, const float *U,
                           float *Y, float *D, double *n, hipStream_t s) {
-  const PassLds L = pass_lds(J, R);
+  const PassLds L = pass_lds(J, R, false);
   if (int e = allow_lds(k_accum_given_u<RW, JW>, L.bytes)) return e;
   hipLaunchKernelGGL((k_accum_given_u<RW, JW>), dim3(K), dim3(256), L.bytes, s, J, R, rp, X, U, Y, D, n);
   return (int)hipGetLastError();
 }
 
-int launch_pass(const PassArgs &a, int n_chunks, hipStream_t s) {
+int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s) {
   if (n_chunks <= 0) return 0;
+  if (variant == kPassWave) {
+    switch (ept_of(a.J, a.R) * 32 + dq_of(a.R)) {
+#define C(E, Q) case E * 32 + Q: return launch_wave_t<E, Q>(a, n_chunks, s);
+      C(4, 1) C(4, 2) C(4, 4) C(4, 8) C(4, 16)
+      C(8, 1) C(8, 2) C(8, 4) C(8, 8) C(8, 16)
+      C(16, 1) C(16, 2) C(16, 4) C(16, 8) C(16, 16)
+      C(24, 1) C(24, 2) C(24, 4) C(24, 8) C(24, 16)
+      C(32, 1) C(32, 2) C(32, 4) C(32, 8) C(32, 16)
+#undef C
+      default: return (int)hipErrorInvalidValue;
+    }
+  }
   switch (rw_of(a.R) * 8 + jw_of(a.J)) {
-#define C(RW, JW) case RW * 8 + JW: return launch_pass_t<RW, JW>(a, n_chunks, s);
+#define C(RW, JW) case RW * 8 + JW: return launch_block_t<RW, JW>(a, n_chunks, s);
     C(1, 1) C(1, 2) C(1, 3) C(1, 4) C(2, 1) C(2, 2) C(2, 3) C(2, 4)
     C(3, 1) C(3, 2) C(3, 3) C(3, 4) C(4, 1) C(4, 2) C(4, 3) C(4, 4)
     C(5, 1) C(5, 2) C(5, 3) C(5, 4) C(6, 1) C(6, 2) C(6, 3) C(6, 4)
@@ -888,6 +1435,13 @@ int launch_pass(const PassArgs &a, int n_chunks, hipStream_t s) {
 #undef C
     default: return (int)hipErrorInvalidValue;
   }
+}
+
+int launch_finish(const PassArgs &a, int mode, hipStream_t s) {
+  const size_t bytes = finish_launch_lds(a.J, a.R);
+  if (int e = allow_lds(k_finish, bytes)) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), bytes, s, a, mode);
+  return (int)hipGetLastError();
 }
 
 int launch_accum_given_u(int J, int R, int K, const int64_t *rp, const float *X, const float *U,
@@ -902,30 +1456,6 @@ int launch_accum_given_u(int J, int R, int K, const int64_t *rp, const float *X,
 #undef C
     default: return (int)hipErrorInvalidValue;
   }
-}
-
-int launch_reduce(const double *partials, double *gpart, const StepHeader *hdr, int plen,
-                  int n_chunks, int n_rgroups, int chunks_per_rgroup, hipStream_t s) {
-  (void)n_chunks;
-  (void)chunks_per_rgroup;
-  dim3 grid((plen + 255) / 256, n_rgroups);
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, partials, gpart, hdr, plen);
-  return (int)hipGetLastError();
-}
-
-int launch_solve(int J, int R, const double *gpart, int n_rgroups, char *vb, int64_t vb_stride,
-                 Ctl *ctl, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(256), 0, s, J, R, gpart, n_rgroups, vb, vb_stride, ctl, mode);
-  return (int)hipGetLastError();
-}
-
-int launch_commit(const StepHeader *hdr, const Touched *touched, uint8_t *cur, int32_t *tlast,
-                  Ctl *ctl, int n_touched, hipStream_t s) {
-  int blocks = (n_touched + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_commit, dim3(blocks), dim3(256), 0, s, hdr, touched, cur, tlast, ctl);
-  return (int)hipGetLastError();
 }
 
 int launch_v_from_f32(int J, int R, const float *V, char *vb_committed, hipStream_t s) {
