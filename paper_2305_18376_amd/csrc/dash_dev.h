@@ -128,7 +128,7 @@ enum { kPassWave = 0, kPassBlock = 1 };
 // Choose the sweep variant for (J, R); returns kPassWave or kPassBlock.
 int pass_variant(int J, int R);
 // Slices per workgroup for a variant and slice count.
-int pass_chunk(int variant, int K);
+int pass_chunk(int variant, int K, int n_cu);
 int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s);
 // Final phase of a pass (one workgroup): mode 0 after an update sweep (Lemma 3,
 // next-pass operands, commit on the last pass), 1 builds the committed V bundle

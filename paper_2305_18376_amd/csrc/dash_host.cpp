@@ -69,6 +69,7 @@ struct dash_ctx {
   char *dstep = nullptr;
   size_t off_gptr = 0, off_groups = 0, step_bytes = 0;
   int variant = kPassWave;
+  int n_cu = 0;   // compute units of the device
   // pinned
   char *hstage[kStages] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t stage_ev[kStages] = {nullptr, nullptr, nullptr, nullptr};
@@ -137,7 +138,7 @@ int choose_chunk(const dash_ctx *c, int K) {
     while ((K + ch - 1) / ch > kMaxChunks) ++ch;
     return ch;
   }
-  return pass_chunk(c->variant, K);
+  return pass_chunk(c->variant, K, c->n_cu);
 }
 
 StepHeader *stage_header(char *blk) { return (StepHeader *)blk; }
@@ -382,6 +383,8 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
     return s;
   };
   if (hipSetDevice(cfg->device) != hipSuccess) return bail(DASH_E_DEVICE);
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess)
+    return bail(DASH_E_DEVICE);
   if (cfg->stream) {
     c->stream = (hipStream_t)cfg->stream;
   } else {

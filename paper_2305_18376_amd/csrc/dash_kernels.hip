@@ -25,18 +25,16 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Sum over c in [c0, c1) of src[c * stride + e], in ascending c, with the loads
-// issued in batches of 8 so their latencies overlap.
+// issued in batches of 16 so their latencies overlap (missing terms add 0).
 __device__ __forceinline__ double ordered_sum(const double *src, int64_t stride, int e, int c0, int c1) {
   double s = 0.0;
-  int c = c0;
-  for (; c + 8 <= c1; c += 8) {
-    double v[8];
+  for (int c = c0; c < c1; c += 16) {
+    double v[16];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = src[(int64_t)(c + i) * stride + e];
+    for (int i = 0; i < 16; ++i) v[i] = (c + i < c1) ? src[(int64_t)(c + i) * stride + e] : 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s += v[i];
+    for (int i = 0; i < 16; ++i) s += v[i];
   }
-  for (; c < c1; ++c) s += src[(int64_t)c * stride + e];
   return s;
 }
 
@@ -169,6 +167,57 @@ __device__ void wave_chol_apply(const double *L, double *x, int n) {
   }
 }
 
+// Gauss-Jordan elimination without pivoting on an SPD system held by one wave
+// in LDS: M is n x (n + m) row-major (the last m columns are right-hand sides),
+// lane i < n owns row i.  Pivot p is the Schur-complement diagonal, i.e. the
+// square of the Cholesky diagonal entry, so the acceptance rule (pivot above
+// kPivotRel times the largest diagonal entry of the original matrix) is the
+// oracle's Cholesky rule.  On success row i ends as (d_i e_i | d_i X_i):
+// the solution is X = M[:, n:] / d.  Returns false uniformly otherwise.
+__device__ bool wave_gj(double *M, int n, int m) {
+  const int lane = threadIdx.x & 63;
+  const int ld = n + m;
+  const double dmax = wave_max(lane < n ? M[lane * ld + lane] : 0.0);
+  if (!(dmax > 0.0)) return false;
+  const double thr = kPivotRel * dmax;
+  for (int p = 0; p < n; ++p) {
+    wave_sync();
+    const double piv = M[p * ld + p];
+    if (!(piv > thr)) return false;
+    if (lane < n && lane != p) {
+      const double f = M[lane * ld + p] / piv;
+      double *row = M + lane * ld;
+      const double *prow = M + p * ld;
+#pragma unroll 4
+      for (int c = p + 1; c < ld; ++c) row[c] -= f * prow[c];
+      row[p] = 0.0;
+    }
+  }
+  wave_sync();
+  return true;
+}
+
+// Ainv = A^{-1} for SPD A (n x n, n <= 32, LDS) by one wave: Gauss-Jordan on
+// [A | I] in `work` (n x 2n doubles).  Same acceptance rule as wave_gj.
+__device__ bool wave_spd_inverse(const double *A, double *Ainv, int n, double *work) {
+  const int lane = threadIdx.x & 63;
+  const int ld = 2 * n;
+  for (int e = lane; e < n * ld; e += 64) {
+    const int r = e / ld, c = e - r * ld;
+    work[e] = (c < n) ? A[r * n + c] : ((c - n == r) ? 1.0 : 0.0);
+  }
+  wave_sync();
+  const bool ok = wave_gj(work, n, n);
+  if (ok) {
+    for (int e = lane; e < n * n; e += 64) {
+      const int r = e / n, c = e - r * n;
+      Ainv[e] = work[r * ld + n + c] / work[r * ld + r];
+    }
+  }
+  wave_sync();
+  return ok;
+}
+
 // Symmetric eigendecomposition A = Z diag(A_out) Z^T of an n x n matrix
 // (n <= 64) by one wave: cyclic parallel Jacobi (Golub & Van Loan, Sec. 8.5,
 // "parallel ordering"), disjoint rotation pairs per round from the round-robin
@@ -266,58 +315,120 @@ __device__ void wave_pinv_apply(double *M, double *x, int n, double *Z, double *
   wave_sync();
 }
 
+// Gauss-Jordan elimination without pivoting of an SPD n x n system held by
+// one wave in registers (n <= RM): lane i < n owns row i of A in m[] (m[c] =
+// A_ic, zero for c >= n; zero rows on lanes >= n) and the i-th entries of NB
+// right-hand sides in b[].  The system is padded to RM x RM with a decoupled
+// diagonal block, so the elimination is straight-line code over compile-time
+// indices; pivot rows are broadcast with readlane.  Pivot p < n is the Schur
+// complement diagonal -- the square of the Cholesky diagonal entry -- and is
+// accepted when above kPivotRel times the largest diagonal entry of A: the
+// oracle's Cholesky acceptance rule.  On success d holds lane i's final pivot
+// and x_i = b[.] / d; returns false, uniformly across the wave, otherwise.
+template <int RM, int NB>
+__device__ __forceinline__ bool wave_gj_reg(double (&m)[RM], double (&b)[NB], double &d, int n) {
+  const int lane = threadIdx.x & 63;
+  double dmax = 0.0;
+#pragma unroll
+  for (int p = 0; p < RM; ++p) {
+    const double v = readlane_d(m[p], p);
+    dmax = (p < n) ? fmax(dmax, v) : dmax;
+  }
+  if (!(dmax > 0.0)) return false;
+  const double thr = kPivotRel * dmax;
+#pragma unroll
+  for (int c = 0; c < RM; ++c) m[c] = (lane == c && c >= n) ? dmax : m[c];
+  d = 1.0;
+#pragma unroll
+  for (int p = 0; p < RM; ++p) {
+    const double piv = readlane_d(m[p], p);
+    if (p < n && !(piv > thr)) return false;
+    d = (lane == p) ? piv : d;
+    const double f = (lane != p) ? m[p] / piv : 0.0;
+#pragma unroll
+    for (int c = p + 1; c < RM; ++c) m[c] = fma(-f, readlane_d(m[c], p), m[c]);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) b[k] = fma(-f, readlane_d(b[k], p), b[k]);
+  }
+  return true;
+}
+
+// Ainv = A^{-1} for SPD A (n x n, n <= RM, LDS, row-major) by the first four
+// waves of the block (one per SIMD): wave w eliminates its own copy of A with
+// the unit vectors e_{w*NB} .. e_{w*NB+NB-1} as right-hand sides, so the
+// columns of the inverse come out in parallel.  Every wave runs the same
+// elimination, hence takes the same acceptance decision; the return value is
+// that decision on waves 0..3 and true elsewhere (the caller combines it
+// through LDS and synchronises the block before reading Ainv).
+template <int RM>
+__device__ bool block_spd_inverse(const double *A, double *Ainv, int n) {
+  constexpr int NB = RM / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv >= 4) return true;
+  double m[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) m[c] = (lane < n && c < n) ? A[lane * n + c] : 0.0;
+  double rhs[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) rhs[k] = (lane == wv * NB + k) ? 1.0 : 0.0;
+  double d;
+  if (!wave_gj_reg<RM, NB>(m, rhs, d, n)) return false;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int col = wv * NB + k;
+    if (lane < n && col < n) Ainv[lane * n + col] = rhs[k] / d;
+  }
+  return true;
+}
+
 // ---------------------------------------------------------------------------
-// Final phase of a pass, run by the last workgroup to arrive (any block size).
+// Final phase of a pass: one workgroup of 1024 threads.
 //   mode 0: F, G, n from the group partials; Lemma 3: V = F G^{-1} into the
 //           spare bundle with V^T V, B = (V^T V)^{-1}, P = V B, V^T; loss and
 //           fit; on the last pass the commit (switch of touched slices and of
 //           the W / V buffers) and the pinned report.
 //   mode 1: build the committed bundle from its V64 (no reduction, no fit).
 //   mode 2: loss and fit of the committed V with F, G from the partials.
+// The R x R inverses come from block_spd_inverse (FP64); when a pivot fails
+// the acceptance rule the eigen pseudo-inverse replaces it, as in the oracle.
 // ---------------------------------------------------------------------------
+constexpr int kFinishThreads = 512;   // 2 waves per SIMD: up to 256 VGPRs for the R x R eliminations
+constexpr int kFinishRed = 48;        // doubles of the reduction scratch
+constexpr int kFinishScr = 1024;      // doubles of the split-product scratch (>= R^2)
+
 __host__ __device__ inline size_t finish_lds_bytes(int J, int R) {
-  return (size_t)(R * J + 5 * R * R + 96) * 8 + 68 * 4;
+  return (size_t)(R * J + 5 * R * R + 64 + kFinishRed + kFinishScr) * 8 + 68 * 4;
 }
 // with a copy of V (J x R, FP64) kept in LDS as well
 __host__ __device__ inline size_t finish_lds_bytes_v(int J, int R) {
   return finish_lds_bytes(J, R) + (size_t)J * R * 8;
 }
 
-// Solve L L^T x = b in place for one right-hand side held by the calling thread
-// (x in LDS or global memory, stride `inc`), L from wave_cholesky.
-__device__ __forceinline__ void chol_solve_thread(const double *L, double *x, int inc, int n) {
-  for (int p = 0; p < n; ++p) {
-    double s = x[p * inc];
-    for (int q = 0; q < p; ++q) s -= L[p * n + q] * x[q * inc];
-    x[p * inc] = s / L[p * n + p];
-  }
-  for (int p = n - 1; p >= 0; --p) {
-    double s = x[p * inc];
-    for (int q = p + 1; q < n; ++q) s -= L[q * n + p] * x[q * inc];
-    x[p * inc] = s / L[p * n + p];
-  }
-}
-
-// pinv(A) of a symmetric PSD n x n matrix into Out (LDS), the whole block
-// taking part; A is destroyed (wave 0 diagonalises it, eigenvectors in Z).
-__device__ void block_pinv(double *A, double *Z, double *Out, int n, double *rot, int *pair) {
+// out = pinv(src) for a symmetric PSD n x n matrix (LDS), the whole block
+// taking part: wave 0 diagonalises a copy (work, eigenvectors in Z), then every
+// thread forms entries of Z diag(1/lambda_kept) Z^T with the relative cutoff.
+__device__ void block_pinv_of(const double *src, double *out, double *work, double *Z, int n,
+                              double *rot, int *pair) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  if ((tid >> 6) == 0) wave_jacobi(A, Z, n, rot, pair);
+  for (int q = tid; q < n * n; q += nt) work[q] = src[q];
+  __syncthreads();
+  if ((tid >> 6) == 0) wave_jacobi(work, Z, n, rot, pair);
   __syncthreads();
   double top = 0.0;
-  for (int i = 0; i < n; ++i) top = fmax(top, fabs(A[i * n + i]));
+  for (int i = 0; i < n; ++i) top = fmax(top, fabs(work[i * n + i]));
   for (int q = tid; q < n * n; q += nt) {
     const int r = q / n, c = q - r * n;
     double acc = 0.0;
     for (int i = 0; i < n; ++i) {
-      const double li = A[i * n + i];
+      const double li = work[i * n + i];
       if (top > 0.0 && li > kEigCutoff * top) acc += Z[r * n + i] * Z[c * n + i] / li;
     }
-    Out[q] = acc;
+    out[q] = acc;
   }
   __syncthreads();
 }
 
+template <int RM>
 __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroups, int mode,
                             unsigned char *smem, size_t lds_avail) {
   const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
@@ -325,14 +436,15 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   const int plen = partial_len(J, R);
   double *sF = (double *)smem;   // F^T, R x J
   double *sG = sF + RJ;
-  double *sL = sG + RR;
-  double *sB = sL + RR;
+  double *sGi = sG + RR;         // G^{-1}
+  double *sB = sGi + RR;         // (V^T V)^{-1}
   double *sVtV = sB + RR;
-  double *sZ = sVtV + RR;
+  double *sZ = sVtV + RR;        // pseudo-inverse scratch (and sW below)
   double *sRot = sZ + RR;        // 64
-  double *sRed = sRot + 64;      // 32
-  int *sPair = (int *)(sRed + 32);
-  int *sFlag = sPair + 64;       // [0]: Cholesky ok, [1]: non-finite seen
+  double *sRed = sRot + 64;      // kFinishRed
+  double *sScr = sRed + kFinishRed;   // kFinishScr: split products
+  int *sPair = (int *)(sScr + kFinishScr);
+  int *sFlag = sPair + 64;       // [0], [2]: inverse ok, [1]: non-finite seen
   // V (J x R) in LDS when the workgroup has room, else worked on in V64 directly
   double *sVl = (double *)(smem + finish_lds_bytes(J, R));
   const bool v_lds = lds_avail >= finish_lds_bytes_v(J, R);
@@ -340,104 +452,84 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   const int out = (mode == 0) ? 1 - gcur : gcur;
   const VBundleView vo = vb_view(a.vb + (int64_t)out * a.vb_stride, J, R);
   double *Vw = v_lds ? sVl : vo.V64;   // V, row-major J x R
-  if (tid == 0) sFlag[1] = 0;
+  if (tid == 0) {
+    sFlag[0] = 1;
+    sFlag[1] = 0;
+    sFlag[2] = 1;
+  }
   double sum_n = 0.0;
   if (mode != 1) {
     for (int e = tid; e < plen; e += nt) {
       const double s = ordered_sum(a.gpart, plen, e, 0, n_rgroups);
       if (e < RJ + RR) sF[e] = s;   // sF and sG are contiguous
-      else sRed[31] = s;
+      else sRed[kFinishRed - 1] = s;
     }
   }
   __syncthreads();
-  if (mode != 1) sum_n = sRed[31];
+  if (mode != 1) sum_n = sRed[kFinishRed - 1];
   double vf = 0.0;
   if (mode == 0) {
-    // Lemma 3: V = F G^{-1}, i.e. G v_j^T = f_j^T for every row j
-    if (wv == 0) {
-      for (int q = lane; q < RR; q += 64) sL[q] = sG[q];
-      wave_sync();
-      const bool okc = wave_cholesky(sL, R);
-      if (lane == 0) sFlag[0] = okc ? 1 : 0;
-    }
+    // Lemma 3: V = F G^{-1}
+    if (!block_spd_inverse<RM>(sG, sGi, R) && lane == 0) sFlag[0] = 0;
     __syncthreads();
-    const bool chol = sFlag[0] != 0;
-    if (!chol) {
-      for (int q = tid; q < RR; q += nt) sL[q] = sG[q];
-      __syncthreads();
-      block_pinv(sL, sZ, sB, R, sRot, sPair);   // sB = pinv(G)
+    if (!sFlag[0]) block_pinv_of(sG, sGi, sB, sZ, R, sRot, sPair);
+    bool bad = false;
+    for (int e = tid; e < J * R; e += nt) {
+      const int j = e / R, r = e - j * R;
+      double x = 0.0;
+#pragma unroll 4
+      for (int c = 0; c < R; ++c) x = fma(sF[c * J + j], sGi[c * R + r], x);
+      Vw[e] = x;
+      if (v_lds) vo.V64[e] = x;
+      vf = fma(x, sF[r * J + j], vf);
+      bad |= !isfinite(x);
     }
-    for (int j = tid; j < J; j += nt) {
-      double *v = Vw + (size_t)j * R;
-      if (chol) {
-        for (int r = 0; r < R; ++r) v[r] = sF[r * J + j];
-        chol_solve_thread(sL, v, 1, R);
-      } else {
-        for (int r = 0; r < R; ++r) {
-          double acc = 0.0;
-          for (int c = 0; c < R; ++c) acc += sB[r * R + c] * sF[c * J + j];
-          v[r] = acc;
-        }
-      }
-      for (int r = 0; r < R; ++r) {
-        const double x = v[r];
-        if (v_lds) vo.V64[(int64_t)j * R + r] = x;
-        vf += x * sF[r * J + j];
-        if (!isfinite(x)) sFlag[1] = 1;
-      }
-    }
+    if (bad) sFlag[1] = 1;
   } else {
     for (int e = tid; e < J * R; e += nt) {
       const double x = vo.V64[e];
       if (v_lds) sVl[e] = x;
       if (mode == 2) {
         const int j = e / R, r = e - j * R;
-        vf += x * sF[r * J + j];
+        vf = fma(x, sF[r * J + j], vf);
       }
     }
   }
-  vf = wave_sum(vf);
-  if (lane == 0) sRed[wv] = vf;
   __syncthreads();
-  double VF = 0.0;
-  for (int w = 0; w < nwv; ++w) VF += sRed[w];
 
   if (mode != 2) {
     // next pass operands: V^T V, B = (V^T V)^{-1}, P = V B, V^T in float32
-    for (int q = tid; q < RR; q += nt) {
+    // V^T V with S threads per entry over interleaved rows j, the S partial
+    // sums added in a fixed order
+    const int S = max(1, min(8, kFinishScr / RR));
+    for (int t = tid; t < RR * S; t += nt) {
+      const int q = t / S, part = t - q * S;
       const int r = q / R, c = q - r * R;
       double acc = 0.0;
-      for (int j = 0; j < J; ++j) acc += Vw[(size_t)j * R + r] * Vw[(size_t)j * R + c];
-      sVtV[q] = acc;
-      vo.VtV[q] = acc;
+#pragma unroll 4
+      for (int j = part; j < J; j += S) acc = fma(Vw[(size_t)j * R + r], Vw[(size_t)j * R + c], acc);
+      sScr[t] = acc;
     }
     for (int e = tid; e < RJ; e += nt) {
       const int r = e / J, j = e - r * J;
       vo.Vt32[e] = (float)Vw[(size_t)j * R + r];
     }
     __syncthreads();
-    if (wv == 0) {
-      for (int q = lane; q < RR; q += 64) sL[q] = sVtV[q];
-      wave_sync();
-      const bool okc = wave_cholesky(sL, R);
-      if (lane == 0) sFlag[0] = okc ? 1 : 0;
+    for (int q = tid; q < RR; q += nt) {
+      double acc = 0.0;
+      for (int part = 0; part < S; ++part) acc += sScr[q * S + part];
+      sVtV[q] = acc;
+      vo.VtV[q] = acc;
     }
     __syncthreads();
-    if (sFlag[0]) {
-      for (int col = tid; col < R; col += nt) {
-        for (int p = 0; p < R; ++p) sB[p * R + col] = (p == col) ? 1.0 : 0.0;
-        chol_solve_thread(sL, sB + col, R, R);
-      }
-      __syncthreads();
-    } else {
-      for (int q = tid; q < RR; q += nt) sL[q] = sVtV[q];
-      __syncthreads();
-      block_pinv(sL, sZ, sB, R, sRot, sPair);
-    }
+    if (!block_spd_inverse<RM>(sVtV, sB, R) && lane == 0) sFlag[2] = 0;
+    __syncthreads();
+    if (!sFlag[2]) block_pinv_of(sVtV, sB, sGi, sZ, R, sRot, sPair);
     for (int e = tid; e < J * R; e += nt) {
       const int j = e / R, c = e - j * R;
       double acc = 0.0;
-      for (int r = 0; r < R; ++r) acc += Vw[(size_t)j * R + r] * sB[r * R + c];
+#pragma unroll 4
+      for (int r = 0; r < R; ++r) acc = fma(Vw[(size_t)j * R + r], sB[r * R + c], acc);
       vo.P32[e] = (float)acc;
     }
   } else {
@@ -445,10 +537,22 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
     __syncthreads();
   }
   if (mode == 1) return;
-  __syncthreads();
+  // loss = sum n - 2 <V, F> + <V^T V, G>
   double vg = 0.0;
-  for (int q = 0; q < RR; ++q) vg += sVtV[q] * sG[q];
-  const double loss = sum_n - 2.0 * VF + vg;
+  for (int q = tid; q < RR; q += nt) vg = fma(sVtV[q], sG[q], vg);
+  vf = wave_sum(vf);
+  vg = wave_sum(vg);
+  if (lane == 0) {
+    sRed[wv] = vf;
+    sRed[16 + wv] = vg;
+  }
+  __syncthreads();
+  double VF = 0.0, VG = 0.0;
+  for (int w = 0; w < nwv; ++w) {
+    VF += sRed[w];
+    VG += sRed[16 + w];
+  }
+  const double loss = sum_n - 2.0 * VF + VG;
   const double fit = sum_n > 0.0 ? 1.0 - sqrt(fmax(0.0, loss)) / sqrt(sum_n) : 1.0;
   const bool ok = isfinite(loss) && !sFlag[1];
   if (tid == 0) {
@@ -512,10 +616,11 @@ __host__ __device__ inline size_t finish_launch_lds(int J, int R) {
   return with_v <= 150 * 1024 ? with_v : finish_lds_bytes(J, R);
 }
 
-__global__ __launch_bounds__(1024) void k_finish(PassArgs a, int mode) {
+template <int RM>
+__global__ __launch_bounds__(kFinishThreads) void k_finish(PassArgs a, int mode) {
   extern __shared__ __align__(16) unsigned char smem[];
   const StepHeader *h = a.hdr;
-  finish_pass(a, h, mode == 1 ? 0 : h->n_rgroups, mode, smem, finish_launch_lds(a.J, a.R));
+  finish_pass<RM>(a, h, mode == 1 ? 0 : h->n_rgroups, mode, smem, finish_launch_lds(a.J, a.R));
 }
 
 // ---------------------------------------------------------------------------
@@ -543,11 +648,21 @@ struct WaveLds {
   size_t oP, oVt, oVtV, oWave, wave_bytes, oSmall, oX, oU, oM, oZ, oRot, oTmp, oPair, oProd, oDcur, bytes;
 };
 
+// padded rank of the wave variant's register tiles (R <= 16)
+__host__ __device__ inline int wave_rc(int R) { return R <= 8 ? 8 : (R <= 11 ? 12 : 16); }
+
+// bytes of one wave's slot in the end-of-chunk combine: F^T (float, padded)
+// then G and n (double)
+__host__ __device__ inline size_t wave_slot_bytes(int J, int R) {
+  return align_up(align_up((size_t)y_stride(J, R) * 4, 16) + (size_t)(R * R + 1) * 8, 16);
+}
+
 __host__ __device__ inline WaveLds wave_lds(int J, int R) {
   WaveLds L;
+  const int RC = wave_rc(R);
   L.XS = J | 1;
   size_t o = 0;
-  L.oP = o;   o += (size_t)J * R * 4;
+  L.oP = o;   o += (size_t)J * RC * 4;   // P = V (V^T V)^{-1}, J x RC, zero-padded columns
   L.oVt = o;  o += (size_t)y_stride(J, R) * 4;
   o = align_up(o, 8);
   L.oVtV = o; o += (size_t)R * R * 8;
@@ -556,17 +671,17 @@ __host__ __device__ inline WaveLds wave_lds(int J, int R) {
   // per-wave region: small vectors, then a union of the row block, the
   // products of diag(Y_k V), and the solve scratch
   size_t w = 0;
-  L.oSmall = w; w += (size_t)(R + 1) * 8 * 3 + (size_t)R * 4;   // sW, sC, sC2 (f64, R+1), sWinv (f32)
+  L.oSmall = w; w += (size_t)(R + 1) * 8 * 3 + (size_t)RC * 4;   // sW, sC, sC2 (f64, R+1), sWinv (f32, RC)
   w = align_up(w, 16);
   const size_t blk = w;
   L.oX = blk;
   L.oU = blk + (size_t)kWaveRows * L.XS * 4;
-  const size_t rows_end = L.oU + (size_t)kWaveRows * (R + 1) * 4;
+  const size_t rows_end = L.oU + (size_t)kWaveRows * RC * 4;
   L.oProd = blk;
   const size_t prod_end = blk + (size_t)y_stride(J, R) * 4;
   L.oDcur = blk;
   L.oM = blk + align_up((size_t)R * R * 4, 16);
-  L.oZ = L.oM + (size_t)R * R * 8;
+  L.oZ = L.oM + (size_t)R * (R + 1) * 8;
   L.oRot = L.oZ + (size_t)R * R * 8;
   L.oTmp = L.oRot + 64 * 8;
   L.oPair = L.oTmp + 64 * 8;
@@ -575,14 +690,14 @@ __host__ __device__ inline WaveLds wave_lds(int J, int R) {
   if (prod_end > end) end = prod_end;
   L.wave_bytes = align_up(end, 16);
   o += L.wave_bytes * kWaveWarps;
-  const size_t comb = (size_t)partial_len(J, R) * 8;
+  const size_t comb = wave_slot_bytes(J, R) * kWaveWarps;
   L.bytes = align_up(o > comb ? o : comb, 16);
   return L;
 }
 
 template <int EPT, int DQ>
 __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
-  constexpr int RC = DQ == 1 ? 8 : DQ == 2 ? 12 : DQ == 4 ? 16 : DQ == 8 ? 24 : 32;  // R <= RC
+  constexpr int RC = DQ == 1 ? 8 : DQ == 2 ? 12 : 16;  // == wave_rc(R): R <= RC
   constexpr int RPL = RC / 4;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sflag;
@@ -618,7 +733,10 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
   const float invJ = 1.0f / (float)J;   // e / J below is exact: e < 2^11, J <= 128
   constexpr int NB = kWaveRows * 2;     // staged floats per lane for a 16 x 128 row block
 
-  for (int e = tid; e < J * R; e += 512) sP[e] = vb.P32[e];
+  for (int e = tid; e < J * RC; e += 512) {
+    const int j = e / RC, r = e - j * RC;
+    sP[e] = (r < R) ? vb.P32[j * R + r] : 0.f;
+  }
   for (int e = tid; e < YS; e += 512) sVt[e] = (e < RJ) ? vb.Vt32[e] : 0.f;
   for (int e = tid; e < RR; e += 512) sVtV[e] = vb.VtV[e];
   __syncthreads();
@@ -652,6 +770,9 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
       dold[i] = (q < RR && !is_new) ? Dst[q] : 0.f;
     }
     const double nold = (lane == 0 && !is_new) ? a.n[(int64_t)b * a.K_cap + k] : 0.0;
+    float yo[EPT];   // stored Y_k, in flight while the rows are processed
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) yo[i] = (64 * i < YS && !is_new) ? Yst[lane + 64 * i] : 0.f;
     // groups of slice k: contiguous run inside [g0, g1)
     int gb = -1, ge = -1;
     for (int base = g0; base < g1; base += 64) {
@@ -671,7 +792,7 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
     {
       if (lane < R) sW[lane] = w;
       const double top = wave_max(fabs(w));
-      if (lane < R) sWinv[lane] = (fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
+      if (lane < RC) sWinv[lane] = (lane < R && fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
       if (lane == 0) sC[R] = 0.0;   // weight of the padding elements of Y_k
     }
     wave_sync();
@@ -701,76 +822,69 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
           const int tot = m * J;
           const float *src = gsrc + (int64_t)r0 * J;
           wave_sync();  // the previous block's readers are done
+          // stage the block (m x J) in LDS; the loads are clamped in bounds and
+          // only the stores are predicated, so every batch is one round trip
           for (int i0 = 0; i0 < NB; i0 += 8) {
             if (64 * i0 >= tot) break;
             float buf[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const int e = lane + 64 * (i0 + i);
-              buf[i] = (e < tot) ? src[e] : 0.f;
+              const float v = src[min(e, tot - 1)];
+              buf[i] = (e < tot) ? v : 0.f;
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
               const int e = lane + 64 * (i0 + i);
-              if (e < tot) {
-                const int row = (int)(((float)e + 0.5f) * invJ);
-                sX[row * XS + (e - row * J)] = buf[i];
-                dn += (double)buf[i] * (double)buf[i];
-              }
+              const int row = (int)(((float)e + 0.5f) * invJ);
+              dn = fma((double)buf[i], (double)buf[i], dn);
+              if (e < tot) sX[row * XS + (e - row * J)] = buf[i];
             }
           }
           wave_sync();
           {
-            const int row = lane >> 2, rq = lane & 3;
-            if (row < m) {
-              float t[RPL];
+            // Lemma 1: u = (x P) * (1/w); lane (row, q) owns ranks q*RPL .. q*RPL+RPL-1.
+            // Rows >= m of the block hold stale values whose results are unused.
+            const int row = lane >> 2, rb = (lane & 3) * RPL;
+            float t[RPL];
 #pragma unroll
-              for (int i = 0; i < RPL; ++i) t[i] = 0.f;
-              const float *xr = sX + row * XS;
+            for (int i = 0; i < RPL; ++i) t[i] = 0.f;
+            const float *xr = sX + row * XS;
+            const float *pc = sP + rb;
 #pragma unroll 4
-              for (int j = 0; j < J; ++j) {
-                const float xv = xr[j];
+            for (int j = 0; j < J; ++j) {
+              const float xv = xr[j];
 #pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                  const int r = rq + 4 * i;
-                  if (r < R) t[i] = fmaf(xv, sP[j * R + r], t[i]);
-                }
-              }
+              for (int i = 0; i < RPL; ++i) t[i] = fmaf(xv, pc[j * RC + i], t[i]);
+            }
 #pragma unroll
-              for (int i = 0; i < RPL; ++i) {
-                const int r = rq + 4 * i;
-                if (r < R) {
-                  const float u = t[i] * sWinv[r];
-                  sU[row * (R + 1) + r] = u;
-                  if (a.last_pass) a.U_out[(out_row + r0 + row) * R + r] = u;
-                }
-              }
+            for (int i = 0; i < RPL; ++i) {
+              const float u = t[i] * sWinv[rb + i];
+              sU[row * RC + rb + i] = u;
+              if (a.last_pass && row < m && rb + i < R) a.U_out[(out_row + r0 + row) * R + rb + i] = u;
             }
           }
           wave_sync();
+          // dY += u^T x (lane = column), dD += u^T u (lane = entry), padded ranks are zero
 #pragma unroll 2
           for (int row = 0; row < m; ++row) {
             const float x0 = sX[row * XS + j0], x1 = sX[row * XS + j1];
-            const float *ur = sU + row * (R + 1);
+            const float *ur = sU + row * RC;
 #pragma unroll
             for (int r = 0; r < RC; ++r) {
-              if (r < R) {
-                const float u = ur[r];
-                dy[r][0] = fmaf(u, x0, dy[r][0]);
-                dy[r][1] = fmaf(u, x1, dy[r][1]);
-              }
+              const float u = ur[r];
+              dy[r][0] = fmaf(u, x0, dy[r][0]);
+              dy[r][1] = fmaf(u, x1, dy[r][1]);
             }
           }
 #pragma unroll
           for (int i = 0; i < DQ; ++i) {
-            const int q = lane + 64 * i;
-            if (q < RR) {
-              const int r = q / R, s = q - r * R;
-              float acc = dD[i];
+            const int q = min(lane + 64 * i, RR - 1);
+            const int r = q / R, s = q - r * R;
+            float acc = dD[i];
 #pragma unroll 4
-              for (int row = 0; row < m; ++row) acc = fmaf(sU[row * (R + 1) + r], sU[row * (R + 1) + s], acc);
-              dD[i] = acc;
-            }
+            for (int row = 0; row < m; ++row) acc = fmaf(sU[row * RC + r], sU[row * RC + s], acc);
+            dD[i] = acc;
           }
         }
       }
@@ -798,17 +912,17 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
       yc[i] = 0.f;
       if (64 * i >= YS) continue;   // uniform: the slice has YS / 64 flat blocks
       const int e = lane + 64 * i;
-      const float yo = is_new ? 0.f : Yst[e];
-      yc[i] = touched ? fmaf(s_old_f, yo, sDY[e]) : yo;
+      yc[i] = touched ? fmaf(s_old_f, yo[i], sDY[e]) : yo[i];
       sProd[e] = yc[i] * sVt[e];   // same element as sDY[e]: read before written
     }
     wave_sync();
     // c_r = sum_j Y_k[r][j] V[j][r]: lane r sums row r of the products in FP64
     double cr = 0.0;
-    if (lane < R) {
-      const float *pr = sProd + lane * J;
+    {
+      const float *pr = sProd + min(lane, R - 1) * J;
 #pragma unroll 8
       for (int j = 0; j < J; ++j) cr += (double)pr[j];
+      if (lane >= R) cr = 0.0;
     }
     wave_sync();  // products consumed: the buffer takes the current D_k
     float *sDcur = (float *)(wbase + L.oDcur);
@@ -822,19 +936,20 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
       }
     }
     wave_sync();
-    if (lane < R) {
-      sC[lane] = cr;
-      sC2[lane] = cr;
-    }
     if (a.mode == 0) {
-      // Lemma 2: (V^T V * D_k) w = c, FP64 Cholesky in the wave's LDS
-      for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * (double)sDcur[q];
-      wave_sync();
-      if (wave_cholesky(sM, R)) {
-        wave_chol_apply(sM, sC, R);
+      // Lemma 2: (V^T V * D_k) w = c in FP64, Gauss-Jordan in registers (lane r
+      // holds row r of the system)
+      double m[RC];
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        m[c] = (lane < R && c < R) ? sVtV[lane * R + c] * (double)sDcur[lane * R + c] : 0.0;
+      double rhs[1] = {cr};
+      double dpiv;
+      if (wave_gj_reg<RC, 1>(m, rhs, dpiv, R)) {
+        if (lane < R) sC[lane] = rhs[0] / dpiv;
       } else {
         for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * (double)sDcur[q];
-        if (lane < R) sC[lane] = sC2[lane];
+        if (lane < R) sC[lane] = cr;
         wave_sync();
         wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
       }
@@ -853,11 +968,10 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < DQ; ++i) {
-      const int q = lane + 64 * i;
-      if (q < RR) {
-        const int r = q / R, s = q - r * R;
-        gacc[i] += sigma * sC[r] * sC[s] * (double)dD[i];
-      }
+      const int q = min(lane + 64 * i, RR - 1);
+      const int r = q / R, s = q - r * R;
+      const double gv = sigma * sC[r] * sC[s] * (double)dD[i];
+      gacc[i] += (lane + 64 * i < RR) ? gv : 0.0;
     }
     if (lane == 0) {
       const double ncur = s_old * nold + dn;
@@ -883,28 +997,42 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
     }
   }
 
-  // combine the waves' accumulators in wave order, write the chunk partial
+  // combine the waves' accumulators: every wave parks its sums in a slot of
+  // its own, then each thread adds the slots of its elements in wave order
   __syncthreads();
-  double *sComb = (double *)smem;
   const int plen = partial_len(J, R);
-  for (int w = 0; w < kWaveWarps; ++w) {
-    if (wv == w) {
+  const size_t slot = wave_slot_bytes(J, R);
+  {
+    unsigned char *mine = smem + (size_t)wv * slot;
+    float *cf = (float *)mine;
+    double *cg = (double *)(mine + align_up((size_t)YS * 4, 16));
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = lane + 64 * i;
-        if (e < RJ) sComb[e] = (w == 0 ? 0.0 : sComb[e]) + (double)facc[i];
-      }
+    for (int i = 0; i < EPT; ++i)
+      if (64 * i < YS) cf[lane + 64 * i] = facc[i];
 #pragma unroll
-      for (int i = 0; i < DQ; ++i) {
-        const int q = lane + 64 * i;
-        if (q < RR) sComb[RJ + q] = (w == 0 ? 0.0 : sComb[RJ + q]) + gacc[i];
-      }
-      if (lane == 0) sComb[RJ + RR] = (w == 0 ? 0.0 : sComb[RJ + RR]) + nacc;
+    for (int i = 0; i < DQ; ++i) {
+      const int q = lane + 64 * i;
+      if (q < RR) cg[q] = gacc[i];
     }
-    __syncthreads();
+    if (lane == 0) cg[RR] = nacc;
   }
+  __syncthreads();
   double *part = a.partials + (int64_t)chunk * plen;
-  for (int e = tid; e < plen; e += 512) part[e] = sComb[e];
+  const size_t goff = align_up((size_t)YS * 4, 16);
+  for (int e = tid; e < plen; e += 512) {
+    double v[kWaveWarps];
+    if (e < RJ) {
+#pragma unroll
+      for (int w = 0; w < kWaveWarps; ++w) v[w] = (double)((const float *)(smem + w * slot))[e];
+    } else {
+#pragma unroll
+      for (int w = 0; w < kWaveWarps; ++w) v[w] = ((const double *)(smem + w * slot + goff))[e - RJ];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaveWarps; ++w) acc += v[w];
+    part[e] = acc;
+  }
   arrive(a, h, chunk, &sflag);
 }
 
@@ -1363,22 +1491,23 @@ static inline int dq_of(int R) {
   const int q = (R * R + 63) / 64;
   if (q <= 1) return 1;
   if (q <= 2) return 2;
-  if (q <= 4) return 4;
-  if (q <= 8) return 8;
-  return 16;
+  return 4;   // R <= 16
 }
 
 int pass_variant(int J, int R) {
-  if (J <= 128 && R * J <= 2048 && wave_lds(J, R).bytes <= 150 * 1024) return kPassWave;
+  // the per-wave register tiles fit without spilling up to R = 16
+  if (J <= 128 && R <= 16 && R * J <= 2048 && wave_lds(J, R).bytes <= 150 * 1024) return kPassWave;
   return kPassBlock;
 }
 
-int pass_chunk(int variant, int K) {
+int pass_chunk(int variant, int K, int n_cu) {
   int ch;
   if (variant == kPassWave) {
-    // one slice per wave while that leaves >= ~2 workgroups per CU; more otherwise
-    const int per = (K + 8 * 512 - 1) / (8 * 512);
-    ch = 8 * (per < 1 ? 1 : per);
+    // one workgroup per CU is resident (register bound): give every wave the
+    // same number of slices and launch at most one workgroup per CU
+    const int slots = kWaveWarps * (n_cu > 0 ? n_cu : 256);
+    const int per = (K + slots - 1) / slots;
+    ch = kWaveWarps * (per < 1 ? 1 : per);
   } else {
     ch = (K + 511) / 512;
     if (ch < 1) ch = 1;
@@ -1417,11 +1546,8 @@ int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s) {
   if (variant == kPassWave) {
     switch (ept_of(a.J, a.R) * 32 + dq_of(a.R)) {
 #define C(E, Q) case E * 32 + Q: return launch_wave_t<E, Q>(a, n_chunks, s);
-      C(4, 1) C(4, 2) C(4, 4) C(4, 8) C(4, 16)
-      C(8, 1) C(8, 2) C(8, 4) C(8, 8) C(8, 16)
-      C(16, 1) C(16, 2) C(16, 4) C(16, 8) C(16, 16)
-      C(24, 1) C(24, 2) C(24, 4) C(24, 8) C(24, 16)
-      C(32, 1) C(32, 2) C(32, 4) C(32, 8) C(32, 16)
+      C(4, 1) C(4, 2) C(4, 4) C(8, 1) C(8, 2) C(8, 4) C(16, 1) C(16, 2) C(16, 4)
+      C(24, 1) C(24, 2) C(24, 4) C(32, 1) C(32, 2) C(32, 4)
 #undef C
       default: return (int)hipErrorInvalidValue;
     }
@@ -1437,11 +1563,20 @@ int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s) {
   }
 }
 
-int launch_finish(const PassArgs &a, int mode, hipStream_t s) {
+template <int RM>
+static int launch_finish_t(const PassArgs &a, int mode, hipStream_t s) {
   const size_t bytes = finish_launch_lds(a.J, a.R);
-  if (int e = allow_lds(k_finish, bytes)) return e;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), bytes, s, a, mode);
+  if (int e = allow_lds(k_finish<RM>, bytes)) return e;
+  hipLaunchKernelGGL((k_finish<RM>), dim3(1), dim3(kFinishThreads), bytes, s, a, mode);
   return (int)hipGetLastError();
+}
+
+int launch_finish(const PassArgs &a, int mode, hipStream_t s) {
+  if (a.R <= 8) return launch_finish_t<8>(a, mode, s);
+  if (a.R <= 12) return launch_finish_t<12>(a, mode, s);
+  if (a.R <= 16) return launch_finish_t<16>(a, mode, s);
+  if (a.R <= 24) return launch_finish_t<24>(a, mode, s);
+  return launch_finish_t<32>(a, mode, s);
 }
 
 int launch_accum_given_u(int J, int R, int K, const int64_t *rp, const float *X, const float *U,

@@ -9,7 +9,10 @@ element.  Tolerances follow from float32 arithmetic on the GPU:
     J <= 256 and R <= 32 in float32: ~sqrt(J) * 2^-24 ~ 1e-6 worst case);
   * W and V pass through R x R solves: the bound is scaled by the condition
     number of the systems, capped at 1e-4;
-  * fit: |difference| <= 1e-6 (FP64 closed form on FP32 state).
+  * fit: the loss is a difference of terms of size sum_n, so a relative
+    state error e (the largest of those of Y, D, n) moves ell = loss / sum_n
+    by about 4 e and fit = 1 - sqrt(ell) by 4 e / (2 sqrt(ell)); the bound is
+    1e-6 + 4 e / (1 - fit).
 """
 import numpy as np
 import pytest
@@ -75,7 +78,8 @@ def check_step(g, o, r, rep, tol_w=1e-4, tag=""):
     assert rep["committed"] == 1
     assert errs["U"] <= 2e-6 and errs["Y"] <= 2e-6 and errs["D"] <= 2e-6 and errs["n"] <= 1e-6, errs
     assert errs["W"] <= tol_w and errs["V"] <= tol_w, errs
-    assert errs["fit"] <= 1e-6, errs
+    e_state = max(errs["Y"], errs["D"], errs["n"])
+    assert errs["fit"] <= 1e-6 + 4.0 * e_state / max(1.0 - r.fit, 1e-3), errs
     return errs
 
 
@@ -125,7 +129,7 @@ def test_init_from_factors_state_matches_oracle():
 
 
 @pytest.mark.parametrize("J,R,n_iter", [(1, 1, 1), (7, 3, 2), (20, 5, 3), (64, 8, 1), (65, 5, 1),
-                                        (88, 10, 1), (128, 20, 1), (200, 17, 2), (256, 32, 1)])
+                                        (88, 10, 1), (128, 20, 1), (200, 17, 2), (128, 16, 1), (64, 32, 1), (256, 32, 1)])
 def test_teacher_forced_update_shapes(J, R, n_iter):
     """One update from an identical state, every (R, J) register class."""
     Dash = _dash()
