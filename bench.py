@@ -40,13 +40,46 @@ def algorithmic_bytes(M, K, K_t, J, R):
             + K * R * 8)
 
 
+def _source_digest():
+    """SHA-256 of the kernel source the library is built from."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2305_18376_amd", "csrc", "dash_kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counter_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed byte-counter
+    summary (profiles/<kernel>_mid_counters.md), or None when that summary is
+    missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_mid_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != _source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=90)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--oracle-steps", type=int, default=10, help="updates replayed by the FP64 oracle")
+    ap.add_argument("--oracle-seconds", type=float, default=25.0,
+                    help="bound on the FP64 oracle replay (CPU baseline and fit check)")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed region, one plain device copy of this many MiB "
+                         "(reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -107,6 +140,14 @@ def main():
     h1 = time.perf_counter()
     prof = g.profile_read()
     g.profile(False)
+    if args.copy_mb > 0:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     dev_ms = ev0.elapsed_time(ev1)
     lat = np.array([a.elapsed_time(b) for a, b in step_ev])
     rows = sum(batches[W_ + i].M for i in range(K_))
@@ -145,20 +186,25 @@ def main():
                                ("pass_ms", "reduce_ms", "solve_ms", "commit_ms", "upload_ms")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "kernel": "k_pass", "algorithmic_bytes_per_step": bytes_pass / K_},
+                     "kernel": "k_pass_wave", "algorithmic_bytes_per_step": bytes_pass / K_},
         "final_fit": last["fit"],
         "gen_s": t_gen,
     }
 
+    tr = counter_traffic("k_pass_wave")
+    out["roofline"]["traffic"] = tr
     if not args.no_oracle:
-        out["fit_check"], out["cpu_baseline"] = oracle_leg(wl, ptr, X, U, batches, gpu_fits,
-                                                           min(args.oracle_steps, W_))
+        out["fit_check"], out["cpu_baseline"] = oracle_leg(wl, ptr, X, U, batches, gpu_fits, last["fit"],
+                                                           args.oracle_seconds)
     print(json.dumps(out), flush=True)
 
 
-def oracle_leg(wl, ptr, X, U, batches, gpu_fits, n):
-    """FP64 oracle over the first n updates (the warm-up updates): fit check and
-    the CPU baseline (single-threaded BLAS)."""
+def oracle_leg(wl, ptr, X, U, batches, gpu_fits, gpu_final_fit, budget_s):
+    """The FP64 oracle replays the same stream from the start (single-threaded
+    BLAS) for at most budget_s seconds of update time: its fits are compared
+    with the GPU's blocking warm-up updates and, when the replay reaches the end
+    of the stream, with the GPU's final fit; its update rate is the CPU
+    baseline."""
     from threadpoolctl import threadpool_limits
     from oracle.dash_oracle import DashOracle
     with threadpool_limits(limits=1):
@@ -166,19 +212,25 @@ def oracle_leg(wl, ptr, X, U, batches, gpu_fits, n):
         slices = [X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)]
         o.init_from_factors(slices, [U[ptr[k]:ptr[k + 1]] for k in range(wl.K0)], wl.W[: wl.K0], wl.V)
         fits, secs, rows = [], 0.0, 0
-        for i in range(n):
-            b = batches[i]
+        for b in batches:
             t = time.perf_counter()
             r = o.update(b.groups(), b.new_slices())
             secs += time.perf_counter() - t
             rows += b.M
             fits.append(r.fit)
-    d = [abs(a - b) for a, b in zip(gpu_fits[:n], fits)]
-    fit_check = {"updates": n, "max_abs_dfit": max(d) if d else None, "oracle_fit_last": fits[-1] if fits else None,
+            if secs >= budget_s:
+                break
+    n = len(fits)
+    d = [abs(a - b) for a, b in zip(gpu_fits, fits)]
+    complete = n == len(batches)
+    if complete:
+        d.append(abs(gpu_final_fit - fits[-1]))
+    fit_check = {"updates_compared": len(d), "oracle_updates": n, "final_fit_compared": complete,
+                 "max_abs_dfit": max(d) if d else None, "oracle_fit_last": fits[-1] if fits else None,
                  "within_1e-3": bool(d and max(d) <= 1e-3)}
     cpu = {"value": rows / secs if secs > 0 else None, "unit": "rows/s", "cores": 1, "kind": "oracle",
-           "sample": f"first {n} updates of the same stream (FP64 numpy oracle, 1 BLAS thread), "
-                     f"{rows} rows in {secs:.1f} s"}
+           "sample": f"updates 1..{n} of the same stream replayed by the FP64 numpy oracle "
+                     f"(1 BLAS thread): {rows} rows in {secs:.1f} s"}
     return fit_check, cpu
 
 
