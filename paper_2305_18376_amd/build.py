@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdash.so")
-SOURCES = [os.path.join(CSRC, "dash_host.cpp"), os.path.join(CSRC, "dash_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "dash_host.cpp"), os.path.join(CSRC, "dash_kernels.hip"),
+           os.path.join(CSRC, "dash_init.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

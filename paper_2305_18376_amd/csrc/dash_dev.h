@@ -126,6 +126,38 @@ enum { kPassWave = 0, kPassBlock = 1 };
 
 // Launchers (dash_kernels.hip).
 // Choose the sweep variant for (J, R); returns kPassWave or kPassBlock.
+// Arguments of the initial-decomposition kernels (PARAFAC2-ALS, Sec. 3.2.1).
+struct InitArgs {
+  int J, R, K;
+  int ys;              // Y slice stride (y_stride)
+  int64_t K_cap;
+  const int64_t *row_ptr;   // device [K+1]
+  const float *X;      // device [row_ptr[K] x J]
+  float *Y;            // state Y [2][K_cap][ys]: buffer 1 holds (X_k V)^T X_k, buffer 0 Y_k
+  float *D;            // state D [2][K_cap][R*R]: buffer 0 holds Pi_k
+  double *Dh;          // [K][R*R] (X_k V)^T X_k V in FP64 (its rank decides P_k's retained eigenspace)
+  double *n;           // state n [K_cap] (buffer 0)
+  double *W;           // state W [K_cap][R] (buffer 0)
+  double *V64;         // V, J x R (the committed bundle's V)
+  double *H;           // R x R
+  double *WtW;         // R x R
+  double *VtV;         // R x R
+  double *Mwinv;       // ((H^T H) * (V^T V))^{-1}, R x R
+  double *part;        // chunk partials [n_chunks][plen]
+  int plen;            // max(2 R^2, J R) + 2
+  int chunk;           // slices per chunk
+  int n_chunks;
+  double *result;      // [0] loss, [1] sum of n_k
+};
+
+int init_gram_chunks(int J);
+int launch_init_gram(int J, int64_t N, int n_gc, const float *X, double *part, double *Gm, hipStream_t s);
+int launch_sym_eig(int n, double *A, double *Z, double *evals, hipStream_t s);
+int launch_top_vectors(int J, int R, const double *evals, const double *Z, double *V64, hipStream_t s);
+int launch_init_start(const InitArgs &a, hipStream_t s);
+int launch_init_iteration(const InitArgs &a, hipStream_t s);
+int launch_init_handoff(const InitArgs &a, hipStream_t s);
+
 int pass_variant(int J, int R);
 // Slices per workgroup for a variant and slice count.
 int pass_chunk(int variant, int K, int n_cu);

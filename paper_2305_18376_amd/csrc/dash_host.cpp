@@ -512,12 +512,100 @@ dash_status dash_init_from_factors(dash_ctx *c, int32_t K, const int64_t *row_pt
 
 dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
                       dash_init_report *report) {
-  (void)K;
-  (void)row_ptr;
-  (void)X;
-  (void)V0;
-  (void)report;
-  return fail(c, DASH_E_BAD_STATE, "dash_init is not available in this build");
+  if (!c) return DASH_E_INVALID_ARG;
+  if (c->initialized) return fail(c, DASH_E_BAD_STATE, "context already initialised");
+  if (K < 1) return fail(c, DASH_E_INVALID_ARG, "K must be >= 1");
+  if (K > c->K_cap) return fail(c, DASH_E_CAPACITY, "K=%d exceeds max_slices", K);
+  if (!X) return fail(c, DASH_E_INVALID_ARG, "X is NULL");
+  if (dash_status s = validate_ptr(c, row_ptr, K, true)) return s;
+  if (row_ptr[0] != 0) return fail(c, DASH_E_INVALID_ARG, "row_ptr[0] must be 0");
+  const int64_t N = row_ptr[K];
+  if (N > c->N_init_cap)
+    return fail(c, DASH_E_CAPACITY, "%lld initial rows exceed max_init_rows", (long long)N);
+  if (dash_status s = reset_device_state(c, K, 0)) return s;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_rowptr, row_ptr, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice,
+                                c->stream));
+  const int J = c->J, R = c->R, RR = R * R;
+  // the initialisation's scratch lives for this call only
+  const int chunk = std::max(1, (K + 1023) / 1024);
+  const int n_chunks = (K + chunk - 1) / chunk;
+  const int plen = std::max(2 * RR, J * R) + 2;
+  const int n_gc = init_gram_chunks(J);
+  const size_t ws_doubles = (size_t)2 * J * J + J + (size_t)(V0 ? 0 : n_gc) * J * J + 4 * (size_t)RR +
+                            (size_t)n_chunks * plen + 2 + (size_t)K * RR;
+  double *ws = nullptr;
+  if (hipMalloc((void **)&ws, ws_doubles * sizeof(double)) != hipSuccess)
+    return fail(c, DASH_E_OUT_OF_MEMORY, "initialisation scratch (%zu doubles)", ws_doubles);
+  struct Freer {
+    double *p;
+    ~Freer() { (void)hipFree(p); }
+  } freer{ws};
+  double *Gm = ws, *Z = Gm + (size_t)J * J, *evals = Z + (size_t)J * J;
+  double *gpart = evals + J;
+  double *small = gpart + (size_t)(V0 ? 0 : n_gc) * J * J;
+  InitArgs a{};
+  a.J = J;
+  a.R = R;
+  a.K = K;
+  a.ys = y_stride(J, R);
+  a.K_cap = c->K_cap;
+  a.row_ptr = c->d_rowptr;
+  a.X = X;
+  a.Y = c->Y;
+  a.D = c->D;
+  a.n = c->n;
+  a.W = c->W;
+  a.V64 = vb_view(c->vb, J, R).V64;   // the committed bundle (generation 0)
+  a.H = small;
+  a.WtW = small + RR;
+  a.VtV = small + 2 * RR;
+  a.Mwinv = small + 3 * RR;
+  a.part = small + 4 * RR;
+  a.plen = plen;
+  a.chunk = chunk;
+  a.n_chunks = n_chunks;
+  a.result = a.part + (size_t)n_chunks * plen;
+  a.Dh = a.result + 2;
+  if (V0) {
+    LAUNCH_OR_FAIL(c, launch_v_from_f32(J, R, V0, c->vb, c->stream));
+  } else {
+    LAUNCH_OR_FAIL(c, launch_init_gram(J, N, n_gc, X, gpart, Gm, c->stream));
+    LAUNCH_OR_FAIL(c, launch_sym_eig(J, Gm, Z, evals, c->stream));
+    LAUNCH_OR_FAIL(c, launch_top_vectors(J, R, evals, Z, a.V64, c->stream));
+  }
+  LAUNCH_OR_FAIL(c, launch_init_start(a, c->stream));
+  const int max_iter = std::max(1, c->cfg.init_max_iter);
+  double prev = 0.0, loss = 0.0, sum_n = 0.0;
+  int iters = 0;
+  for (int it = 1; it <= max_iter; ++it) {
+    LAUNCH_OR_FAIL(c, launch_init_iteration(a, c->stream));
+    double res[2];
+    HIP_OR_FAIL(c, hipMemcpyAsync(res, a.result, sizeof res, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    iters = it;
+    loss = res[0];
+    sum_n = res[1];
+    if (!std::isfinite(loss)) return fail(c, DASH_E_NUMERIC, "non-finite loss in initial iteration %d", it);
+    if (it > 1 && std::fabs(prev - loss) <= c->cfg.init_tol * std::fabs(loss)) break;
+    prev = loss;
+  }
+  LAUNCH_OR_FAIL(c, launch_init_handoff(a, c->stream));
+  if (dash_status s = enqueue_prep(c)) return s;
+  c->step = 0;
+  if (dash_status s = enqueue_eval(c, K)) return s;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->initialized = true;
+  c->K = c->K_enq = c->K_pending = K;
+  c->step = c->step_enq = 0;
+  c->m_last = 0;
+  c->pending.clear();
+  c->rows_pending = 0;
+  if (report) {
+    report->iters = iters;
+    report->loss = loss;
+    report->fit = sum_n > 0.0 ? 1.0 - std::sqrt(std::max(0.0, loss)) / std::sqrt(sum_n) : 1.0;
+  }
+  return DASH_OK;
 }
 
 dash_status dash_ingest_rows(dash_ctx *c, int32_t n, const int32_t *slice_id, const int64_t *row_ptr,

@@ -1,0 +1,110 @@
+"""GPU parity of the initial decomposition (dash_init: PARAFAC2-ALS of
+Sec. 3.2.1 and the hand-off to the streaming state) against the FP64 oracle.
+
+The GPU keeps the per-slice products (X_k V)^T X_k and the Procrustes-rotated
+slices Y_k in float32 and does every R x R step (P_k^{-1/2}, the CP-ALS solves)
+in float64, so after the same number of ALS iterations its factors agree with
+the oracle's to float32 accuracy amplified by the conditioning of the ALS map:
+factors and state normwise within 1e-5; the loss, a difference of terms of
+size sum_n, within 1e-6 sum_n; the fit within 1e-5.
+"""
+import numpy as np
+import pytest
+
+from oracle.dash_oracle import DashOracle, parafac2_als
+from paper_2305_18376_amd.synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def run_pair(slices, R, max_iter, tol, V0=None, lam=0.9):
+    from paper_2305_18376_amd.dash import Dash
+    J = slices[0].shape[1]
+    o = DashOracle(J, R, lam)
+    res = o.init_parafac2(slices, max_iter=max_iter, tol=tol, V0=V0)
+    ptr = np.concatenate([[0], np.cumsum([x.shape[0] for x in slices])]).astype(np.int64)
+    g = Dash(J, R, lam=lam, max_slices=len(slices) + 64, max_rows=1 << 16, max_groups=4096,
+             max_init_rows=int(ptr[-1]), init_max_iter=max_iter, init_tol=tol)
+    rep = g.init(ptr, dev(np.concatenate(slices)), None if V0 is None else dev(V0))
+    return o, res, g, rep
+
+
+def compare(o, res, g, rep, tol_f=1e-5, tag=""):
+    st, ost = g.get_state(), o.state()
+    errs = {k: relerr(st[k], ost[k]) for k in ("V", "W", "Y", "D", "n")}
+    sn = float(np.sum(ost["n"]))
+    # the loss is a difference of terms of size sum_n: measured relative to it
+    errs["loss"] = abs(rep["loss"] - res.losses[-1]) / sn
+    ofit = 1.0 - np.sqrt(max(0.0, res.losses[-1])) / np.sqrt(sn)
+    errs["fit"] = abs(rep["fit"] - ofit)
+    print(tag, rep["iters"], res.iters, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert rep["iters"] == res.iters
+    for k in ("V", "W", "Y", "D"):
+        assert errs[k] <= tol_f, (k, errs)
+    assert errs["n"] <= 1e-6, errs
+    assert errs["loss"] <= 1e-6 and errs["fit"] <= 1e-5, errs
+    return errs
+
+
+def test_init_tiny_planted_fixed_iterations():
+    wl = make_workload("tiny")
+    slices = wl.init_slices()
+    o, res, g, rep = run_pair(slices, wl.R, max_iter=10, tol=0.0)
+    compare(o, res, g, rep, tag="tiny")
+    # the state handed over reproduces the initial loss (closed form of the update)
+    upd = g.update()
+    assert upd["rows"] == 0
+    assert abs(upd["fit"] - o.fit()) <= 1e-5
+
+
+def test_init_stops_on_tolerance_like_the_oracle():
+    wl = make_workload("tiny")
+    slices = wl.init_slices()
+    # ALS on this tensor shrinks the loss by 63 %, 44 %, 35 % in iterations 5, 6, 7:
+    # a tolerance of 0.5 stops at iteration 6 with a wide margin on both sides
+    o, res, g, rep = run_pair(slices, wl.R, max_iter=30, tol=0.5)
+    assert res.iters == 6
+    compare(o, res, g, rep, tag="tol")
+
+
+def test_init_given_v0_and_rank_deficient_slices():
+    rng = np.random.default_rng(7)
+    J, R, K = 24, 6, 40
+    V = rng.standard_normal((J, R))
+    slices = []
+    for k in range(K):
+        m = int(rng.integers(2, 5)) if k % 5 == 0 else int(rng.integers(R + 2, 40))   # some I_k < R
+        U = rng.standard_normal((m, R))
+        slices.append(((U * rng.uniform(0.5, 1.5, R)) @ V.T + 0.05 * rng.standard_normal((m, J))).astype(np.float32))
+    V0 = V + 0.1 * rng.standard_normal((J, R))
+    o, res, g, rep = run_pair(slices, R, max_iter=6, tol=0.0, V0=V0)
+    compare(o, res, g, rep, tag="v0")
+
+
+@pytest.mark.parametrize("J,R", [(88, 10), (130, 16), (256, 32)])
+def test_init_shapes_then_one_update(J, R):
+    wl = make_workload("mid", J=J, R=R, K0=120, median=60, lo=R + 1, hi=400, n_steps=2)
+    ptr, X = wl.init_data()
+    slices = [X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)]
+    o, res, g, rep = run_pair(slices, R, max_iter=5, tol=0.0, lam=wl.lam)
+    compare(o, res, g, rep, tag=f"J={J} R={R}")
+    b = wl.step(1)
+    r = o.update(b.groups(), b.new_slices())
+    g.ingest_slices(b.new_ptr, dev(b.new_rows))
+    g.ingest_rows(b.row_ids, b.row_ptr, dev(b.rows))
+    upd = g.update()
+    print("update fit", upd["fit"], r.fit, flush=True)
+    assert abs(upd["fit"] - r.fit) <= 1e-5
