@@ -118,7 +118,9 @@ struct PassArgs {
   float *U_out;        // [M_cap][R]
   double *partials;    // [n_chunks][partial_len]
   double *gpart;       // [n_rgroups][partial_len]
-  int32_t *counters;   // [n_rgroups_cap + 1] arrival tickets, zero between launches
+  int32_t *counters;   // [kMaxChunks + 1] arrival tickets (the last one: all groups), zero between launches
+  int fuse;            // the last workgroup to arrive runs the final phase in the same launch
+  int lds_bytes;       // dynamic LDS of the sweep launch
 };
 
 // Kernel variants of the sweep.
@@ -162,6 +164,12 @@ int pass_variant(int J, int R);
 // Slices per workgroup for a variant and slice count.
 int pass_chunk(int variant, int K, int n_cu);
 int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s);
+// Copy bytes (a multiple of 16 not required) from a device-visible pinned host
+// block to device memory with a kernel on stream s.
+int launch_fetch(const char *src_mapped, char *dst, size_t bytes, hipStream_t s);
+// Dynamic LDS of a sweep launch that also runs the final phase, or 0 when the
+// two do not fit one workgroup.
+size_t fused_pass_lds(int variant, int J, int R);
 // Final phase of a pass (one workgroup): mode 0 after an update sweep (Lemma 3,
 // next-pass operands, commit on the last pass), 1 builds the committed V bundle
 // from its V64, 2 evaluates the fit after an evaluation sweep.

@@ -66,9 +66,12 @@ struct dash_ctx {
   double *gpart = nullptr;
   int32_t *counters = nullptr;
   int64_t *d_rowptr = nullptr;
-  char *dstep = nullptr;
+  char *dstep[kStages] = {nullptr, nullptr, nullptr, nullptr};   // device copies of the stages
+  char *hstage_dev[kStages] = {nullptr, nullptr, nullptr, nullptr};   // device view of the pinned stages
+  bool desc_fetch = true;   // true: copy each descriptor to device memory first; false: kernels read it in place
   size_t off_gptr = 0, off_groups = 0, step_bytes = 0;
   int variant = kPassWave;
+  int fused_lds = 0;   // > 0: the sweep launch runs the final phase too (its dynamic LDS)
   int n_cu = 0;   // compute units of the device
   // pinned
   char *hstage[kStages] = {nullptr, nullptr, nullptr, nullptr};
@@ -195,7 +198,30 @@ hipError_t take_stage(dash_ctx *c, int *idx) {
   return hipSuccess;
 }
 
-PassArgs base_args(const dash_ctx *c) {
+// Bring stage s (bytes) to the device: a fetch kernel on the compute stream
+// reads the pinned block through its device mapping, so the update's kernels
+// follow it on the same queue without a copy-engine round trip.  The block is
+// free for the host again once stage_ev[s] has completed.
+hipError_t upload_stage(dash_ctx *c, int s, size_t bytes, bool profile) {
+  hipError_t e = hipSuccess;
+  if (!c->desc_fetch) return e;   // the kernels read the pinned block in place (see stage_done)
+  if (profile) e = prof_begin(c, kProfUpload);
+  if (e == hipSuccess) e = (hipError_t)launch_fetch(c->hstage_dev[s], c->dstep[s], bytes, c->stream);
+  if (e == hipSuccess && profile) e = prof_end(c);
+  if (e == hipSuccess) e = hipEventRecord(c->stage_ev[s], c->stream);
+  c->stage_used[s] = true;
+  return e;
+}
+
+// After the kernels of an update that read stage s in place: the host may
+// rewrite the block once they have run.
+hipError_t stage_done(dash_ctx *c, int s) {
+  if (c->desc_fetch) return hipSuccess;
+  c->stage_used[s] = true;
+  return hipEventRecord(c->stage_ev[s], c->stream);
+}
+
+PassArgs base_args(const dash_ctx *c, int s) {
   PassArgs a{};
   a.J = c->J;
   a.R = c->R;
@@ -203,9 +229,10 @@ PassArgs base_args(const dash_ctx *c) {
   a.lambda = c->cfg.lambda;
   a.log2_lambda = std::log2(c->cfg.lambda);
   a.K_cap = c->K_cap;
-  a.hdr = (const StepHeader *)c->dstep;
-  a.chunk_gptr = (const int32_t *)(c->dstep + c->off_gptr);
-  a.groups = (const Group *)(c->dstep + c->off_groups);
+  const char *d = c->desc_fetch ? c->dstep[s] : c->hstage_dev[s];
+  a.hdr = (const StepHeader *)d;
+  a.chunk_gptr = (const int32_t *)(d + c->off_gptr);
+  a.groups = (const Group *)(d + c->off_groups);
   a.Y = c->Y;
   a.D = c->D;
   a.n = c->n;
@@ -219,6 +246,8 @@ PassArgs base_args(const dash_ctx *c) {
   a.partials = c->partials;
   a.gpart = c->gpart;
   a.counters = c->counters;
+  a.fuse = c->fused_lds > 0 ? 1 : 0;
+  a.lds_bytes = c->fused_lds;
   return a;
 }
 
@@ -245,20 +274,19 @@ dash_status enqueue_eval(dash_ctx *c, int K) {
   int32_t *gptr = (int32_t *)(blk + c->off_gptr);
   for (int i = 0; i <= nch; ++i) gptr[i] = 0;
   const size_t bytes = c->off_gptr + sizeof(int32_t) * (nch + 1);
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->dstep, blk, bytes, hipMemcpyHostToDevice, c->stream));
-  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
-  c->stage_used[s] = true;
-  PassArgs a = base_args(c);
+  HIP_OR_FAIL(c, upload_stage(c, s, bytes, false));
+  PassArgs a = base_args(c, s);
   a.pass = 0;
   a.last_pass = 0;
   a.mode = 1;
   LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
-  LAUNCH_OR_FAIL(c, launch_finish(a, 2, c->stream));
+  if (!a.fuse) LAUNCH_OR_FAIL(c, launch_finish(a, 2, c->stream));
+  HIP_OR_FAIL(c, stage_done(c, s));
   return DASH_OK;
 }
 
 dash_status enqueue_prep(dash_ctx *c) {
-  PassArgs a = base_args(c);
+  PassArgs a = base_args(c, 0);   // reads no descriptor
   LAUNCH_OR_FAIL(c, launch_finish(a, 1, c->stream));
   return DASH_OK;
 }
@@ -377,6 +405,10 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->G_cap = cfg->max_groups_per_update + c->K_cap;  // new slices are groups too
   c->N_init_cap = cfg->max_init_rows;
   c->variant = pass_variant(cfg->J, cfg->R);
+  c->fused_lds = (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
+  if (const char *e = std::getenv("DASH_FUSE"))
+    if (std::atoi(e) == 0) c->fused_lds = 0;
+  if (const char *e = std::getenv("DASH_DESC_FETCH")) c->desc_fetch = std::atoi(e) != 0;
   if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
   auto bail = [&](dash_status s) {
     dash_destroy(c);
@@ -413,10 +445,12 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->off_gptr = align_up(sizeof(StepHeader), 64);
   c->off_groups = align_up(c->off_gptr + sizeof(int32_t) * (n_chunks_cap + 1), 64);
   c->step_bytes = align_up(c->off_groups + sizeof(Group) * c->G_cap, 256);
-  if (dalloc(&c->dstep, c->step_bytes) != hipSuccess) return bail(DASH_E_OUT_OF_MEMORY);
   for (int s = 0; s < kStages; ++s) {
-    if (hipHostMalloc((void **)&c->hstage[s], c->step_bytes, hipHostMallocDefault) != hipSuccess)
+    if (dalloc(&c->dstep[s], c->step_bytes) != hipSuccess) return bail(DASH_E_OUT_OF_MEMORY);
+    if (hipHostMalloc((void **)&c->hstage[s], c->step_bytes, hipHostMallocMapped) != hipSuccess)
       return bail(DASH_E_OUT_OF_MEMORY);
+    if (hipHostGetDevicePointer((void **)&c->hstage_dev[s], c->hstage[s], 0) != hipSuccess)
+      return bail(DASH_E_DEVICE);
     if (hipEventCreateWithFlags(&c->stage_ev[s], hipEventDisableTiming) != hipSuccess)
       return bail(DASH_E_DEVICE);
   }
@@ -456,8 +490,8 @@ dash_status dash_destroy(dash_ctx *c) {
   (void)hipFree(c->gpart);
   (void)hipFree(c->counters);
   (void)hipFree(c->d_rowptr);
-  (void)hipFree(c->dstep);
   for (int s = 0; s < kStages; ++s) {
+    (void)hipFree(c->dstep[s]);
     if (c->hstage[s]) (void)hipHostFree(c->hstage[s]);
     if (c->stage_ev[s]) (void)hipEventDestroy(c->stage_ev[s]);
   }
@@ -720,13 +754,9 @@ dash_status dash_update_async(dash_ctx *c) {
   h->report = (void *)(c->dreport + slot);
   c->hreport[slot].done = 0;
   const size_t bytes = c->off_groups + sizeof(Group) * ng;
-  HIP_OR_FAIL(c, prof_begin(c, kProfUpload));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->dstep, blk, bytes, hipMemcpyHostToDevice, c->stream));
-  HIP_OR_FAIL(c, prof_end(c));
-  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
-  c->stage_used[s] = true;
+  HIP_OR_FAIL(c, upload_stage(c, s, bytes, true));
 
-  PassArgs a = base_args(c);
+  PassArgs a = base_args(c, s);
   a.mode = 0;
   for (int p = 0; p < c->cfg.n_iter; ++p) {
     a.pass = p;
@@ -734,10 +764,13 @@ dash_status dash_update_async(dash_ctx *c) {
     HIP_OR_FAIL(c, prof_begin(c, kProfPass));
     LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
     HIP_OR_FAIL(c, prof_end(c));
-    HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
-    LAUNCH_OR_FAIL(c, launch_finish(a, 0, c->stream));
-    HIP_OR_FAIL(c, prof_end(c));
+    if (!a.fuse) {
+      HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
+      LAUNCH_OR_FAIL(c, launch_finish(a, 0, c->stream));
+      HIP_OR_FAIL(c, prof_end(c));
+    }
   }
+  HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
   c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
   c->K_enq = K;

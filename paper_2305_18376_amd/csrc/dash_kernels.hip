@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "dash_dev.h"
 #include "dash_math.h"
 
@@ -197,10 +199,12 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
 
 // Arrival of a workgroup whose chunk partial is written: the last of each group
 // of kChunksPerRGroup chunks to arrive sums the group's partials in chunk order
-// into gpart (a first reduction level inside the sweep launch; k_finish does the
-// second).  The group's ticket is reset by that workgroup, so all tickets are
-// zero again when the launch ends.
-__device__ void arrive(const PassArgs &a, const StepHeader *h, int chunk, int *sflag) {
+// into gpart (a first reduction level inside the sweep launch; the final phase
+// does the second).  With a.fuse, the last group reducer to finish takes a
+// second ticket and returns true: it then runs the final phase.  Every ticket is
+// reset by the workgroup that drew the last number, so all are zero again when
+// the launch ends.
+__device__ bool arrive(const PassArgs &a, const StepHeader *h, int chunk, int *sflag) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int plen = partial_len(a.J, a.R);
   const int cpr = h->chunks_per_rgroup;
@@ -213,11 +217,32 @@ __device__ void arrive(const PassArgs &a, const StepHeader *h, int chunk, int *s
     *sflag = (old == c1 - c0 - 1) ? 1 : 0;
   }
   __syncthreads();
-  if (!*sflag) return;
+  if (!*sflag) return false;
   __threadfence();
   for (int e = tid; e < plen; e += nt) a.gpart[(int64_t)rg * plen + e] = ordered_sum(a.partials, plen, e, c0, c1);
-  if (tid == 0) a.counters[rg] = 0;
+  if (!a.fuse) {
+    if (tid == 0) a.counters[rg] = 0;
+    return false;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.counters[rg] = 0;
+    __threadfence();
+    const int old = atomicAdd(&a.counters[kMaxChunks], 1);
+    *sflag = (old == h->n_rgroups - 1) ? 1 : 0;
+    if (*sflag) a.counters[kMaxChunks] = 0;
+  }
+  __syncthreads();
+  if (!*sflag) return false;
+  __threadfence();
+  return true;
 }
+
+// R bucket of the final phase's register eliminations
+template <int RQ>
+struct FinishBucket {
+  static constexpr int value = RQ <= 8 ? 8 : RQ <= 12 ? 12 : RQ <= 16 ? 16 : RQ <= 24 ? 24 : 32;
+};
 
 // Final phase of a pass as its own single-workgroup launch (modes as finish_pass).
 __host__ __device__ inline size_t finish_launch_lds(int J, int R) {
@@ -642,7 +667,8 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
     for (int w = 0; w < kWaveWarps; ++w) acc += v[w];
     part[e] = acc;
   }
-  arrive(a, h, chunk, &sflag);
+  if (arrive(a, h, chunk, &sflag))
+    finish_pass<FinishBucket<RC>::value>(a, h, h->n_rgroups, a.mode == 0 ? 0 : 2, smem, (size_t)a.lds_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,7 +989,8 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
     if (q < RR) part[R * J + q] = gacc[i];
   }
   if (tid == 0) part[R * J + RR] = nacc;
-  arrive(a, h, chunk, &sflag);
+  if (arrive(a, h, chunk, &sflag))
+    finish_pass<FinishBucket<4 * RW>::value>(a, h, h->n_rgroups, a.mode == 0 ? 0 : 2, smem, (size_t)a.lds_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,8 +1056,17 @@ __global__ __launch_bounds__(256) void k_accum_given_u(int J, int R, const int64
 }
 
 // ---------------------------------------------------------------------------
-// small conversion kernels
+// small copy and conversion kernels
 // ---------------------------------------------------------------------------
+// dst[0, bytes) = src[0, bytes); src is pinned host memory mapped for the
+// device.  16-byte words, one per thread, all loads in flight at once.
+__global__ void k_fetch(const uint4 *src, uint4 *dst, int64_t n16, const unsigned char *src_tail,
+                        unsigned char *dst_tail, int tail) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
+  if (i < tail) dst_tail[i] = src_tail[i];
+}
+
 __global__ void k_v_from_f32(int JR, const float *V, double *V64) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e < JR) V64[e] = (double)V[e];
@@ -1127,18 +1163,27 @@ int pass_chunk(int variant, int K, int n_cu) {
 
 template <int EPT, int DQ>
 static int launch_wave_t(const PassArgs &a, int n_chunks, hipStream_t s) {
-  const WaveLds L = wave_lds(a.J, a.R);
-  if (int e = allow_lds(k_pass_wave<EPT, DQ>, L.bytes)) return e;
-  hipLaunchKernelGGL((k_pass_wave<EPT, DQ>), dim3(n_chunks), dim3(512), L.bytes, s, a);
+  const size_t bytes = a.fuse ? (size_t)a.lds_bytes : wave_lds(a.J, a.R).bytes;
+  if (int e = allow_lds(k_pass_wave<EPT, DQ>, bytes)) return e;
+  hipLaunchKernelGGL((k_pass_wave<EPT, DQ>), dim3(n_chunks), dim3(512), bytes, s, a);
   return (int)hipGetLastError();
 }
 
 template <int RW, int JW>
 static int launch_block_t(const PassArgs &a, int n_chunks, hipStream_t s) {
-  const PassLds L = pass_lds(a.J, a.R);
-  if (int e = allow_lds(k_pass_block<RW, JW>, L.bytes)) return e;
-  hipLaunchKernelGGL((k_pass_block<RW, JW>), dim3(n_chunks), dim3(256), L.bytes, s, a);
+  const size_t bytes = a.fuse ? (size_t)a.lds_bytes : pass_lds(a.J, a.R).bytes;
+  if (int e = allow_lds(k_pass_block<RW, JW>, bytes)) return e;
+  hipLaunchKernelGGL((k_pass_block<RW, JW>), dim3(n_chunks), dim3(256), bytes, s, a);
   return (int)hipGetLastError();
+}
+
+size_t fused_pass_lds(int variant, int J, int R) {
+  const size_t sweep = (variant == kPassWave) ? wave_lds(J, R).bytes : pass_lds(J, R).bytes;
+  const size_t cap = 160 * 1024;
+  const size_t with_v = std::max(sweep, finish_launch_lds(J, R));
+  if (with_v <= cap) return with_v;
+  const size_t base = std::max(sweep, finish_lds_bytes(J, R));
+  return base <= cap ? base : 0;
 }
 
 template <int RW, int JW>
@@ -1200,6 +1245,17 @@ int launch_accum_given_u(int J, int R, int K, const int64_t *rp, const float *X,
 #undef C
     default: return (int)hipErrorInvalidValue;
   }
+}
+
+int launch_fetch(const char *src, char *dst, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return 0;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int tail = (int)(bytes - (size_t)n16 * 16);
+  const int64_t threads = std::max<int64_t>(n16, tail);
+  hipLaunchKernelGGL(k_fetch, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, (const uint4 *)src,
+                     (uint4 *)dst, n16, (const unsigned char *)src + n16 * 16, (unsigned char *)dst + n16 * 16,
+                     tail);
+  return (int)hipGetLastError();
 }
 
 int launch_v_from_f32(int J, int R, const float *V, char *vb_committed, hipStream_t s) {
