@@ -196,16 +196,19 @@ dash_status dash_save(dash_ctx *ctx, const char *path);
 dash_status dash_load(dash_ctx *ctx, const char *path);
 
 /* Per-kernel device time of the update path, measured with HIP events recorded
- * around each launch on the context's stream.  dash_profile(ctx, 1) clears the
- * counters and starts recording; dash_profile(ctx, 0) stops.  dash_profile_read
- * waits for outstanding work and returns the sums since the last clear. */
+ * around each launch on the context's stream.  dash_profile(ctx, every) clears
+ * the counters and, for every > 0, records the launches of the updates whose
+ * index (dash_update_report.step) is a multiple of `every` (1: all of them;
+ * timing events perturb the launches they bracket, so sampling keeps the
+ * others undisturbed); dash_profile(ctx, 0) stops.  dash_profile_read waits for
+ * outstanding work and returns the sums since the last clear. */
 typedef struct dash_profile_stats {
   int64_t updates;
   int64_t pass_launches, reduce_launches, solve_launches, commit_launches, upload_launches;
   double pass_ms, reduce_ms, solve_ms, commit_ms, upload_ms;
 } dash_profile_stats;
 
-dash_status dash_profile(dash_ctx *ctx, int32_t enable);
+dash_status dash_profile(dash_ctx *ctx, int32_t every);
 dash_status dash_profile_read(dash_ctx *ctx, dash_profile_stats *out);
 
 const char *dash_status_string(dash_status s);

@@ -94,7 +94,8 @@ struct dash_ctx {
   int chunk_override = 0;
   std::vector<int> order;  // scratch
   // profiling: event pairs around launches, folded into stats on read
-  bool profiling = false;
+  bool profiling = false;   // events around this update's launches
+  int prof_every = 0;       // > 0: profile the updates whose index is a multiple of it
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_kind;  // kind per recorded pair
   int ev_used = 0;           // pairs recorded since the last fold
@@ -351,12 +352,15 @@ dash_status dash_profile(dash_ctx *c, int32_t enable) {
   if (enable && c->ev.empty()) {
     c->ev.resize(2 * kProfPairs, nullptr);
     c->ev_kind.resize(kProfPairs, 0);
-    for (auto &e : c->ev) HIP_OR_FAIL(c, hipEventCreate(&e));
+    // timing-only events: no system-scope fence, so they do not write back and
+    // invalidate the caches around the launches they bracket
+    for (auto &e : c->ev) HIP_OR_FAIL(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
-  if (c->profiling) HIP_OR_FAIL(c, prof_fold(c));
+  if (c->ev_used) HIP_OR_FAIL(c, prof_fold(c));
   c->ev_used = 0;
   c->prof = dash_profile_stats{};
-  c->profiling = enable != 0;
+  c->prof_every = enable > 0 ? enable : 0;
+  c->profiling = false;
   return DASH_OK;
 }
 
@@ -740,6 +744,7 @@ dash_status dash_update_async(dash_ctx *c) {
     gptr[cidx] = gi;
   }
   const int64_t step = c->step_enq + 1;
+  c->profiling = c->prof_every > 0 && step % c->prof_every == 0;
   const int slot = (int)(step % kReportRing);
   std::memset(h, 0, sizeof *h);
   h->K = K;
@@ -772,6 +777,7 @@ dash_status dash_update_async(dash_ctx *c) {
   }
   HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
+  c->profiling = false;
   c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
   c->K_enq = K;
   c->step_enq = step;

@@ -253,8 +253,10 @@ class Dash:
         assert Y.shape == (K, self.R, self.J) and D.shape == (K, self.R, self.R) and n.shape == (K,)
         self._check(lib().dash_set_state(self._h, K, _ptr(V), _ptr(W), _ptr(Y), _ptr(D), _ptr(n)), "dash_set_state")
 
-    def profile(self, enable=True):
-        self._check(lib().dash_profile(self._h, 1 if enable else 0), "dash_profile")
+    def profile(self, every=1):
+        """Time the launches of every `every`-th update (0 or False: stop)."""
+        every = int(every) if every is not True else 1
+        self._check(lib().dash_profile(self._h, max(0, every)), "dash_profile")
 
     def profile_read(self):
         st = ProfileStats()
