@@ -53,7 +53,9 @@ typedef struct dash_config {
   int32_t n_iter;            /* ALS passes per update; 1 is Algorithm 1                  */
   int32_t init_max_iter;     /* PARAFAC2-ALS iterations of dash_init (paper: 10)         */
   double init_tol;           /* stop when |d loss| <= init_tol * loss                   */
-  int32_t precision;         /* DASH_PREC_FP32                                           */
+  int32_t precision;         /* DASH_PREC_FP32, or DASH_PREC_MIXED: the new rows' products
+                                (Lemma 1's x V (V^T V)^{-1} and U_new^T X_new, U_new^T U_new)
+                                on BF16 MFMA with FP32 sums; state FP32, R x R FP64   */
   int32_t stats_mode;        /* DASH_STATS_EXACT                                         */
   int64_t max_slices;        /* capacity in slices (K never exceeds it)                  */
   int64_t max_rows_per_update;   /* capacity in rows staged for one update               */

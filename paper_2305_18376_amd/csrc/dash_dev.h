@@ -120,6 +120,7 @@ struct PassArgs {
   double *gpart;       // [n_rgroups][partial_len]
   int32_t *counters;   // [kMaxChunks + 1] arrival tickets (the last one: all groups), zero between launches
   int fuse;            // the last workgroup to arrive runs the final phase in the same launch
+  int mixed;           // 1: Lemma 1 and the row accumulation on BF16 MFMA (FP32 sums)
   int lds_bytes;       // dynamic LDS of the sweep launch
 };
 
@@ -160,7 +161,7 @@ int launch_init_start(const InitArgs &a, hipStream_t s);
 int launch_init_iteration(const InitArgs &a, hipStream_t s);
 int launch_init_handoff(const InitArgs &a, hipStream_t s);
 
-int pass_variant(int J, int R);
+int pass_variant(int J, int R, int precision);
 // Slices per workgroup for a variant and slice count.
 int pass_chunk(int variant, int K, int n_cu);
 int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s);

@@ -248,6 +248,7 @@ PassArgs base_args(const dash_ctx *c, int s) {
   a.gpart = c->gpart;
   a.counters = c->counters;
   a.fuse = c->fused_lds > 0 ? 1 : 0;
+  a.mixed = c->cfg.precision == DASH_PREC_MIXED ? 1 : 0;
   a.lds_bytes = c->fused_lds;
   return a;
 }
@@ -397,7 +398,8 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   if (cfg->max_slices < 1 || cfg->max_slices > (int64_t)1 << 30 || cfg->max_rows_per_update < 1 ||
       cfg->max_groups_per_update < 1 || cfg->max_init_rows < 0)
     return DASH_E_INVALID_ARG;
-  if (cfg->precision != DASH_PREC_FP32 || cfg->stats_mode != DASH_STATS_EXACT)
+  if ((cfg->precision != DASH_PREC_FP32 && cfg->precision != DASH_PREC_MIXED) ||
+      cfg->stats_mode != DASH_STATS_EXACT)
     return DASH_E_INVALID_ARG;
   dash_ctx *c = new (std::nothrow) dash_ctx();
   if (!c) return DASH_E_OUT_OF_MEMORY;
@@ -408,7 +410,7 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->M_cap = cfg->max_rows_per_update;
   c->G_cap = cfg->max_groups_per_update + c->K_cap;  // new slices are groups too
   c->N_init_cap = cfg->max_init_rows;
-  c->variant = pass_variant(cfg->J, cfg->R);
+  c->variant = pass_variant(cfg->J, cfg->R, cfg->precision);
   c->fused_lds = (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
   if (const char *e = std::getenv("DASH_FUSE"))
     if (std::atoi(e) == 0) c->fused_lds = 0;

@@ -710,6 +710,61 @@ __host__ __device__ inline PassLds pass_lds(int J, int R, bool with_finish = tru
   return L;
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision (BF16 MFMA) row products of the block variant.
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16] (i < 8) and receives C[4 (l / 16) + i][l % 16]
+// (i < 4); products of BF16-rounded operands, FP32 accumulation.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// the mixed-precision tiles of one slice: wave w owns the dY column tiles
+// w, w+4, w+8, w+12 (16 columns each) for both rank tiles (accY[2 c + mt]), and
+// the dD tile w of the (R / 16)^2 rank-tile pairs
+constexpr int kMxTiles = 8;
+
+// dY += U^T X, dD += U^T U on MFMA for one staged block (rows >= m are zero
+// in both sX and sU; mp = m rounded up to 32).  The U^T operand of a rank
+// tile is loaded once per 32-row step and serves every column tile, and, as
+// the B operand of dD, the rank-tile pairs too.
+__device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU, int XS, int mp, int J,
+                                               int R, f32x4 (&accY)[kMxTiles], f32x4 &accD) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
+  const int li = lane & 15, lk = (lane >> 4) * 8;
+  for (int ks = 0; ks < mp; ks += 32) {
+    bf16x8 au[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int r = mt * 16 + li;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) au[mt][q] = (__bf16)((r < R) ? sU[(ks + lk + q) * (R + 1) + r] : 0.f);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int nt = wv + 4 * c;
+      if (nt < NT) {
+        const int j = min(nt * 16 + li, J - 1);
+        bf16x8 bv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bv[q] = (__bf16)sX[(ks + lk + q) * XS + j];
+        accY[2 * c] = mfma_bf16(au[0], bv, accY[2 * c]);
+        if (MT > 1) accY[2 * c + 1] = mfma_bf16(au[1], bv, accY[2 * c + 1]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (wv < MT * MT) {
+      const int mt = wv / MT, st = wv - mt * MT;
+      accD = mfma_bf16(mt == 0 ? au[0] : au[1], st == 0 ? au[0] : au[1], accD);
+    }
+  }
+}
+
 // dY += U^T X and dD += U^T U for one staged block of m rows (block variant).
 template <int RW, int JW>
 __device__ __forceinline__ void accum_block(const float *sX, const float *sU, int XS, int m, int J,
@@ -742,7 +797,7 @@ __device__ __forceinline__ void accum_block(const float *sX, const float *sU, in
   }
 }
 
-template <int RW, int JW>
+template <int RW, int JW, bool MX>
 __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sflag;
@@ -780,13 +835,13 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   for (int e = tid; e < R * J; e += 256) sVt[e] = vb.Vt32[e];
   for (int e = tid; e < RR; e += 256) sVtV[e] = vb.VtV[e];
 
-  double facc[RW][JW];
+  float facc[RW][JW];   // F^T partial of the chunk (the chunk partials are summed in FP64)
   double gacc[4] = {0.0, 0.0, 0.0, 0.0};
   double nacc = 0.0;
 #pragma unroll
   for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
-    for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = 0.0;
+    for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = 0.f;
 
   const int k0 = chunk * h->chunk;
   const int k1 = min(K, k0 + h->chunk);
@@ -820,49 +875,169 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) dY[rr][jj] = 0.f;
 
-    if (touched && a.mode == 0) {
-      for (int gi = gb; gi < g; ++gi) {
-        const Group gr = a.groups[gi];
-        for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
-          const int m = min(MB, gr.nrows - r0);
-          __syncthreads();
-          const float *src = gr.src + (int64_t)r0 * J;
-          for (int e = tid; e < m * J; e += 256) {
-            const int row = e / J, col = e - row * J;
-            sX[row * XS + col] = src[e];
-          }
-          __syncthreads();
-          if (lane < m) {
-            float tacc[RW];
+    if constexpr (MX) {
+      if (touched && a.mode == 0) {
+        // Lemma 1 and the accumulation on BF16 MFMA (FP32 sums)
+        f32x4 accY[kMxTiles];
+        f32x4 accD = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int rr = 0; rr < RW; ++rr) tacc[rr] = 0.f;
-            float nx = 0.f;
-            const float *xr = sX + lane * XS;
-            for (int j = 0; j < J; ++j) {
-              const float xv = xr[j];
-              nx = fmaf(xv, xv, nx);
+        for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int li = lane & 15, lk = (lane >> 4) * 8;
+        const int NTu = (R + 15) >> 4;
+        for (int gi = gb; gi < g; ++gi) {
+          const Group gr = a.groups[gi];
+          for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
+            const int m = min(MB, gr.nrows - r0);
+            const int mp = (m + 31) & ~31;
+            __syncthreads();
+            const float *src = gr.src + (int64_t)r0 * J;
+            for (int e = tid; e < mp * J; e += 256) {
+              const int row = e / J, col = e - row * J;
+              const float x = (row < m) ? src[e] : 0.f;
+              sX[row * XS + col] = x;
+              dn = fma((double)x, (double)x, dn);
+            }
+            __syncthreads();
+            // u = (x P) * (1/w): wave w takes rows 16w .. 16w+15 of the block
+            if (16 * wv < mp) {
+              f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+              const int row = 16 * wv + li;
+              for (int ks = 0; ks < J; ks += 32) {
+                bf16x8 av;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                  const int kk = ks + lk + q;
+                  av[q] = (__bf16)((kk < J) ? sX[row * XS + kk] : 0.f);
+                }
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                  if (nt >= NTu) break;
+                  const int n = nt * 16 + li;
+                  bf16x8 bv;
+#pragma unroll
+                  for (int q = 0; q < 8; ++q) {
+                    const int kk = ks + lk + q;
+                    bv[q] = (__bf16)((kk < J && n < R) ? sP[kk * R + n] : 0.f);
+                  }
+                  acc[nt] = mfma_bf16(av, bv, acc[nt]);
+                }
+              }
+#pragma unroll
+              for (int nt = 0; nt < 2; ++nt) {
+                if (nt >= NTu) break;
+                const int n = nt * 16 + li;
+                if (n < R) {
+                  const float wi = sWinv[n];
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) {
+                    const int rr = 16 * wv + (lane >> 4) * 4 + q;
+                    const float u = (rr < m) ? acc[nt][q] * wi : 0.f;
+                    sU[rr * (R + 1) + n] = u;
+                    if (a.last_pass && rr < m) a.U_out[(gr.out_row + r0 + rr) * R + n] = u;
+                  }
+                }
+              }
+            }
+            __syncthreads();
+            accum_block_mx(sX, sU, XS, mp, J, R, accY, accD);
+          }
+        }
+        // hand the tiles to the [rank][column] register layout through LDS
+        __syncthreads();
+        float *sDY = sX;   // R x J (the row block is dead)
+        float *sDD = sU;   // R x R
+        {
+          const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
+#pragma unroll
+          for (int i = 0; i < kMxTiles; ++i) {
+            const int c = i >> 1, mt = i & 1;
+            const int nt = wv + 4 * c;
+            if (nt >= NT || mt >= MT) continue;
+            const int j = nt * 16 + li;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = mt * 16 + (lane >> 4) * 4 + q;
+              if (r < R && j < J) sDY[r * J + j] = accY[i][q];
+            }
+          }
+          if (wv < MT * MT) {
+            const int mt = wv / MT, st = wv - mt * MT;
+            const int c = st * 16 + li;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = mt * 16 + (lane >> 4) * 4 + q;
+              if (r < R && c < R) sDD[r * R + c] = accD[q];
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr) {
+          const int r = wv + 4 * rr;
+#pragma unroll
+          for (int jj = 0; jj < JW; ++jj) {
+            const int j = lane + 64 * jj;
+            dY[rr][jj] = (r < R && j < J) ? sDY[r * J + j] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int q = tid + 256 * i;
+          dD[i] = (q < RR) ? sDD[q] : 0.f;
+        }
+        // ||x||^2 of the slice's rows, summed over the block in wave order
+        dn = wave_sum(dn);
+        __syncthreads();
+        if (lane == 0) sTmp[wv] = dn;
+        __syncthreads();
+        dn = (wv == 0) ? ((sTmp[0] + sTmp[1]) + sTmp[2]) + sTmp[3] : 0.0;
+        __syncthreads();
+      }
+    } else {
+    if (touched && a.mode == 0) {
+        for (int gi = gb; gi < g; ++gi) {
+          const Group gr = a.groups[gi];
+          for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
+            const int m = min(MB, gr.nrows - r0);
+            __syncthreads();
+            const float *src = gr.src + (int64_t)r0 * J;
+            for (int e = tid; e < m * J; e += 256) {
+              const int row = e / J, col = e - row * J;
+              sX[row * XS + col] = src[e];
+            }
+            __syncthreads();
+            if (lane < m) {
+              float tacc[RW];
+#pragma unroll
+              for (int rr = 0; rr < RW; ++rr) tacc[rr] = 0.f;
+              float nx = 0.f;
+              const float *xr = sX + lane * XS;
+              for (int j = 0; j < J; ++j) {
+                const float xv = xr[j];
+                nx = fmaf(xv, xv, nx);
+#pragma unroll
+                for (int rr = 0; rr < RW; ++rr) {
+                  const int r = wv + 4 * rr;
+                  if (r < R) tacc[rr] = fmaf(xv, sP[j * R + r], tacc[rr]);
+                }
+              }
 #pragma unroll
               for (int rr = 0; rr < RW; ++rr) {
                 const int r = wv + 4 * rr;
-                if (r < R) tacc[rr] = fmaf(xv, sP[j * R + r], tacc[rr]);
+                if (r < R) {
+                  const float u = tacc[rr] * sWinv[r];
+                  sU[lane * (R + 1) + r] = u;
+                  if (a.last_pass) a.U_out[(gr.out_row + r0 + lane) * R + r] = u;
+                }
               }
+              if (wv == 0) dn += (double)nx;
             }
-#pragma unroll
-            for (int rr = 0; rr < RW; ++rr) {
-              const int r = wv + 4 * rr;
-              if (r < R) {
-                const float u = tacc[rr] * sWinv[r];
-                sU[lane * (R + 1) + r] = u;
-                if (a.last_pass) a.U_out[(gr.out_row + r0 + lane) * R + r] = u;
-              }
-            }
-            if (wv == 0) dn += (double)nx;
+            __syncthreads();
+            accum_block<RW, JW>(sX, sU, XS, m, J, R, dY, dD);
           }
-          __syncthreads();
-          accum_block<RW, JW>(sX, sU, XS, m, J, R, dY, dD);
         }
+        if (wv == 0) dn = wave_sum(dn);
       }
-      if (wv == 0) dn = wave_sum(dn);
     }
 
     const int b = a.cur[(int64_t)gcur * a.K_cap + k];
@@ -932,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       if (r < R) {
         const double wr = sigma * sC[r];
 #pragma unroll
-        for (int jj = 0; jj < JW; ++jj) facc[rr][jj] += wr * (double)yv[rr][jj];
+        for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = fmaf((float)wr, yv[rr][jj], facc[rr][jj]);
       }
     }
 #pragma unroll
@@ -980,7 +1155,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
 #pragma unroll
     for (int jj = 0; jj < JW; ++jj) {
       const int j = lane + 64 * jj;
-      if (r < R && j < J) part[r * J + j] = facc[rr][jj];
+      if (r < R && j < J) part[r * J + j] = (double)facc[rr][jj];
     }
   }
 #pragma unroll
@@ -1139,7 +1314,8 @@ static inline int dq_of(int R) {
   return 4;   // R <= 16
 }
 
-int pass_variant(int J, int R) {
+int pass_variant(int J, int R, int precision) {
+  if (precision != 0) return kPassBlock;   // the BF16 MFMA row phase lives in the block variant
   // the per-wave register tiles fit without spilling up to R = 16
   if (J <= 128 && R <= 16 && R * J <= 2048 && wave_lds(J, R).bytes <= 150 * 1024) return kPassWave;
   return kPassBlock;
@@ -1172,8 +1348,13 @@ static int launch_wave_t(const PassArgs &a, int n_chunks, hipStream_t s) {
 template <int RW, int JW>
 static int launch_block_t(const PassArgs &a, int n_chunks, hipStream_t s) {
   const size_t bytes = a.fuse ? (size_t)a.lds_bytes : pass_lds(a.J, a.R).bytes;
-  if (int e = allow_lds(k_pass_block<RW, JW>, bytes)) return e;
-  hipLaunchKernelGGL((k_pass_block<RW, JW>), dim3(n_chunks), dim3(256), bytes, s, a);
+  if (a.mixed) {   // one instantiation covers every shape (R <= 32, J <= 256)
+    if (int e = allow_lds(k_pass_block<8, 4, true>, bytes)) return e;
+    hipLaunchKernelGGL((k_pass_block<8, 4, true>), dim3(n_chunks), dim3(256), bytes, s, a);
+  } else {
+    if (int e = allow_lds(k_pass_block<RW, JW, false>, bytes)) return e;
+    hipLaunchKernelGGL((k_pass_block<RW, JW, false>), dim3(n_chunks), dim3(256), bytes, s, a);
+  }
   return (int)hipGetLastError();
 }
 
@@ -1206,6 +1387,7 @@ int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s) {
       default: return (int)hipErrorInvalidValue;
     }
   }
+  if (a.mixed) return launch_block_t<8, 4>(a, n_chunks, s);
   switch (rw_of(a.R) * 8 + jw_of(a.J)) {
 #define C(RW, JW) case RW * 8 + JW: return launch_block_t<RW, JW>(a, n_chunks, s);
     C(1, 1) C(1, 2) C(1, 3) C(1, 4) C(2, 1) C(2, 2) C(2, 3) C(2, 4)

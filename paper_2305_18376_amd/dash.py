@@ -129,7 +129,7 @@ class Dash:
 
     def __init__(self, J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20,
                  max_groups=65536, max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10,
-                 device=0, stream=None):
+                 device=0, stream=None, precision=PREC_FP32):
         import torch
         L = lib()
         cfg = DashConfig()
@@ -142,6 +142,7 @@ class Dash:
         cfg.max_init_rows = max_init_rows
         cfg.init_max_iter = init_max_iter
         cfg.init_tol = init_tol
+        cfg.precision = precision
         cfg.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream

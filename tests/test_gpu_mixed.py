@@ -1,0 +1,121 @@
+"""GPU parity of the mixed-precision update (DASH_PREC_MIXED: Lemma 1's products
+and the new rows' accumulation U^T X, U^T U on BF16 MFMA with FP32 sums; the
+stored state stays FP32 and every R x R solve FP64) against the FP64 oracle.
+
+Bounds: each BF16 operand carries a relative rounding error of at most 2^-9,
+so a product term carries about 2^-8 and a sum of them normwise about 2^-8
+times the ratio sum|a||b| / |sum a b|, which the planted data keep near 1:
+U_new, Y_k, D_k within 1e-2 normwise; W and V, through the R x R solves,
+within 5e-2; the fit -- the benchmark's bar -- within 1e-3.  The FP32 path on
+the same inputs is reported beside it.
+"""
+import numpy as np
+import pytest
+
+from oracle.dash_oracle import DashOracle
+from paper_2305_18376_amd.synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def start(wl, precision, ptr, X, U):
+    from paper_2305_18376_amd.dash import Dash, PREC_FP32
+    g = Dash(wl.J, wl.R, lam=wl.lam, n_iter=wl.n_iter, max_slices=wl.K_max + 64, max_rows=1 << 20,
+             max_groups=1 << 16, precision=precision)
+    g.init_from_factors(ptr, dev(X), dev(U), dev(wl.W[: wl.K0]), dev(wl.V))
+    return g
+
+
+def feed(g, b):
+    g.ingest_slices(b.new_ptr, dev(b.new_rows))
+    g.ingest_rows(b.row_ids, b.row_ptr, dev(b.rows))
+
+
+def u_in_gpu_order(r, b):
+    """Oracle U_new rows in the library's output order (ingest order: new slices, then groups)."""
+    parts = list(r.U_new_slices) + list(r.U_groups)
+    parts = [p for p in parts if p.shape[0]]
+    return np.concatenate(parts)
+
+
+def slice_of_rows(b, K_old):
+    """Slice id of every U_new row, in the same order."""
+    new_ids = np.repeat(np.arange(K_old, K_old + b.n_new), np.diff(b.new_ptr))
+    old_ids = np.repeat(b.row_ids, np.diff(b.row_ptr))
+    return np.concatenate([new_ids, old_ids]).astype(np.int64)
+
+
+@pytest.mark.parametrize("J,R", [(88, 10), (128, 20), (256, 32)])
+def test_mixed_teacher_forced_one_update(J, R):
+    from paper_2305_18376_amd.dash import PREC_MIXED
+    wl = make_workload("precision", J=J, R=R, K0=150, median=40, lo=R + 1, hi=300, n_steps=2)
+    ptr, X, U = wl.init_data(want_u=True)
+    o = DashOracle(wl.J, wl.R, wl.lam)
+    o.init_from_factors([X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)], [U[ptr[k]:ptr[k + 1]] for k in range(wl.K0)],
+                        wl.W[: wl.K0], wl.V)
+    g = start(wl, PREC_MIXED, ptr, X, U)
+    b = wl.step(1)
+    r = o.update(b.groups(), b.new_slices())
+    feed(g, b)
+    rep = g.update()
+    st, ost = g.get_state(), o.state()
+    V, W, Un = g.get_factors()
+    errs = {k: relerr(st[k], ost[k]) for k in ("Y", "D", "n", "W", "V")}
+    errs["U"] = relerr(Un.cpu().numpy(), u_in_gpu_order(r, b))
+    errs["fit"] = abs(rep["fit"] - r.fit)
+    print(f"J={J} R={R}", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert rep["committed"] == 1
+    assert errs["U"] <= 1e-2 and errs["Y"] <= 1e-2 and errs["D"] <= 1e-2 and errs["n"] <= 1e-6, errs
+    assert errs["W"] <= 5e-2 and errs["V"] <= 5e-2, errs
+    assert errs["fit"] <= 1e-3, errs
+
+
+def test_precision_workload_error_table():
+    """Heavy-tailed rows with column scales 1e-3..1e3 (the precision workload,
+    fewer slices): both precisions free-run five updates from the planted state
+    beside the oracle; the per-result error table is printed."""
+    from paper_2305_18376_amd.dash import PREC_FP32, PREC_MIXED
+    wl = make_workload("precision", K0=400, n_steps=5)
+    ptr, X, U = wl.init_data(want_u=True)
+    o = DashOracle(wl.J, wl.R, wl.lam)
+    o.init_from_factors([X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)], [U[ptr[k]:ptr[k + 1]] for k in range(wl.K0)],
+                        wl.W[: wl.K0], wl.V)
+    gs = {"fp32": start(wl, PREC_FP32, ptr, X, U), "mixed": start(wl, PREC_MIXED, ptr, X, U)}
+    worst = {p: {"V": 0.0, "W": 0.0, "U": 0.0, "US": 0.0, "fit": 0.0} for p in gs}
+    for s in range(1, 6):
+        b = wl.step(s)
+        K_old = o.K
+        r = o.update(b.groups(), b.new_slices())
+        ou = u_in_gpu_order(r, b)
+        ids = slice_of_rows(b, K_old)
+        ost = o.state()
+        for p, g in gs.items():
+            feed(g, b)
+            rep = g.update()
+            V, W, Un = g.get_factors()
+            W, Un = W.cpu().numpy(), Un.cpu().numpy()
+            # U_new S_k does not depend on the scaling gauge of S_k (1/w amplifies small w)
+            e = {"V": relerr(V.cpu().numpy(), ost["V"]), "W": relerr(W, ost["W"]),
+                 "U": relerr(Un, ou), "US": relerr(Un * W[ids], ou * ost["W"][ids]),
+                 "fit": abs(rep["fit"] - r.fit)}
+            for k in e:
+                worst[p][k] = max(worst[p][k], e[k])
+    print("precision workload, worst over 5 updates (normwise relative; fit absolute; "
+          "US = U_new S_k):", flush=True)
+    for p in gs:
+        print(f"  {p:6s}", {k: f"{v:.2e}" for k, v in worst[p].items()}, flush=True)
+    assert worst["fp32"]["fit"] <= 1e-5
+    assert worst["mixed"]["fit"] <= 1e-3
