@@ -216,6 +216,66 @@ dash_status dash_profile_read(dash_ctx *ctx, dash_profile_stats *out);
 const char *dash_status_string(dash_status s);
 const char *dash_last_error(const dash_ctx *ctx);
 
+/* Non-blocking completion check (Algorithm 1's outputs as they become ready):
+ * reaps, in order, the enqueued updates that have finished, up to cap, and
+ * writes their reports to reports[0 .. *n_done).  If one of them was not
+ * committed (non-finite factors), the call drains the context like dash_wait,
+ * reports that update last and returns DASH_E_NUMERIC.  reports is host memory
+ * (may be NULL when cap == 0). */
+dash_status dash_poll(dash_ctx *ctx, dash_update_report *reports, int32_t cap, int32_t *n_done);
+
+/* Device bytes that dash_create allocates for cfg (the admission footprint of
+ * a served stream).  Errors: DASH_E_INVALID_ARG. */
+dash_status dash_footprint(const dash_config *cfg, int64_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Serving: many independent streams (one context each, each on a HIP stream
+ * of its own) on one device.  Every stream is an irregular tensor of its own
+ * with its own J, R and lambda (Problem 1 per stream); streams share nothing,
+ * so a stream's results are bit for bit those it would have alone.
+ * ------------------------------------------------------------------------- */
+typedef struct dash_server dash_server;
+
+typedef struct dash_server_report {
+  int32_t stream;      /* stream id                                              */
+  int32_t committed;   /* as dash_update_report.committed                       */
+  int64_t step;        /* the stream's update index                              */
+  int64_t rows;        /* rows the update consumed                               */
+  double fit;          /* the stream's fit after the update                      */
+  double latency_us;   /* host time from the tick that cut the update to the
+                          poll that saw it committed                             */
+} dash_server_report;
+
+/* A server on `device` whose streams may together allocate at most
+ * budget_bytes of device memory.  Errors: DASH_E_INVALID_ARG,
+ * DASH_E_OUT_OF_MEMORY. */
+dash_status dash_server_create(int32_t device, int64_t budget_bytes, dash_server **out);
+/* Close every stream (waiting for their work) and free the server. */
+dash_status dash_server_destroy(dash_server *srv);
+/* Admit a stream: if its footprint (dash_footprint) fits the unused budget,
+ * create its context (cfg->device and cfg->stream are replaced by the
+ * server's) and return its id; otherwise DASH_E_CAPACITY and nothing changes
+ * (retry once streams have closed).  Other errors as dash_create. */
+dash_status dash_server_open(dash_server *srv, const dash_config *cfg, int32_t *stream);
+/* Close a stream: wait for its work, free its context, return its budget. */
+dash_status dash_server_close(dash_server *srv, int32_t stream);
+/* The context of a stream (dash_init*, dash_ingest_*, dash_get_* are called on
+ * it directly; dash_update* / dash_wait / dash_poll are left to the server),
+ * or NULL for an unknown or closed id. */
+dash_ctx *dash_server_context(dash_server *srv, int32_t stream);
+/* One scheduling tick: every open stream with staged rows gets one update
+ * enqueued (all of them run concurrently); rows staged after the tick go to
+ * the next one.  *launched (may be NULL) receives the count.  Returns the first
+ * error of a stream (its message is in dash_last_error of its context); the
+ * other streams are still served. */
+dash_status dash_server_tick(dash_server *srv, int32_t *launched);
+/* Collect finished updates (wait = 0: those done now; wait = 1: everything in
+ * flight) into out[0 .. *n), at most cap.  A stream whose update was rolled
+ * back reports it with committed = 0 and loses the updates enqueued after it;
+ * the first such status is returned. */
+dash_status dash_server_poll(dash_server *srv, int32_t wait, dash_server_report *out, int32_t cap,
+                             int32_t *n);
+
 #ifdef __cplusplus
 }
 #endif

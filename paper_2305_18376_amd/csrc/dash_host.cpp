@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -91,6 +92,7 @@ struct dash_ctx {
   std::vector<PendingGroup> pending;
   int64_t rows_pending = 0;
   std::deque<InFlight> inflight;
+  hipEvent_t done_ev[kReportRing] = {};   // recorded after each update's launches (by report slot)
   int chunk_override = 0;
   std::vector<int> order;  // scratch
   // profiling: event pairs around launches, folded into stats on read
@@ -318,6 +320,24 @@ dash_status validate_ptr(dash_ctx *c, const int64_t *ptr, int64_t n, bool nonemp
   return DASH_OK;
 }
 
+// Device bytes a context with this configuration allocates at creation.
+int64_t context_footprint(const dash_config *cfg) {
+  const int64_t R = cfg->R, Kc = cfg->max_slices;
+  const int64_t YS = y_stride(cfg->J, cfg->R);
+  const int64_t n_chunks_cap = std::min<int64_t>(Kc, kMaxChunks);
+  const int64_t plen = partial_len(cfg->J, cfg->R);
+  const int64_t G_cap = cfg->max_groups_per_update + Kc;
+  auto al = [](int64_t b) { return (b < 256 ? 256 : b + 255) / 256 * 256; };
+  const int64_t step_bytes = (int64_t)align_up(
+      align_up(align_up(sizeof(StepHeader), 64) + sizeof(int32_t) * (n_chunks_cap + 1), 64) +
+          sizeof(Group) * G_cap, 256);
+  return al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) + al(8 * 2 * Kc) + al(2 * Kc) + al(4 * 2 * Kc) +
+         al(8 * 2 * Kc * R) + al(2 * (int64_t)vb_bytes(cfg->J, cfg->R)) + al(sizeof(Ctl)) +
+         al(4 * cfg->max_rows_per_update * R) + al(8 * n_chunks_cap * plen) +
+         al(8 * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) +
+         al(4 * (kMaxChunks + 1)) + al(8 * (Kc + 1)) + kStages * al(step_bytes);
+}
+
 dash_status read_ctl(dash_ctx *c, Ctl *out) {
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   HIP_OR_FAIL(c, hipMemcpy(out, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
@@ -462,6 +482,8 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   }
   if (hipHostMalloc((void **)&c->hreport, sizeof(Report) * kReportRing, hipHostMallocMapped) != hipSuccess)
     return bail(DASH_E_OUT_OF_MEMORY);
+  for (auto &e : c->done_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail(DASH_E_DEVICE);
   std::memset(c->hreport, 0, sizeof(Report) * kReportRing);
   if (hipHostGetDevicePointer((void **)&c->dreport, c->hreport, 0) != hipSuccess) return bail(DASH_E_DEVICE);
   if (hipMemsetAsync(c->Y, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess ||
@@ -502,6 +524,8 @@ dash_status dash_destroy(dash_ctx *c) {
     if (c->stage_ev[s]) (void)hipEventDestroy(c->stage_ev[s]);
   }
   if (c->hreport) (void)hipHostFree(c->hreport);
+  for (auto &e : c->done_ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -780,6 +804,7 @@ dash_status dash_update_async(dash_ctx *c) {
   HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
   c->profiling = false;
+  HIP_OR_FAIL(c, hipEventRecord(c->done_ev[slot], c->stream));
   c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
   c->K_enq = K;
   c->step_enq = step;
@@ -840,6 +865,47 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
               (long long)failed_step);
   }
   return st;
+}
+
+dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_t *n_done) {
+  if (!c || !n_done || cap < 0 || (cap > 0 && !reps)) return DASH_E_INVALID_ARG;
+  *n_done = 0;
+  while (!c->inflight.empty() && *n_done < cap) {
+    const InFlight f = c->inflight.front();
+    const hipError_t q = hipEventQuery(c->done_ev[f.slot]);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) return fail(c, DASH_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
+    const Report &r = c->hreport[f.slot];
+    if (!r.committed) {
+      // the rollback needs the stream idle: drain like dash_wait, report the failed update
+      dash_update_report last{};
+      const dash_status st = dash_wait(c, &last);
+      reps[(*n_done)++] = last;
+      return st;
+    }
+    c->inflight.pop_front();
+    c->K = f.K_after;
+    c->step = f.step;
+    c->m_last = f.rows;
+    dash_update_report &o = reps[(*n_done)++];
+    o.step = r.step;
+    o.rows = r.rows;
+    o.K = r.K;
+    o.committed = 1;
+    o.fit = r.fit;
+    o.loss = r.loss;
+    o.sum_n = r.sum_n;
+  }
+  return DASH_OK;
+}
+
+dash_status dash_footprint(const dash_config *cfg, int64_t *bytes) {
+  if (!cfg || !bytes) return DASH_E_INVALID_ARG;
+  if (cfg->J < 1 || cfg->J > kMaxJ || cfg->R < 1 || cfg->R > kMaxR || cfg->max_slices < 1 ||
+      cfg->max_rows_per_update < 1 || cfg->max_groups_per_update < 1)
+    return DASH_E_INVALID_ARG;
+  *bytes = context_footprint(cfg);
+  return DASH_OK;
 }
 
 dash_status dash_update(dash_ctx *c, dash_update_report *rep) {
@@ -1058,6 +1124,140 @@ dash_status dash_load(dash_ctx *c, const char *path) {
   c->pending.clear();
   c->rows_pending = 0;
   return DASH_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Serving: many streams (contexts) on one device
+// ---------------------------------------------------------------------------
+struct dash_server {
+  int device = 0;
+  int64_t budget = 0, used = 0;
+  struct Stream {
+    dash_ctx *ctx = nullptr;
+    int64_t footprint = 0;
+    std::deque<double> cuts;   // host time (us) at which each in-flight update was cut
+  };
+  std::vector<Stream> streams;
+};
+
+static double now_us() {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+dash_status dash_server_create(int32_t device, int64_t budget_bytes, dash_server **out) {
+  if (!out || budget_bytes < 0) return DASH_E_INVALID_ARG;
+  dash_server *srv = new (std::nothrow) dash_server();
+  if (!srv) return DASH_E_OUT_OF_MEMORY;
+  srv->device = device;
+  srv->budget = budget_bytes;
+  *out = srv;
+  return DASH_OK;
+}
+
+dash_status dash_server_destroy(dash_server *srv) {
+  if (!srv) return DASH_OK;
+  for (auto &st : srv->streams)
+    if (st.ctx) dash_destroy(st.ctx);
+  delete srv;
+  return DASH_OK;
+}
+
+dash_status dash_server_open(dash_server *srv, const dash_config *cfg, int32_t *stream) {
+  if (!srv || !cfg || !stream) return DASH_E_INVALID_ARG;
+  int64_t fp = 0;
+  if (dash_status s = dash_footprint(cfg, &fp)) return s;
+  if (srv->used + fp > srv->budget) return DASH_E_CAPACITY;   // admission: caller may retry later
+  dash_config c2 = *cfg;
+  c2.device = srv->device;
+  c2.stream = nullptr;   // every stream gets a HIP stream of its own
+  dash_ctx *ctx = nullptr;
+  if (dash_status s = dash_create(&c2, &ctx)) return s;
+  int32_t id = -1;
+  for (size_t i = 0; i < srv->streams.size(); ++i)
+    if (!srv->streams[i].ctx) {
+      id = (int32_t)i;
+      break;
+    }
+  if (id < 0) {
+    srv->streams.emplace_back();
+    id = (int32_t)srv->streams.size() - 1;
+  }
+  srv->streams[id].ctx = ctx;
+  srv->streams[id].footprint = fp;
+  srv->streams[id].cuts.clear();
+  srv->used += fp;
+  *stream = id;
+  return DASH_OK;
+}
+
+dash_status dash_server_close(dash_server *srv, int32_t stream) {
+  if (!srv || stream < 0 || stream >= (int32_t)srv->streams.size() || !srv->streams[stream].ctx)
+    return DASH_E_INVALID_ARG;
+  auto &st = srv->streams[stream];
+  dash_destroy(st.ctx);
+  srv->used -= st.footprint;
+  st = dash_server::Stream{};
+  return DASH_OK;
+}
+
+dash_ctx *dash_server_context(dash_server *srv, int32_t stream) {
+  if (!srv || stream < 0 || stream >= (int32_t)srv->streams.size()) return nullptr;
+  return srv->streams[stream].ctx;
+}
+
+dash_status dash_server_tick(dash_server *srv, int32_t *launched) {
+  if (!srv) return DASH_E_INVALID_ARG;
+  int32_t n = 0;
+  dash_status first = DASH_OK;
+  for (auto &st : srv->streams) {
+    dash_ctx *c = st.ctx;
+    if (!c || !c->initialized || c->rows_pending == 0) continue;
+    const double t = now_us();
+    const dash_status s = dash_update_async(c);
+    if (s != DASH_OK) {
+      if (first == DASH_OK) first = s;
+      continue;
+    }
+    st.cuts.push_back(t);
+    ++n;
+  }
+  if (launched) *launched = n;
+  return first;
+}
+
+dash_status dash_server_poll(dash_server *srv, int32_t wait, dash_server_report *out, int32_t cap,
+                             int32_t *n) {
+  if (!srv || !n || cap < 0 || (cap > 0 && !out)) return DASH_E_INVALID_ARG;
+  *n = 0;
+  dash_status first = DASH_OK;
+  for (size_t id = 0; id < srv->streams.size() && *n < cap; ++id) {
+    auto &st = srv->streams[id];
+    if (!st.ctx || st.cuts.empty()) continue;
+    if (wait && hipStreamSynchronize(st.ctx->stream) != hipSuccess) {
+      if (first == DASH_OK) first = DASH_E_DEVICE;
+      continue;
+    }
+    dash_update_report reps[kReportRing];
+    int32_t got = 0;
+    const dash_status s = dash_poll(st.ctx, reps, std::min<int32_t>(kReportRing, cap - *n), &got);
+    const double t = now_us();
+    for (int32_t i = 0; i < got && !st.cuts.empty(); ++i) {
+      dash_server_report &o = out[(*n)++];
+      o.stream = (int32_t)id;
+      o.committed = reps[i].committed;
+      o.step = reps[i].step;
+      o.rows = reps[i].rows;
+      o.fit = reps[i].fit;
+      o.latency_us = t - st.cuts.front();
+      st.cuts.pop_front();
+    }
+    if (s != DASH_OK) {   // rolled back: every update of the stream that was in flight is gone
+      st.cuts.clear();
+      if (first == DASH_OK) first = s;
+    }
+  }
+  return first;
 }
 
 }  // extern "C"

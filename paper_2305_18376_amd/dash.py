@@ -61,6 +61,14 @@ class Dims(C.Structure):
                 ("initialized", C.c_int32)]
 
 
+class ServerReport(C.Structure):
+    _fields_ = [("stream", C.c_int32), ("committed", C.c_int32), ("step", C.c_int64), ("rows", C.c_int64),
+                ("fit", C.c_double), ("latency_us", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = C.c_void_p
 _SIGS = {
     "dash_config_default": (None, [C.POINTER(DashConfig), C.c_int32, C.c_int32]),
@@ -83,6 +91,15 @@ _SIGS = {
     "dash_profile_read": (C.c_int, [_P, C.POINTER(ProfileStats)]),
     "dash_status_string": (C.c_char_p, [C.c_int]),
     "dash_last_error": (C.c_char_p, [_P]),
+    "dash_poll": (C.c_int, [_P, C.POINTER(UpdateReport), C.c_int32, C.POINTER(C.c_int32)]),
+    "dash_footprint": (C.c_int, [C.POINTER(DashConfig), C.POINTER(C.c_int64)]),
+    "dash_server_create": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(_P)]),
+    "dash_server_destroy": (C.c_int, [_P]),
+    "dash_server_open": (C.c_int, [_P, C.POINTER(DashConfig), C.POINTER(C.c_int32)]),
+    "dash_server_close": (C.c_int, [_P, C.c_int32]),
+    "dash_server_context": (_P, [_P, C.c_int32]),
+    "dash_server_tick": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "dash_server_poll": (C.c_int, [_P, C.c_int32, C.POINTER(ServerReport), C.c_int32, C.POINTER(C.c_int32)]),
 }
 
 _lib = None
@@ -101,6 +118,32 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def make_config(J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20, max_groups=65536,
+                max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10, device=0, precision=PREC_FP32):
+    cfg = DashConfig()
+    lib().dash_config_default(C.byref(cfg), J, R)
+    cfg.lam = lam
+    cfg.n_iter = n_iter
+    cfg.max_slices = max_slices
+    cfg.max_rows_per_update = max_rows
+    cfg.max_groups_per_update = max_groups
+    cfg.max_init_rows = max_init_rows
+    cfg.init_max_iter = init_max_iter
+    cfg.init_tol = init_tol
+    cfg.precision = precision
+    cfg.device = device
+    return cfg
+
+
+def footprint(**kw):
+    """Device bytes of a context with these settings (make_config's keywords)."""
+    b = C.c_int64()
+    st = lib().dash_footprint(C.byref(make_config(**kw)), C.byref(b))
+    if st != OK:
+        raise DashError(st, "dash_footprint")
+    return b.value
 
 
 class DashError(RuntimeError):
@@ -129,21 +172,17 @@ class Dash:
 
     def __init__(self, J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20,
                  max_groups=65536, max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10,
-                 device=0, stream=None, precision=PREC_FP32):
+                 device=0, stream=None, precision=PREC_FP32, _handle=None):
+        if _handle is not None:   # a context owned by a DashServer
+            self._h, self._owned = _handle, False
+            self.J, self.R, self.device = J, R, device
+            self._borrowed = []
+            return
+        self._owned = True
+        cfg = make_config(J, R, lam, n_iter, max_slices, max_rows, max_groups, max_init_rows, init_max_iter,
+                          init_tol, device, precision)
         import torch
         L = lib()
-        cfg = DashConfig()
-        L.dash_config_default(C.byref(cfg), J, R)
-        cfg.lam = lam
-        cfg.n_iter = n_iter
-        cfg.max_slices = max_slices
-        cfg.max_rows_per_update = max_rows
-        cfg.max_groups_per_update = max_groups
-        cfg.max_init_rows = max_init_rows
-        cfg.init_max_iter = init_max_iter
-        cfg.init_tol = init_tol
-        cfg.precision = precision
-        cfg.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
         cfg.stream = stream
@@ -164,7 +203,8 @@ class Dash:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().dash_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lib().dash_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -218,6 +258,15 @@ class Dash:
     def update_async(self):
         self._check(lib().dash_update_async(self._h), "dash_update_async")
 
+    def poll(self, cap=64):
+        """Reports of the enqueued updates that have finished (non-blocking)."""
+        reps = (UpdateReport * cap)()
+        n = C.c_int32()
+        st = lib().dash_poll(self._h, reps, cap, C.byref(n))
+        out = [reps[i].as_dict() for i in range(n.value)]
+        self._check(st, "dash_poll")
+        return out
+
     def wait(self):
         rep = UpdateReport()
         st = lib().dash_wait(self._h, C.byref(rep))
@@ -269,3 +318,71 @@ class Dash:
 
     def load(self, path):
         self._check(lib().dash_load(self._h, str(path).encode()), "dash_load")
+
+
+class DashServer:
+    """Many streams on one device (the serving layer of the library)."""
+
+    def __init__(self, budget_bytes, device=0):
+        h = _P()
+        st = lib().dash_server_create(device, int(budget_bytes), C.byref(h))
+        if st != OK:
+            raise DashError(st, "dash_server_create")
+        self._h = h
+        self.device = device
+        self._streams = {}
+
+    def open(self, J, R, **kw):
+        """Admit a stream; returns (id, Dash view of its context) or raises DashError
+        with status E_CAPACITY when its footprint does not fit the unused budget."""
+        cfg = make_config(J, R, device=self.device, **kw)
+        sid = C.c_int32()
+        st = lib().dash_server_open(self._h, C.byref(cfg), C.byref(sid))
+        if st != OK:
+            raise DashError(st, "dash_server_open")
+        g = Dash(J, R, device=self.device, _handle=lib().dash_server_context(self._h, sid.value))
+        self._streams[sid.value] = g
+        return sid.value, g
+
+    def close_stream(self, sid):
+        g = self._streams.pop(sid)
+        g._h = None
+        st = lib().dash_server_close(self._h, sid)
+        if st != OK:
+            raise DashError(st, "dash_server_close")
+
+    def tick(self):
+        n = C.c_int32()
+        st = lib().dash_server_tick(self._h, C.byref(n))
+        if st != OK:
+            raise DashError(st, "dash_server_tick")
+        for g in self._streams.values():
+            g._inflight_borrowed = getattr(g, "_inflight_borrowed", []) + g._borrowed
+            g._borrowed = []
+        return n.value
+
+    def poll(self, wait=False, cap=4096):
+        out = (ServerReport * cap)()
+        n = C.c_int32()
+        st = lib().dash_server_poll(self._h, 1 if wait else 0, out, cap, C.byref(n))
+        reps = [out[i].as_dict() for i in range(n.value)]
+        if wait:
+            for g in self._streams.values():
+                g._inflight_borrowed = []
+        if st != OK:
+            raise DashError(st, "dash_server_poll")
+        return reps
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for g in self._streams.values():
+                g._h = None
+            lib().dash_server_destroy(self._h)
+            self._h = None
+            self._streams = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

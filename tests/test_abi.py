@@ -68,3 +68,27 @@ def test_null_arguments():
     assert L.dash_update(None, None) == D.E_INVALID_ARG
     assert L.dash_get_dims(None, None) == D.E_INVALID_ARG
     assert L.dash_last_error(None) == b""
+
+
+def test_footprint_and_admission_without_a_device():
+    """Admission is decided from the footprint before any device call."""
+    import ctypes as C
+    small = D.make_config(32, 8, max_slices=1000, max_rows=10000, max_groups=1000)
+    big = D.make_config(32, 8, max_slices=100000, max_rows=10000, max_groups=1000)
+    a, b = C.c_int64(), C.c_int64()
+    assert D.lib().dash_footprint(C.byref(small), C.byref(a)) == D.OK
+    assert D.lib().dash_footprint(C.byref(big), C.byref(b)) == D.OK
+    assert 0 < a.value < b.value
+    # the state alone: 2 buffers of Y, D, n, W per slice
+    ys = (8 * 32 + 63) // 64 * 64
+    assert a.value >= 2 * 1000 * (ys * 4 + 64 * 4 + 8 + 8 * 8)
+    bad = D.make_config(32, 8)
+    bad.R = 0
+    assert D.lib().dash_footprint(C.byref(bad), C.byref(a)) == D.E_INVALID_ARG
+    srv = C.c_void_p()
+    assert D.lib().dash_server_create(0, a.value - 1, C.byref(srv)) == D.OK
+    sid = C.c_int32(-1)
+    assert D.lib().dash_server_open(srv, C.byref(small), C.byref(sid)) == D.E_CAPACITY
+    assert sid.value == -1
+    assert D.lib().dash_server_context(srv, 0) is None
+    assert D.lib().dash_server_destroy(srv) == D.OK
