@@ -30,6 +30,18 @@ METRIC = "ingested rows/sec at fit within 1e-3 of FP64 oracle; p50/p99 update la
 HBM_PEAK_GBS = 8000.0
 
 
+WORKLOAD_TEXT = {
+    "mid": "mid dual-way stream: K0=2000 slices, I_k lognormal(median 800, clip 100..4000), "
+           "J=88, R=10, +U{1..20} rows/slice and +20 slices per update, lambda=0.95, 1 ALS pass",
+    "batch_r10": "batching stream: K0=20000 slices, J=128, R=10, per update truncated-Zipf(1.2) rows per slice "
+                 "(0..200, mean 21.4) and 20 new slices, lambda=0.95, 1 ALS pass",
+    "batch_r20": "batching stream: K0=20000 slices, J=128, R=20, per update truncated-Zipf(1.2) rows per slice "
+                 "(0..200, mean 21.4) and 20 new slices, lambda=0.95, 1 ALS pass",
+    "precision": "precision stream: K0=20000 slices, J=256, R=32, Student-t(3) rows and noise, column scales "
+                 "10^U[-3,3], Zipf(1.2) arrivals, lambda=0.95, 1 ALS pass",
+}
+
+
 def algorithmic_bytes(M, K, K_t, J, R):
     """Bytes one update pass must move (the per-pass model of the design notes):
     new rows read, U_new written, every slice's Y_k / D_k / n_k / W row read,
@@ -72,8 +84,14 @@ def counter_traffic(kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=90)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None, help="timed updates (mid: 90, others: 20)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up updates (mid: 10, others: 3)")
+    ap.add_argument("--workload", default="mid", choices=["mid", "batch_r10", "batch_r20", "precision"],
+                    help="mid is the headline workload; the others are the batching and precision ones "
+                         "(their initial slices are shorter: the per-update cost does not depend on them)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: replay each update's launches from one HIP graph; 0: launch directly")
     ap.add_argument("--sample-every", type=int, default=10,
                     help="time the kernels of every N-th update with HIP events (events perturb "
                          "the launches they bracket, so the others run undisturbed)")
@@ -100,9 +118,16 @@ def main():
     from paper_2305_18376_amd.dash import Dash
     from paper_2305_18376_amd.synth import make_workload
 
-    W_, K_ = args.warmup, args.steps
+    big = args.workload != "mid"
+    W_ = args.warmup if args.warmup is not None else (3 if big else 10)
+    K_ = args.steps if args.steps is not None else (20 if big else 90)
     n_total = W_ + K_
-    wl = make_workload("mid", n_steps=max(100, n_total))
+    if big:
+        # initial slices of log-normal length median 24 (the update cost depends on K, not on them)
+        wl = make_workload(args.workload, n_steps=n_total, median=24, lo=1, hi=200)
+        wl.init_len = np.maximum(wl.init_len, wl.R + 1)
+    else:
+        wl = make_workload("mid", n_steps=max(100, n_total))
     t0 = time.time()
     ptr, X, U = wl.init_data(want_u=True)
     batches = [wl.step(s) for s in range(1, n_total + 1)]
@@ -110,10 +135,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    from paper_2305_18376_amd.dash import PREC_FP32, PREC_MIXED
+    max_rows = max(64 * 1024, max(b.M for b in batches) + 1)
+    max_groups = max(8192, max(b.n_groups + b.n_new for b in batches) + 1)
     g = Dash(wl.J, wl.R, lam=wl.lam, n_iter=wl.n_iter, max_slices=wl.K_max + 64,
-             max_rows=64 * 1024, max_groups=8192)
+             max_rows=max_rows, max_groups=max_groups,
+             precision=PREC_MIXED if args.precision == "mixed" else PREC_FP32)
     Xd, Ud = to(X), to(U)
     g.init_from_factors(ptr, Xd, Ud, to(wl.W[: wl.K0]), to(wl.V))
+    g.graph(bool(args.graph))
     del Xd, Ud
     dbat = []
     for b in batches:
@@ -134,16 +164,14 @@ def main():
     # timed region
     stream = torch.cuda.current_stream(dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K_)]
     g.profile(args.sample_every)
+    g.spans(True)   # per-update device spans with timing-only events (p50 / p99)
     torch.cuda.synchronize()
     h0 = time.perf_counter()
     ev0.record(stream)
     for i in range(K_):
-        step_ev[i][0].record(stream)
         stage(W_ + i)
         g.update_async()
-        step_ev[i][1].record(stream)
     ev1.record(stream)
     last = g.wait()
     torch.cuda.synchronize()
@@ -159,7 +187,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     dev_ms = ev0.elapsed_time(ev1)
-    lat = np.array([a.elapsed_time(b) for a, b in step_ev])
+    lat = g.spans_read()
+    g.spans(False)
     rows = sum(batches[W_ + i].M for i in range(K_))
     value = rows / (dev_ms / 1e3)
 
@@ -186,16 +215,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16-mfma/f32",
         "data": "synthetic",
-        "config": {"workload": "mid dual-way stream: K0=2000 slices, I_k lognormal(median 800, clip 100..4000), "
-                               "J=88, R=10, +U{1..20} rows/slice and +20 slices per update, lambda=0.95, 1 ALS pass",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "K_final": wl.K_at(n_total), "rows_timed": rows},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "note": "per-update device span, back-to-back updates"},
         "host_ms_per_step": (h1 - h0) * 1e3 / K_,
         "kernel_us_avg": {k: (1e3 * prof[k + "_ms"] / prof[k + "_launches"]) if prof[k + "_launches"] else None
                           for k in ("pass", "solve", "upload")},
+        "launch": "hip graph (node parameters rewritten per update)" if args.graph else "direct",
         "kernel_timing": f"HIP events around the launches of every {args.sample_every}-th update "
                          f"({prof['updates']} sampled)",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -75,6 +75,8 @@ typedef struct dash_update_report {
   double fit;        /* 1 - sqrt(loss)/sqrt(sum_n) after the update                 */
   double loss;       /* eq. [new_loss] with compounding weights, closed form        */
   double sum_n;      /* sum over slices of the forgetting-weighted squared norms    */
+  double device_us;  /* device time of the update: from its first launch starting
+                        to its final phase ending (device realtime clock)       */
 } dash_update_report;
 
 typedef struct dash_init_report {
@@ -223,6 +225,21 @@ const char *dash_last_error(const dash_ctx *ctx);
  * reports that update last and returns DASH_E_NUMERIC.  reports is host memory
  * (may be NULL when cap == 0). */
 dash_status dash_poll(dash_ctx *ctx, dash_update_report *reports, int32_t cap, int32_t *n_done);
+
+/* Graph mode (enable = 1): each update's launches -- descriptor fetch, the
+ * n_iter sweeps and final phases -- are replayed from one executable HIP graph
+ * captured at the first update, with every kernel node's grid and arguments
+ * rewritten for the update at hand (no allocation, no memset node).  Updates
+ * that dash_profile times are launched directly.  Waits for the context's
+ * work; enable = 0 drops the graph. */
+dash_status dash_graph(dash_ctx *ctx, int32_t enable);
+
+/* Per-update device spans: with dash_spans(ctx, 1) the device_us of every
+ * update reaped from then on by dash_update, dash_wait or dash_poll is kept;
+ * dash_spans_read copies them (milliseconds, in update order), at most cap.
+ * dash_spans(ctx, 0) stops; either call clears the list. */
+dash_status dash_spans(dash_ctx *ctx, int32_t enable);
+dash_status dash_spans_read(dash_ctx *ctx, float *ms, int32_t cap, int32_t *n);
 
 /* Device bytes that dash_create allocates for cfg (the admission footprint of
  * a served stream).  Errors: DASH_E_INVALID_ARG. */

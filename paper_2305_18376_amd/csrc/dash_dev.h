@@ -58,8 +58,10 @@ struct Report {
   int64_t step, rows;
   int32_t K, committed;
   double fit, loss, sum_n;
+  uint64_t t_start, t_end;   // device realtime clock (100 MHz) at the update's first and last launch
   int32_t done, pad;
 };
+constexpr double kRealtimeMHz = 100.0;
 
 // One "V bundle": everything a pass needs from V, double-buffered.
 //   V64  [J][R]  float64 master
@@ -121,6 +123,7 @@ struct PassArgs {
   int32_t *counters;   // [kMaxChunks + 1] arrival tickets (the last one: all groups), zero between launches
   int fuse;            // the last workgroup to arrive runs the final phase in the same launch
   int mixed;           // 1: Lemma 1 and the row accumulation on BF16 MFMA (FP32 sums)
+  int stamp_start;     // 1: the first pass's workgroup 0 stamps the report's start time
   int lds_bytes;       // dynamic LDS of the sweep launch
 };
 
@@ -167,7 +170,17 @@ int pass_chunk(int variant, int K, int n_cu);
 int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s);
 // Copy bytes (a multiple of 16 not required) from a device-visible pinned host
 // block to device memory with a kernel on stream s.
-int launch_fetch(const char *src_mapped, char *dst, size_t bytes, hipStream_t s);
+int launch_fetch(const char *src_mapped, char *dst, size_t bytes, void *report, hipStream_t s);
+// The fetch kernel's arguments and grid for bytes (for rewriting a graph node).
+struct FetchArgs {
+  const void *src, *src_tail;
+  void *dst, *dst_tail;
+  int64_t n16;
+  int tail;
+  void *report;   // Report of the update (its start time is written), or NULL
+  unsigned grid;
+};
+FetchArgs fetch_args(const char *src_mapped, char *dst, size_t bytes, void *report);
 // Dynamic LDS of a sweep launch that also runs the final phase, or 0 when the
 // two do not fit one workgroup.
 size_t fused_pass_lds(int variant, int J, int R);

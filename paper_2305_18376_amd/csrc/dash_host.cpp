@@ -92,7 +92,18 @@ struct dash_ctx {
   std::vector<PendingGroup> pending;
   int64_t rows_pending = 0;
   std::deque<InFlight> inflight;
-  hipEvent_t done_ev[kReportRing] = {};   // recorded after each update's launches (by report slot)
+  // graph mode: an update's launches (descriptor fetch, n_iter sweeps, final
+  // phases) replayed from an instantiated graph whose kernel-node parameters
+  // (grid sizes, descriptor pointers) are rewritten for every update.  One
+  // graph per descriptor stage: a stage is reused only after the update that
+  // last used it has completed, so no graph is rewritten while in flight.
+  bool graph_on = false;
+  hipGraph_t graph[kStages] = {};
+  hipGraphExec_t gexec[kStages] = {};
+  std::vector<hipGraphNode_t> gnodes[kStages];      // kernel nodes in launch order
+  std::vector<hipKernelNodeParams> gparams[kStages];   // their captured parameters
+  bool spans_on = false;                   // collect every reaped update's device span
+  std::vector<float> spans;                // spans (ms) of the reaped updates
   int chunk_override = 0;
   std::vector<int> order;  // scratch
   // profiling: event pairs around launches, folded into stats on read
@@ -205,11 +216,11 @@ hipError_t take_stage(dash_ctx *c, int *idx) {
 // reads the pinned block through its device mapping, so the update's kernels
 // follow it on the same queue without a copy-engine round trip.  The block is
 // free for the host again once stage_ev[s] has completed.
-hipError_t upload_stage(dash_ctx *c, int s, size_t bytes, bool profile) {
+hipError_t upload_stage(dash_ctx *c, int s, size_t bytes, bool profile, void *report) {
   hipError_t e = hipSuccess;
   if (!c->desc_fetch) return e;   // the kernels read the pinned block in place (see stage_done)
   if (profile) e = prof_begin(c, kProfUpload);
-  if (e == hipSuccess) e = (hipError_t)launch_fetch(c->hstage_dev[s], c->dstep[s], bytes, c->stream);
+  if (e == hipSuccess) e = (hipError_t)launch_fetch(c->hstage_dev[s], c->dstep[s], bytes, report, c->stream);
   if (e == hipSuccess && profile) e = prof_end(c);
   if (e == hipSuccess) e = hipEventRecord(c->stage_ev[s], c->stream);
   c->stage_used[s] = true;
@@ -251,6 +262,7 @@ PassArgs base_args(const dash_ctx *c, int s) {
   a.counters = c->counters;
   a.fuse = c->fused_lds > 0 ? 1 : 0;
   a.mixed = c->cfg.precision == DASH_PREC_MIXED ? 1 : 0;
+  a.stamp_start = c->desc_fetch ? 0 : 1;
   a.lds_bytes = c->fused_lds;
   return a;
 }
@@ -278,7 +290,7 @@ dash_status enqueue_eval(dash_ctx *c, int K) {
   int32_t *gptr = (int32_t *)(blk + c->off_gptr);
   for (int i = 0; i <= nch; ++i) gptr[i] = 0;
   const size_t bytes = c->off_gptr + sizeof(int32_t) * (nch + 1);
-  HIP_OR_FAIL(c, upload_stage(c, s, bytes, false));
+  HIP_OR_FAIL(c, upload_stage(c, s, bytes, false, nullptr));
   PassArgs a = base_args(c, s);
   a.pass = 0;
   a.last_pass = 0;
@@ -336,6 +348,117 @@ int64_t context_footprint(const dash_config *cfg) {
          al(4 * cfg->max_rows_per_update * R) + al(8 * n_chunks_cap * plen) +
          al(8 * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) +
          al(4 * (kMaxChunks + 1)) + al(8 * (Kc + 1)) + kStages * al(step_bytes);
+}
+
+// Device time of an update from its report's realtime stamps (microseconds).
+double device_us(const Report &r) {
+  return (r.t_end > r.t_start && r.t_start) ? (double)(r.t_end - r.t_start) / kRealtimeMHz : 0.0;
+}
+
+void graph_reset(dash_ctx *c) {
+  for (int s = 0; s < kStages; ++s) {
+    if (c->gexec[s]) (void)hipGraphExecDestroy(c->gexec[s]);
+    if (c->graph[s]) (void)hipGraphDestroy(c->graph[s]);
+    c->gexec[s] = nullptr;
+    c->graph[s] = nullptr;
+    c->gnodes[s].clear();
+    c->gparams[s].clear();
+  }
+}
+
+// Enqueue the launches of one update (stage s, descriptor bytes, nch chunks)
+// as a graph.  The first call captures fetch -> (sweep [-> final phase]) x n_iter
+// and instantiates it; later calls rewrite every kernel node's grid and
+// arguments for this update and relaunch the same executable graph.
+dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report) {
+  const int n_iter = c->cfg.n_iter;
+  PassArgs base = base_args(c, s);
+  base.mode = 0;
+  std::vector<PassArgs> args(n_iter, base);
+  for (int p = 0; p < n_iter; ++p) {
+    args[p].pass = p;
+    args[p].last_pass = (p == n_iter - 1) ? 1 : 0;
+  }
+  FetchArgs fa = fetch_args(c->hstage_dev[s], c->dstep[s], bytes, report);
+  if (!c->gexec[s]) {
+    HIP_OR_FAIL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int e = launch_fetch(c->hstage_dev[s], c->dstep[s], bytes, report, c->stream);
+    for (int p = 0; p < n_iter && !e; ++p) {
+      e = launch_pass(args[p], c->variant, nch, c->stream);
+      if (!e && !base.fuse) e = launch_finish(args[p], 0, c->stream);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (e || ee != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, DASH_E_DEVICE, "graph capture failed (%d, %s)", e, hipGetErrorString(ee));
+    }
+    c->graph[s] = g;
+    size_t count = 0;
+    HIP_OR_FAIL(c, hipGraphGetNodes(g, nullptr, &count));
+    std::vector<hipGraphNode_t> nodes(count);
+    HIP_OR_FAIL(c, hipGraphGetNodes(g, nodes.data(), &count));
+    // the captured nodes form one chain: order them from the root
+    std::vector<hipGraphNode_t> chain;
+    hipGraphNode_t cur = nullptr;
+    for (auto nd : nodes) {
+      size_t ndep = 0;
+      HIP_OR_FAIL(c, hipGraphNodeGetDependencies(nd, nullptr, &ndep));
+      if (ndep == 0) cur = nd;
+    }
+    while (cur) {
+      chain.push_back(cur);
+      size_t nd = 0;
+      HIP_OR_FAIL(c, hipGraphNodeGetDependentNodes(cur, nullptr, &nd));
+      if (nd != 1) break;
+      hipGraphNode_t nx = nullptr;
+      HIP_OR_FAIL(c, hipGraphNodeGetDependentNodes(cur, &nx, &nd));
+      cur = nx;
+    }
+    const size_t expect = 1 + (size_t)n_iter * (base.fuse ? 1 : 2);
+    if (chain.size() != expect || count != expect) {
+      (void)hipGraphDestroy(g);
+      c->graph[s] = nullptr;
+      return fail(c, DASH_E_DEVICE, "captured graph has %zu nodes, expected %zu", count, expect);
+    }
+    c->gnodes[s] = chain;
+    c->gparams[s].resize(chain.size());
+    for (size_t i = 0; i < chain.size(); ++i)
+      HIP_OR_FAIL(c, hipGraphKernelNodeGetParams(chain[i], &c->gparams[s][i]));
+    HIP_OR_FAIL(c, hipGraphInstantiate(&c->gexec[s], g, nullptr, nullptr, 0));
+  } else {
+    // rewrite the nodes: fetch, then per pass the sweep (and the final phase)
+    size_t i = 0;
+    {
+      hipKernelNodeParams kp = c->gparams[s][i];
+      void *fargs[] = {&fa.src, &fa.dst, &fa.n16, &fa.src_tail, &fa.dst_tail, &fa.tail, &fa.report};
+      kp.gridDim = dim3(fa.grid);
+      kp.kernelParams = fargs;
+      HIP_OR_FAIL(c, hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kp));
+      ++i;
+    }
+    for (int p = 0; p < n_iter; ++p) {
+      hipKernelNodeParams kp = c->gparams[s][i];
+      void *pargs[] = {&args[p]};
+      kp.gridDim = dim3(nch);
+      kp.kernelParams = pargs;
+      HIP_OR_FAIL(c, hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kp));
+      ++i;
+      if (!base.fuse) {
+        hipKernelNodeParams kf = c->gparams[s][i];
+        int mode0 = 0;
+        void *fin[] = {&args[p], &mode0};
+        kf.kernelParams = fin;
+        HIP_OR_FAIL(c, hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kf));
+        ++i;
+      }
+    }
+  }
+  HIP_OR_FAIL(c, hipGraphLaunch(c->gexec[s], c->stream));
+  // the pinned block and this stage's graph are free again once the whole update ran
+  HIP_OR_FAIL(c, hipEventRecord(c->stage_ev[s], c->stream));
+  c->stage_used[s] = true;
+  return DASH_OK;
 }
 
 dash_status read_ctl(dash_ctx *c, Ctl *out) {
@@ -482,8 +605,7 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   }
   if (hipHostMalloc((void **)&c->hreport, sizeof(Report) * kReportRing, hipHostMallocMapped) != hipSuccess)
     return bail(DASH_E_OUT_OF_MEMORY);
-  for (auto &e : c->done_ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail(DASH_E_DEVICE);
+
   std::memset(c->hreport, 0, sizeof(Report) * kReportRing);
   if (hipHostGetDevicePointer((void **)&c->dreport, c->hreport, 0) != hipSuccess) return bail(DASH_E_DEVICE);
   if (hipMemsetAsync(c->Y, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess ||
@@ -524,8 +646,7 @@ dash_status dash_destroy(dash_ctx *c) {
     if (c->stage_ev[s]) (void)hipEventDestroy(c->stage_ev[s]);
   }
   if (c->hreport) (void)hipHostFree(c->hreport);
-  for (auto &e : c->done_ev)
-    if (e) (void)hipEventDestroy(e);
+  graph_reset(c);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -784,27 +905,31 @@ dash_status dash_update_async(dash_ctx *c) {
   h->M = c->rows_pending;
   h->report = (void *)(c->dreport + slot);
   c->hreport[slot].done = 0;
+  c->hreport[slot].t_start = c->hreport[slot].t_end = 0;
   const size_t bytes = c->off_groups + sizeof(Group) * ng;
-  HIP_OR_FAIL(c, upload_stage(c, s, bytes, true));
 
-  PassArgs a = base_args(c, s);
-  a.mode = 0;
-  for (int p = 0; p < c->cfg.n_iter; ++p) {
-    a.pass = p;
-    a.last_pass = (p == c->cfg.n_iter - 1) ? 1 : 0;
-    HIP_OR_FAIL(c, prof_begin(c, kProfPass));
-    LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
-    HIP_OR_FAIL(c, prof_end(c));
-    if (!a.fuse) {
-      HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
-      LAUNCH_OR_FAIL(c, launch_finish(a, 0, c->stream));
+  if (c->graph_on && !c->profiling && c->desc_fetch) {
+    if (dash_status st = graph_update(c, s, bytes, nch, h->report)) return st;
+  } else {
+    HIP_OR_FAIL(c, upload_stage(c, s, bytes, true, h->report));
+    PassArgs a = base_args(c, s);
+    a.mode = 0;
+    for (int p = 0; p < c->cfg.n_iter; ++p) {
+      a.pass = p;
+      a.last_pass = (p == c->cfg.n_iter - 1) ? 1 : 0;
+      HIP_OR_FAIL(c, prof_begin(c, kProfPass));
+      LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
       HIP_OR_FAIL(c, prof_end(c));
+      if (!a.fuse) {
+        HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
+        LAUNCH_OR_FAIL(c, launch_finish(a, 0, c->stream));
+        HIP_OR_FAIL(c, prof_end(c));
+      }
     }
   }
   HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
   c->profiling = false;
-  HIP_OR_FAIL(c, hipEventRecord(c->done_ev[slot], c->stream));
   c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
   c->K_enq = K;
   c->step_enq = step;
@@ -823,6 +948,7 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
     const InFlight f = c->inflight.front();
     c->inflight.pop_front();
     const Report &r = c->hreport[f.slot];
+    if (c->spans_on) c->spans.push_back((float)(device_us(r) * 1e-3));
     if (!failed && r.committed) {
       c->K = f.K_after;
       c->step = f.step;
@@ -835,6 +961,7 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
         rep->fit = r.fit;
         rep->loss = r.loss;
         rep->sum_n = r.sum_n;
+        rep->device_us = device_us(r);
       }
     } else if (!failed) {
       failed = true;
@@ -847,6 +974,7 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
         rep->fit = r.fit;
         rep->loss = r.loss;
         rep->sum_n = r.sum_n;
+        rep->device_us = device_us(r);
       }
     }
   }
@@ -872,10 +1000,9 @@ dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_
   *n_done = 0;
   while (!c->inflight.empty() && *n_done < cap) {
     const InFlight f = c->inflight.front();
-    const hipError_t q = hipEventQuery(c->done_ev[f.slot]);
-    if (q == hipErrorNotReady) break;
-    if (q != hipSuccess) return fail(c, DASH_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
     const Report &r = c->hreport[f.slot];
+    // the final phase writes the report, then (after a system-scope fence) done
+    if (!__atomic_load_n(&r.done, __ATOMIC_ACQUIRE)) break;
     if (!r.committed) {
       // the rollback needs the stream idle: drain like dash_wait, report the failed update
       dash_update_report last{};
@@ -884,6 +1011,7 @@ dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_
       return st;
     }
     c->inflight.pop_front();
+    if (c->spans_on) c->spans.push_back((float)(device_us(r) * 1e-3));
     c->K = f.K_after;
     c->step = f.step;
     c->m_last = f.rows;
@@ -895,7 +1023,30 @@ dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_
     o.fit = r.fit;
     o.loss = r.loss;
     o.sum_n = r.sum_n;
+    o.device_us = device_us(r);
   }
+  return DASH_OK;
+}
+
+dash_status dash_graph(dash_ctx *c, int32_t enable) {
+  if (!c) return DASH_E_INVALID_ARG;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  graph_reset(c);
+  c->graph_on = enable != 0;
+  return DASH_OK;
+}
+
+dash_status dash_spans(dash_ctx *c, int32_t enable) {
+  if (!c) return DASH_E_INVALID_ARG;
+  c->spans.clear();
+  c->spans_on = enable != 0;
+  return DASH_OK;
+}
+
+dash_status dash_spans_read(dash_ctx *c, float *ms, int32_t cap, int32_t *n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !ms)) return DASH_E_INVALID_ARG;
+  *n = (int32_t)std::min<size_t>((size_t)cap, c->spans.size());
+  std::copy(c->spans.begin(), c->spans.begin() + *n, ms);
   return DASH_OK;
 }
 

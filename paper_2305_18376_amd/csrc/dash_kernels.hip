@@ -181,6 +181,7 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   const bool commit = ok && a.ctl->ok && !a.ctl->poison;
   if (tid == 0) {
     Report *rep = (Report *)h->report;
+    rep->t_end = __builtin_amdgcn_s_memrealtime();
     rep->step = h->step;
     rep->rows = h->M;
     rep->K = h->K;
@@ -193,7 +194,9 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
     else
       a.ctl->poison = 1;
     a.ctl->ok = 1;  // reset for the next update
-    rep->done = 1;  // visible to the host once the kernel has completed
+    // the host polls `done`: every other field must be visible before it
+    __threadfence_system();
+    rep->done = 1;
   }
 }
 
@@ -338,6 +341,8 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
   const StepHeader *h = a.hdr;
   const int chunk = blockIdx.x;
   if (chunk >= h->n_chunks) return;
+  if (a.stamp_start && chunk == 0 && threadIdx.x == 0 && a.pass == 0 && a.mode == 0 && h->report)
+    ((Report *)h->report)->t_start = __builtin_amdgcn_s_memrealtime();
   const int J = a.J, R = a.R, RR = R * R, RJ = R * J, YS = a.ys;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K = h->K, Kp = h->K_prev;
@@ -804,6 +809,8 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   const StepHeader *h = a.hdr;
   const int chunk = blockIdx.x;
   if (chunk >= h->n_chunks) return;
+  if (a.stamp_start && chunk == 0 && threadIdx.x == 0 && a.pass == 0 && a.mode == 0 && h->report)
+    ((Report *)h->report)->t_start = __builtin_amdgcn_s_memrealtime();
   const int J = a.J, R = a.R;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K = h->K, Kp = h->K_prev;
@@ -1236,8 +1243,9 @@ __global__ __launch_bounds__(256) void k_accum_given_u(int J, int R, const int64
 // dst[0, bytes) = src[0, bytes); src is pinned host memory mapped for the
 // device.  16-byte words, one per thread, all loads in flight at once.
 __global__ void k_fetch(const uint4 *src, uint4 *dst, int64_t n16, const unsigned char *src_tail,
-                        unsigned char *dst_tail, int tail) {
+                        unsigned char *dst_tail, int tail, Report *rep) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0 && rep) rep->t_start = __builtin_amdgcn_s_memrealtime();
   if (i < n16) dst[i] = src[i];
   if (i < tail) dst_tail[i] = src_tail[i];
 }
@@ -1429,14 +1437,24 @@ int launch_accum_given_u(int J, int R, int K, const int64_t *rp, const float *X,
   }
 }
 
-int launch_fetch(const char *src, char *dst, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return 0;
-  const int64_t n16 = (int64_t)(bytes / 16);
-  const int tail = (int)(bytes - (size_t)n16 * 16);
-  const int64_t threads = std::max<int64_t>(n16, tail);
-  hipLaunchKernelGGL(k_fetch, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, (const uint4 *)src,
-                     (uint4 *)dst, n16, (const unsigned char *)src + n16 * 16, (unsigned char *)dst + n16 * 16,
-                     tail);
+FetchArgs fetch_args(const char *src, char *dst, size_t bytes, void *report) {
+  FetchArgs f;
+  f.report = report;
+  f.n16 = (int64_t)(bytes / 16);
+  f.tail = (int)(bytes - (size_t)f.n16 * 16);
+  f.src = src;
+  f.dst = dst;
+  f.src_tail = src + f.n16 * 16;
+  f.dst_tail = dst + f.n16 * 16;
+  const int64_t threads = std::max<int64_t>(std::max<int64_t>(f.n16, f.tail), 1);
+  f.grid = (unsigned)((threads + 255) / 256);
+  return f;
+}
+
+int launch_fetch(const char *src, char *dst, size_t bytes, void *report, hipStream_t s) {
+  const FetchArgs f = fetch_args(src, dst, bytes, report);
+  hipLaunchKernelGGL(k_fetch, dim3(f.grid), dim3(256), 0, s, (const uint4 *)f.src, (uint4 *)f.dst, f.n16,
+                     (const unsigned char *)f.src_tail, (unsigned char *)f.dst_tail, f.tail, (Report *)f.report);
   return (int)hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ class DashConfig(C.Structure):
 
 class UpdateReport(C.Structure):
     _fields_ = [("step", C.c_int64), ("rows", C.c_int64), ("K", C.c_int32), ("committed", C.c_int32),
-                ("fit", C.c_double), ("loss", C.c_double), ("sum_n", C.c_double)]
+                ("fit", C.c_double), ("loss", C.c_double), ("sum_n", C.c_double), ("device_us", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -93,6 +93,9 @@ _SIGS = {
     "dash_last_error": (C.c_char_p, [_P]),
     "dash_poll": (C.c_int, [_P, C.POINTER(UpdateReport), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_footprint": (C.c_int, [C.POINTER(DashConfig), C.POINTER(C.c_int64)]),
+    "dash_spans": (C.c_int, [_P, C.c_int32]),
+    "dash_graph": (C.c_int, [_P, C.c_int32]),
+    "dash_spans_read": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_server_create": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(_P)]),
     "dash_server_destroy": (C.c_int, [_P]),
     "dash_server_open": (C.c_int, [_P, C.POINTER(DashConfig), C.POINTER(C.c_int32)]),
@@ -257,6 +260,20 @@ class Dash:
 
     def update_async(self):
         self._check(lib().dash_update_async(self._h), "dash_update_async")
+
+    def graph(self, enable=True):
+        """Replay each update's launches from one HIP graph (node parameters rewritten per update)."""
+        self._check(lib().dash_graph(self._h, 1 if enable else 0), "dash_graph")
+
+    def spans(self, enable=True):
+        """Record (or stop recording) each update's device span."""
+        self._check(lib().dash_spans(self._h, 1 if enable else 0), "dash_spans")
+
+    def spans_read(self, cap=1 << 16):
+        buf = (C.c_float * cap)()
+        n = C.c_int32()
+        self._check(lib().dash_spans_read(self._h, buf, cap, C.byref(n)), "dash_spans_read")
+        return np.frombuffer(buf, dtype=np.float32, count=n.value).copy()
 
     def poll(self, cap=64):
         """Reports of the enqueued updates that have finished (non-blocking)."""
