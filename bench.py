@@ -90,6 +90,8 @@ def main():
                     help="mid is the headline workload; the others are the batching and precision ones "
                          "(their initial slices are shorter: the per-update cost does not depend on them)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="N > 0: the warm-up updates try every launch schedule N times and keep the fastest")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay each update's launches from one HIP graph; 0: launch directly")
     ap.add_argument("--sample-every", type=int, default=10,
@@ -120,6 +122,8 @@ def main():
 
     big = args.workload != "mid"
     W_ = args.warmup if args.warmup is not None else (3 if big else 10)
+    if args.autotune > 0:
+        W_ = max(W_, 8 * args.autotune + 2)   # at most 8 candidate schedules
     K_ = args.steps if args.steps is not None else (20 if big else 90)
     n_total = W_ + K_
     if big:
@@ -144,6 +148,8 @@ def main():
     Xd, Ud = to(X), to(U)
     g.init_from_factors(ptr, Xd, Ud, to(wl.W[: wl.K0]), to(wl.V))
     g.graph(bool(args.graph))
+    if args.autotune > 0:
+        g.autotune(args.autotune)
     del Xd, Ud
     dbat = []
     for b in batches:
@@ -225,6 +231,7 @@ def main():
         "kernel_us_avg": {k: (1e3 * prof[k + "_ms"] / prof[k + "_launches"]) if prof[k + "_launches"] else None
                           for k in ("pass", "solve", "upload")},
         "launch": "hip graph (node parameters rewritten per update)" if args.graph else "direct",
+        "schedule": g.schedule(),
         "kernel_timing": f"HIP events around the launches of every {args.sample_every}-th update "
                          f"({prof['updates']} sampled)",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

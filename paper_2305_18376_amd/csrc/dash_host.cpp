@@ -41,6 +41,16 @@ struct InFlight {
   int32_t K_prev, K_after;
   int64_t rows;
   int slot;
+  int cand;        // autotuning candidate the update ran with, or -1
+  double bytes;    // its algorithmic bytes (the autotuner's cost unit)
+};
+
+// How an update is launched: sweep variant, slices per wave (or workgroup)
+// relative to the default, and whether the final phase rides in the sweep.
+struct Schedule {
+  int variant;
+  int spread;   // 1: the default chunking; 2: twice the slices per chunk
+  int fuse;
 };
 
 }  // namespace
@@ -72,6 +82,14 @@ struct dash_ctx {
   bool desc_fetch = true;   // true: copy each descriptor to device memory first; false: kernels read it in place
   size_t off_gptr = 0, off_groups = 0, step_bytes = 0;
   int variant = kPassWave;
+  Schedule sched{kPassWave, 1, 1};         // current schedule
+  // autotuning (dash_autotune): candidates tried in turn over the next updates,
+  // each scored by device time per algorithmic byte; the best is kept
+  std::vector<Schedule> tune_cands;
+  std::vector<double> tune_us, tune_bytes;
+  std::vector<int> tune_n;
+  int tune_per = 0, tune_next = 0;
+  bool tuned = false;
   int fused_lds = 0;   // > 0: the sweep launch runs the final phase too (its dynamic LDS)
   int n_cu = 0;   // compute units of the device
   // pinned
@@ -102,6 +120,7 @@ struct dash_ctx {
   hipGraphExec_t gexec[kStages] = {};
   std::vector<hipGraphNode_t> gnodes[kStages];      // kernel nodes in launch order
   std::vector<hipKernelNodeParams> gparams[kStages];   // their captured parameters
+  Schedule gsched{-1, 0, 0};                // the schedule the graphs were captured with
   bool spans_on = false;                   // collect every reaped update's device span
   std::vector<float> spans;                // spans (ms) of the reaped updates
   int chunk_override = 0;
@@ -155,7 +174,10 @@ int choose_chunk(const dash_ctx *c, int K) {
     while ((K + ch - 1) / ch > kMaxChunks) ++ch;
     return ch;
   }
-  return pass_chunk(c->variant, K, c->n_cu);
+  const int ch = pass_chunk(c->sched.variant, K, c->n_cu) * c->sched.spread;
+  int out = std::max(1, std::min(ch, K));
+  while ((K + out - 1) / out > kMaxChunks) ++out;
+  return out;
 }
 
 StepHeader *stage_header(char *blk) { return (StepHeader *)blk; }
@@ -260,10 +282,11 @@ PassArgs base_args(const dash_ctx *c, int s) {
   a.partials = c->partials;
   a.gpart = c->gpart;
   a.counters = c->counters;
-  a.fuse = c->fused_lds > 0 ? 1 : 0;
+  const int flds = c->sched.fuse ? (int)fused_pass_lds(c->sched.variant, c->J, c->R) : 0;
+  a.fuse = flds > 0 ? 1 : 0;
   a.mixed = c->cfg.precision == DASH_PREC_MIXED ? 1 : 0;
   a.stamp_start = c->desc_fetch ? 0 : 1;
-  a.lds_bytes = c->fused_lds;
+  a.lds_bytes = flds;
   return a;
 }
 
@@ -295,7 +318,7 @@ dash_status enqueue_eval(dash_ctx *c, int K) {
   a.pass = 0;
   a.last_pass = 0;
   a.mode = 1;
-  LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
+  LAUNCH_OR_FAIL(c, launch_pass(a, c->sched.variant, nch, c->stream));
   if (!a.fuse) LAUNCH_OR_FAIL(c, launch_finish(a, 2, c->stream));
   HIP_OR_FAIL(c, stage_done(c, s));
   return DASH_OK;
@@ -355,7 +378,26 @@ double device_us(const Report &r) {
   return (r.t_end > r.t_start && r.t_start) ? (double)(r.t_end - r.t_start) / kRealtimeMHz : 0.0;
 }
 
+// Fold one reaped update into the autotuner's scores; once every candidate has
+// run tune_per times, keep the one with the least device time per byte.
+void tune_account(dash_ctx *c, const InFlight &f, const Report &r) {
+  if (f.cand < 0 || c->tuned || f.cand >= (int)c->tune_cands.size()) return;
+  const double us = device_us(r);
+  if (us <= 0.0) return;
+  c->tune_us[f.cand] += us;
+  c->tune_bytes[f.cand] += f.bytes;
+  c->tune_n[f.cand] += 1;
+  for (int n : c->tune_n)
+    if (n < c->tune_per) return;
+  int best = 0;
+  for (int i = 1; i < (int)c->tune_cands.size(); ++i)
+    if (c->tune_us[i] / c->tune_bytes[i] < c->tune_us[best] / c->tune_bytes[best]) best = i;
+  c->sched = c->tune_cands[best];
+  c->tuned = true;
+}
+
 void graph_reset(dash_ctx *c) {
+  c->gsched = Schedule{-1, 0, 0};
   for (int s = 0; s < kStages; ++s) {
     if (c->gexec[s]) (void)hipGraphExecDestroy(c->gexec[s]);
     if (c->graph[s]) (void)hipGraphDestroy(c->graph[s]);
@@ -384,7 +426,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int e = launch_fetch(c->hstage_dev[s], c->dstep[s], bytes, report, c->stream);
     for (int p = 0; p < n_iter && !e; ++p) {
-      e = launch_pass(args[p], c->variant, nch, c->stream);
+      e = launch_pass(args[p], c->sched.variant, nch, c->stream);
       if (!e && !base.fuse) e = launch_finish(args[p], 0, c->stream);
     }
     hipGraph_t g = nullptr;
@@ -557,6 +599,7 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->fused_lds = (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
   if (const char *e = std::getenv("DASH_FUSE"))
     if (std::atoi(e) == 0) c->fused_lds = 0;
+  c->sched = Schedule{c->variant, 1, c->fused_lds > 0 ? 1 : 0};
   if (const char *e = std::getenv("DASH_DESC_FETCH")) c->desc_fetch = std::atoi(e) != 0;
   if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
   auto bail = [&](dash_status s) {
@@ -856,6 +899,12 @@ dash_status dash_update_async(dash_ctx *c) {
     if (s != DASH_OK) return s;
   }
   const int K = c->K_pending, Kp = c->K_enq;
+  int cand = -1;
+  if (!c->tune_cands.empty() && !c->tuned) {
+    cand = c->tune_next % (int)c->tune_cands.size();
+    c->tune_next++;
+    c->sched = c->tune_cands[cand];
+  }
   const int ch = choose_chunk(c, K);
   const int nch = (K + ch - 1) / ch;
   int s;
@@ -908,7 +957,15 @@ dash_status dash_update_async(dash_ctx *c) {
   c->hreport[slot].t_start = c->hreport[slot].t_end = 0;
   const size_t bytes = c->off_groups + sizeof(Group) * ng;
 
-  if (c->graph_on && !c->profiling && c->desc_fetch) {
+  const bool tuning = !c->tune_cands.empty() && !c->tuned;
+  if (c->graph_on && !c->profiling && c->desc_fetch && !tuning) {
+    if (c->gsched.variant != c->sched.variant || c->gsched.spread != c->sched.spread ||
+        c->gsched.fuse != c->sched.fuse) {
+      // captured for another schedule: drop the graphs once nothing runs them
+      HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+      graph_reset(c);
+      c->gsched = c->sched;
+    }
     if (dash_status st = graph_update(c, s, bytes, nch, h->report)) return st;
   } else {
     HIP_OR_FAIL(c, upload_stage(c, s, bytes, true, h->report));
@@ -918,7 +975,7 @@ dash_status dash_update_async(dash_ctx *c) {
       a.pass = p;
       a.last_pass = (p == c->cfg.n_iter - 1) ? 1 : 0;
       HIP_OR_FAIL(c, prof_begin(c, kProfPass));
-      LAUNCH_OR_FAIL(c, launch_pass(a, c->variant, nch, c->stream));
+      LAUNCH_OR_FAIL(c, launch_pass(a, c->sched.variant, nch, c->stream));
       HIP_OR_FAIL(c, prof_end(c));
       if (!a.fuse) {
         HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
@@ -930,7 +987,12 @@ dash_status dash_update_async(dash_ctx *c) {
   HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
   c->profiling = false;
-  c->inflight.push_back({step, Kp, K, c->rows_pending, slot});
+  {
+    const double J = c->J, R = c->R, M = (double)c->rows_pending, Kt = (double)ng;
+    const double bytes = c->cfg.n_iter * (M * J * 4 + M * R * 4 + K * (R * J * 4 + R * R * 4 + 8 + R * 8) +
+                                          Kt * (R * J * 4 + R * R * 4 + 8) + K * R * 8);
+    c->inflight.push_back({step, Kp, K, c->rows_pending, slot, cand, bytes});
+  }
   c->K_enq = K;
   c->step_enq = step;
   c->pending.clear();
@@ -949,6 +1011,7 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
     c->inflight.pop_front();
     const Report &r = c->hreport[f.slot];
     if (c->spans_on) c->spans.push_back((float)(device_us(r) * 1e-3));
+    if (r.committed) tune_account(c, f, r);
     if (!failed && r.committed) {
       c->K = f.K_after;
       c->step = f.step;
@@ -1012,6 +1075,7 @@ dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_
     }
     c->inflight.pop_front();
     if (c->spans_on) c->spans.push_back((float)(device_us(r) * 1e-3));
+    tune_account(c, f, r);
     c->K = f.K_after;
     c->step = f.step;
     c->m_last = f.rows;
@@ -1024,6 +1088,49 @@ dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_
     o.loss = r.loss;
     o.sum_n = r.sum_n;
     o.device_us = device_us(r);
+  }
+  return DASH_OK;
+}
+
+dash_status dash_autotune(dash_ctx *c, int32_t trials) {
+  if (!c || trials < 0) return DASH_E_INVALID_ARG;
+  c->tune_cands.clear();
+  c->tune_us.clear();
+  c->tune_bytes.clear();
+  c->tune_n.clear();
+  c->tune_next = 0;
+  c->tuned = false;
+  const int fl = (int)fused_pass_lds(c->variant, c->J, c->R);
+  c->sched = Schedule{c->variant, 1, fl > 0 ? 1 : 0};
+  if (trials == 0) return DASH_OK;
+  std::vector<int> variants{c->variant};
+  if (c->variant == kPassWave) variants.push_back(kPassBlock);
+  for (int v : variants)
+    for (int spread : {1, 2})
+      for (int fuse : {1, 0}) {
+        if (fuse && fused_pass_lds(v, c->J, c->R) == 0) continue;
+        c->tune_cands.push_back(Schedule{v, spread, fuse});
+      }
+  c->tune_us.assign(c->tune_cands.size(), 0.0);
+  c->tune_bytes.assign(c->tune_cands.size(), 0.0);
+  c->tune_n.assign(c->tune_cands.size(), 0);
+  c->tune_per = trials;
+  return DASH_OK;
+}
+
+dash_status dash_autotune_read(dash_ctx *c, dash_schedule *out) {
+  if (!c || !out) return DASH_E_INVALID_ARG;
+  out->variant = c->sched.variant;
+  out->spread = c->sched.spread;
+  out->fused = c->sched.fuse;
+  out->tuned = c->tuned ? 1 : 0;
+  out->candidates = (int32_t)c->tune_cands.size();
+  out->ns_per_kb = 0.0;
+  for (size_t i = 0; i < c->tune_cands.size(); ++i) {
+    const Schedule &k = c->tune_cands[i];
+    if (k.variant == c->sched.variant && k.spread == c->sched.spread && k.fuse == c->sched.fuse &&
+        c->tune_bytes[i] > 0)
+      out->ns_per_kb = 1e3 * c->tune_us[i] / (c->tune_bytes[i] / 1024.0);
   }
   return DASH_OK;
 }

@@ -61,6 +61,14 @@ class Dims(C.Structure):
                 ("initialized", C.c_int32)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("spread", C.c_int32), ("fused", C.c_int32), ("tuned", C.c_int32),
+                ("candidates", C.c_int32), ("ns_per_kb", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class ServerReport(C.Structure):
     _fields_ = [("stream", C.c_int32), ("committed", C.c_int32), ("step", C.c_int64), ("rows", C.c_int64),
                 ("fit", C.c_double), ("latency_us", C.c_double)]
@@ -95,6 +103,8 @@ _SIGS = {
     "dash_footprint": (C.c_int, [C.POINTER(DashConfig), C.POINTER(C.c_int64)]),
     "dash_spans": (C.c_int, [_P, C.c_int32]),
     "dash_graph": (C.c_int, [_P, C.c_int32]),
+    "dash_autotune": (C.c_int, [_P, C.c_int32]),
+    "dash_autotune_read": (C.c_int, [_P, C.POINTER(Schedule)]),
     "dash_spans_read": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_server_create": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(_P)]),
     "dash_server_destroy": (C.c_int, [_P]),
@@ -260,6 +270,15 @@ class Dash:
 
     def update_async(self):
         self._check(lib().dash_update_async(self._h), "dash_update_async")
+
+    def autotune(self, trials=2):
+        """Try every launch schedule `trials` times over the next updates and keep the fastest."""
+        self._check(lib().dash_autotune(self._h, int(trials)), "dash_autotune")
+
+    def schedule(self):
+        sc = Schedule()
+        self._check(lib().dash_autotune_read(self._h, C.byref(sc)), "dash_autotune_read")
+        return sc.as_dict()
 
     def graph(self, enable=True):
         """Replay each update's launches from one HIP graph (node parameters rewritten per update)."""

@@ -70,3 +70,25 @@ def test_graph_back_to_back_async_equals_direct():
     se, sg = eager.get_state(), graph.get_state()
     for k in se:
         np.testing.assert_array_equal(se[k], sg[k])
+
+
+def test_autotune_picks_a_schedule_and_stays_exact():
+    """Every candidate schedule computes the same update (to the order of FP64
+    partial sums); after the trials the best is kept, in graph mode too."""
+    from oracle.dash_oracle import DashOracle
+    wl = make_workload("mid", K0=300, n_steps=14)
+    ptr, X, U = wl.init_data(want_u=True)
+    g = make(wl, ptr, X, U, True)
+    g.autotune(1)
+    o = DashOracle(wl.J, wl.R, wl.lam)
+    o.init_from_factors([X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)], [U[ptr[k]:ptr[k + 1]] for k in range(wl.K0)],
+                        wl.W[: wl.K0], wl.V)
+    keep = []
+    for s in range(1, 15):
+        b = wl.step(s)
+        r = o.update(b.groups(), b.new_slices())
+        stage(g, b, keep)
+        rep = g.update()
+        assert abs(rep["fit"] - r.fit) <= 1e-5, (s, rep["fit"], r.fit)
+    sc = g.schedule()
+    assert sc["tuned"] == 1 and sc["candidates"] >= 4 and sc["ns_per_kb"] > 0, sc
