@@ -64,6 +64,8 @@ struct dash_ctx {
   int64_t K_cap = 0, M_cap = 0, G_cap = 0, N_init_cap = 0;
   // device state
   float *Y = nullptr;
+  float *Yc = nullptr;   // compensation words of Y and D (mixed precision only)
+  float *Dc = nullptr;
   float *D = nullptr;
   double *n = nullptr;
   uint8_t *cur = nullptr;
@@ -271,6 +273,8 @@ PassArgs base_args(const dash_ctx *c, int s) {
   a.groups = (const Group *)(d + c->off_groups);
   a.Y = c->Y;
   a.D = c->D;
+  a.Yc = c->Yc;
+  a.Dc = c->Dc;
   a.n = c->n;
   a.cur = c->cur;
   a.tlast = c->tlast;
@@ -333,6 +337,10 @@ dash_status enqueue_prep(dash_ctx *c) {
 // Committed-buffer index 0 for everything; slices [0, K) last folded at update tl.
 dash_status reset_device_state(dash_ctx *c, int32_t K, int32_t tl) {
   HIP_OR_FAIL(c, hipMemsetAsync(c->cur, 0, (size_t)(2 * c->K_cap), c->stream));
+  if (c->Yc) {
+    HIP_OR_FAIL(c, hipMemsetAsync(c->Yc, 0, sizeof(float) * 2 * c->K_cap * y_stride(c->J, c->R), c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->Dc, 0, sizeof(float) * 2 * c->K_cap * c->R * c->R, c->stream));
+  }
   std::vector<int32_t> t(std::max<int32_t>(K, 1), tl);
   if (K > 0)
     HIP_OR_FAIL(c, hipMemcpy(c->tlast, t.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
@@ -366,7 +374,8 @@ int64_t context_footprint(const dash_config *cfg) {
   const int64_t step_bytes = (int64_t)align_up(
       align_up(align_up(sizeof(StepHeader), 64) + sizeof(int32_t) * (n_chunks_cap + 1), 64) +
           sizeof(Group) * G_cap, 256);
-  return al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) + al(8 * 2 * Kc) + al(2 * Kc) + al(4 * 2 * Kc) +
+  const int64_t carry = cfg->precision == DASH_PREC_MIXED ? al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) : 0;
+  return carry + al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) + al(8 * 2 * Kc) + al(2 * Kc) + al(4 * 2 * Kc) +
          al(8 * 2 * Kc * R) + al(2 * (int64_t)vb_bytes(cfg->J, cfg->R)) + al(sizeof(Ctl)) +
          al(4 * cfg->max_rows_per_update * R) + al(8 * n_chunks_cap * plen) +
          al(8 * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) +
@@ -633,6 +642,9 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
             dalloc(&c->gpart, sizeof(double) * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) == hipSuccess &&
             dalloc(&c->counters, sizeof(int32_t) * (kMaxChunks + 1)) == hipSuccess &&
             dalloc(&c->d_rowptr, sizeof(int64_t) * (Kc + 1)) == hipSuccess;
+  if (ok && cfg->precision == DASH_PREC_MIXED)
+    ok = dalloc(&c->Yc, sizeof(float) * 2 * Kc * YS) == hipSuccess &&
+         dalloc(&c->Dc, sizeof(float) * 2 * Kc * R * R) == hipSuccess;
   if (!ok) return bail(DASH_E_OUT_OF_MEMORY);
   c->off_gptr = align_up(sizeof(StepHeader), 64);
   c->off_groups = align_up(c->off_gptr + sizeof(int32_t) * (n_chunks_cap + 1), 64);
@@ -653,6 +665,8 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   if (hipHostGetDevicePointer((void **)&c->dreport, c->hreport, 0) != hipSuccess) return bail(DASH_E_DEVICE);
   if (hipMemsetAsync(c->Y, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess ||
       hipMemsetAsync(c->cur, 0, (size_t)(2 * Kc), c->stream) != hipSuccess ||
+      (c->Yc && hipMemsetAsync(c->Yc, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess) ||
+      (c->Dc && hipMemsetAsync(c->Dc, 0, sizeof(float) * 2 * Kc * R * R, c->stream) != hipSuccess) ||
       hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * 2 * Kc, c->stream) != hipSuccess ||
       hipMemsetAsync(c->counters, 0, sizeof(int32_t) * (kMaxChunks + 1), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
@@ -672,6 +686,8 @@ dash_status dash_destroy(dash_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   (void)hipFree(c->Y);
   (void)hipFree(c->D);
+  (void)hipFree(c->Yc);
+  (void)hipFree(c->Dc);
   (void)hipFree(c->n);
   (void)hipFree(c->cur);
   (void)hipFree(c->tlast);
@@ -1225,7 +1241,7 @@ dash_status dash_get_state(dash_ctx *c, double *V, double *W, double *Y, double 
     }
     int e = launch_export_state(c->J, c->R, c->K, c->step, c->cfg.lambda, c->Y, c->D, c->n,
                                 c->cur + (int64_t)ctl.gcur * c->K_cap, c->tlast + (int64_t)ctl.gcur * c->K_cap,
-                                c->K_cap, dY, dD, dn, c->stream);
+                                c->K_cap, dY, dD, dn, c->Yc, c->Dc, c->stream);
     hipError_t he = (hipError_t)e;
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he == hipSuccess && Y) he = hipMemcpy(Y, dY, sizeof(double) * K * R * J, hipMemcpyDeviceToHost);
@@ -1250,13 +1266,24 @@ dash_status dash_set_state(dash_ctx *c, int32_t K, const double *V, const double
   const int64_t tl = c->step;
   if (dash_status s = reset_device_state(c, K, (int32_t)tl)) return s;
   // the state is stored in float32 (Y, D) and float64 (n, W, V); the cast is the
-  // only host-side arithmetic
-  std::vector<float> f((size_t)std::max<int64_t>(K * R * J, K * R * R));
-  for (int64_t i = 0; i < K * R * J; ++i) f[i] = (float)Y[i];
+  // only host-side arithmetic (a mixed-precision context also keeps the
+  // remainder of the cast as its compensation word)
+  std::vector<float> f((size_t)std::max<int64_t>(K * R * J, K * R * R)), lo(c->Yc ? f.size() : 0);
+  for (int64_t i = 0; i < K * R * J; ++i) {
+    f[i] = (float)Y[i];
+    if (c->Yc) lo[i] = (float)(Y[i] - (double)f[i]);
+  }
   HIP_OR_FAIL(c, hipMemcpy2D(c->Y, sizeof(float) * y_stride(c->J, c->R), f.data(), sizeof(float) * R * J,
                              sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
-  for (int64_t i = 0; i < K * R * R; ++i) f[i] = (float)D[i];
+  if (c->Yc)
+    HIP_OR_FAIL(c, hipMemcpy2D(c->Yc, sizeof(float) * y_stride(c->J, c->R), lo.data(), sizeof(float) * R * J,
+                               sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
+  for (int64_t i = 0; i < K * R * R; ++i) {
+    f[i] = (float)D[i];
+    if (c->Dc) lo[i] = (float)(D[i] - (double)f[i]);
+  }
   HIP_OR_FAIL(c, hipMemcpy(c->D, f.data(), sizeof(float) * K * R * R, hipMemcpyHostToDevice));
+  if (c->Dc) HIP_OR_FAIL(c, hipMemcpy(c->Dc, lo.data(), sizeof(float) * K * R * R, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->n, n, sizeof(double) * K, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->W, W, sizeof(double) * K * R, hipMemcpyHostToDevice));
   const VBundleView v = vb_view(c->vb, c->J, c->R);
@@ -1276,10 +1303,12 @@ dash_status dash_set_state(dash_ctx *c, int32_t K, const double *V, const double
 namespace {
 // Checkpoint file: header, then the raw committed state exactly as the device
 // holds it (float32 Y_k and D_k without the pending lambda^dt, float64 n_k,
-// W and V, int32 t_k), so that a restored context continues bit for bit.
+// W and V, int32 t_k; a mixed-precision context appends the compensation
+// words of Y_k and D_k and sets `carry`), so that a restored context continues
+// bit for bit.
 struct CkptHeader {
   char magic[8];
-  int32_t J, R, K, pad;
+  int32_t J, R, K, carry;
   int64_t step;
   double lambda;
 };
@@ -1311,6 +1340,15 @@ dash_status dash_save(dash_ctx *c, const char *path) {
   if (he == hipSuccess) he = hipMemcpy(Y.data(), dY, sizeof(float) * Y.size(), hipMemcpyDeviceToHost);
   if (he == hipSuccess) he = hipMemcpy(D.data(), dD, sizeof(float) * D.size(), hipMemcpyDeviceToHost);
   if (he == hipSuccess) he = hipMemcpy(n.data(), dn, sizeof(double) * n.size(), hipMemcpyDeviceToHost);
+  std::vector<float> Yc(c->Yc ? Y.size() : 0), Dc(c->Dc ? D.size() : 0);
+  if (c->Yc && he == hipSuccess) {
+    // the carry arrays share the layout of Y and D: gathered by the same kernel
+    he = (hipError_t)launch_gather_state(c->J, c->R, c->K, c->Yc, c->Dc, c->n,
+                                         c->cur + (int64_t)ctl.gcur * c->K_cap, c->K_cap, dY, dD, dn, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he == hipSuccess) he = hipMemcpy(Yc.data(), dY, sizeof(float) * Yc.size(), hipMemcpyDeviceToHost);
+    if (he == hipSuccess) he = hipMemcpy(Dc.data(), dD, sizeof(float) * Dc.size(), hipMemcpyDeviceToHost);
+  }
   (void)hipFree(dY);
   (void)hipFree(dD);
   (void)hipFree(dn);
@@ -1330,10 +1368,12 @@ dash_status dash_save(dash_ctx *c, const char *path) {
   h.K = c->K;
   h.step = c->step;
   h.lambda = c->cfg.lambda;
+  h.carry = c->Yc ? 1 : 0;
   bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(Y.data(), 4, Y.size(), fp) == Y.size() &&
             std::fwrite(D.data(), 4, D.size(), fp) == D.size() && std::fwrite(n.data(), 8, n.size(), fp) == n.size() &&
             std::fwrite(W.data(), 8, W.size(), fp) == W.size() && std::fwrite(V.data(), 8, V.size(), fp) == V.size() &&
-            std::fwrite(tl.data(), 4, tl.size(), fp) == tl.size();
+            std::fwrite(tl.data(), 4, tl.size(), fp) == tl.size() &&
+            std::fwrite(Yc.data(), 4, Yc.size(), fp) == Yc.size() && std::fwrite(Dc.data(), 4, Dc.size(), fp) == Dc.size();
   ok = (std::fclose(fp) == 0) && ok;
   return ok ? DASH_OK : fail(c, DASH_E_IO, "short write to %s", path);
 }
@@ -1356,9 +1396,15 @@ dash_status dash_load(dash_ctx *c, const char *path) {
   std::vector<float> Y(K * R * J), D(K * R * R);
   std::vector<double> n(K), W(K * R), V(J * R);
   std::vector<int32_t> tl(K);
+  if (h.carry != 0 && h.carry != 1) {
+    std::fclose(fp);
+    return fail(c, DASH_E_IO, "%s: bad carry flag", path);
+  }
+  std::vector<float> Yc(h.carry ? Y.size() : 0), Dc(h.carry ? D.size() : 0);
   bool ok = std::fread(Y.data(), 4, Y.size(), fp) == Y.size() && std::fread(D.data(), 4, D.size(), fp) == D.size() &&
             std::fread(n.data(), 8, n.size(), fp) == n.size() && std::fread(W.data(), 8, W.size(), fp) == W.size() &&
-            std::fread(V.data(), 8, V.size(), fp) == V.size() && std::fread(tl.data(), 4, tl.size(), fp) == tl.size();
+            std::fread(V.data(), 8, V.size(), fp) == V.size() && std::fread(tl.data(), 4, tl.size(), fp) == tl.size() &&
+            std::fread(Yc.data(), 4, Yc.size(), fp) == Yc.size() && std::fread(Dc.data(), 4, Dc.size(), fp) == Dc.size();
   std::fclose(fp);
   if (!ok) return fail(c, DASH_E_IO, "short read from %s", path);
   if (dash_status s = dash_wait(c, nullptr)) return s;
@@ -1366,6 +1412,11 @@ dash_status dash_load(dash_ctx *c, const char *path) {
   HIP_OR_FAIL(c, hipMemcpy2D(c->Y, sizeof(float) * y_stride(c->J, c->R), Y.data(), sizeof(float) * R * J,
                              sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->D, D.data(), sizeof(float) * D.size(), hipMemcpyHostToDevice));
+  if (c->Yc && h.carry) {   // a float32 context drops the words; a mixed one without them starts at zero
+    HIP_OR_FAIL(c, hipMemcpy2D(c->Yc, sizeof(float) * y_stride(c->J, c->R), Yc.data(), sizeof(float) * R * J,
+                               sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
+    HIP_OR_FAIL(c, hipMemcpy(c->Dc, Dc.data(), sizeof(float) * Dc.size(), hipMemcpyHostToDevice));
+  }
   HIP_OR_FAIL(c, hipMemcpy(c->n, n.data(), sizeof(double) * n.size(), hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->W, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->tlast, tl.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));

@@ -684,7 +684,7 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
 // ---------------------------------------------------------------------------
 struct PassLds {
   int XS, MB;
-  size_t oP, oVt, oX, oU, oW, oWinv, oC, oC2, oM, oDc, oVtV, oZ, oTmp, oRot, oPair, bytes;
+  size_t oP, oVt, oX, oU, oW, oWinv, oC, oC2, oM, oDc, oDlo, oVtV, oZ, oTmp, oRot, oPair, bytes;
 };
 
 __host__ __device__ inline PassLds pass_lds(int J, int R, bool with_finish = true) {
@@ -704,6 +704,7 @@ __host__ __device__ inline PassLds pass_lds(int J, int R, bool with_finish = tru
   L.oC2 = o;   o += (size_t)R * 8;
   L.oM = o;    o += (size_t)R * R * 8;
   L.oDc = o;   o += (size_t)R * R * 4;
+  L.oDlo = o;  o += (size_t)R * R * 4;   // compensation of D_k (mixed precision)
   o = align_up(o, 8);
   L.oVtV = o;  o += (size_t)R * R * 8;
   L.oZ = o;    o += (size_t)R * R * 8;
@@ -830,6 +831,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   double *sC2 = (double *)(smem + L.oC2);
   double *sM = (double *)(smem + L.oM);
   float *sDc = (float *)(smem + L.oDc);
+  float *sDlo = (float *)(smem + L.oDlo);
   double *sVtV = (double *)(smem + L.oVtV);
   double *sZ = (double *)(smem + L.oZ);
   double *sTmp = (double *)(smem + L.oTmp);
@@ -1053,6 +1055,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
     const float s_old_f = (float)s_old;
     const float *Yst = a.Y + ((int64_t)b * a.K_cap + k) * a.ys;
     float yv[RW][JW];
+    float ylo[RW][JW];   // compensation (mixed precision): Y_k = yv + ylo
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
       const int r = wv + 4 * rr;
@@ -1060,7 +1063,18 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       for (int jj = 0; jj < JW; ++jj) {
         const int j = lane + 64 * jj;
         const float yo = (!is_new && r < R && j < J) ? Yst[r * J + j] : 0.f;
-        yv[rr][jj] = touched ? fmaf(s_old_f, yo, dY[rr][jj]) : yo;
+        if constexpr (MX) {
+          // compensated running sum: (hi, lo) folded in FP64 and split again
+          const float *Ycst = a.Yc + ((int64_t)b * a.K_cap + k) * a.ys;
+          const float yl = (!is_new && r < R && j < J) ? Ycst[r * J + j] : 0.f;
+          const double v = touched ? s_old * ((double)yo + (double)yl) + (double)dY[rr][jj]
+                                   : (double)yo + (double)yl;
+          yv[rr][jj] = (float)v;
+          ylo[rr][jj] = (float)(v - (double)yv[rr][jj]);
+        } else {
+          yv[rr][jj] = touched ? fmaf(s_old_f, yo, dY[rr][jj]) : yo;
+          ylo[rr][jj] = 0.f;
+        }
       }
     }
 #pragma unroll
@@ -1070,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) {
         const int j = lane + 64 * jj;
-        if (r < R && j < J) part += (double)yv[rr][jj] * (double)sVt[r * J + j];
+        if (r < R && j < J) part += ((double)yv[rr][jj] + (double)ylo[rr][jj]) * (double)sVt[r * J + j];
       }
       part = wave_sum(part);
       if (lane == 0 && r < R) {
@@ -1084,16 +1098,25 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       const int q = tid + 256 * i;
       if (q < RR) {
         const float dold = is_new ? 0.f : Dst[q];
-        const float dc = touched ? fmaf(s_old_f, dold, dD[i]) : dold;
-        sDc[q] = dc;
-        sM[q] = sVtV[q] * (double)dc;
+        if constexpr (MX) {
+          const float dl = is_new ? 0.f : a.Dc[((int64_t)b * a.K_cap + k) * RR + q];
+          const double v = touched ? s_old * ((double)dold + (double)dl) + (double)dD[i] : (double)dold + (double)dl;
+          sDc[q] = (float)v;
+          sDlo[q] = (float)(v - (double)sDc[q]);
+          sM[q] = sVtV[q] * v;
+        } else {
+          const float dc = touched ? fmaf(s_old_f, dold, dD[i]) : dold;
+          sDc[q] = dc;
+          sM[q] = sVtV[q] * (double)dc;
+        }
       }
     }
     __syncthreads();
     if (a.mode == 0) {
       if (wv == 0) {
         if (!wave_cholesky(sM, R)) {
-          for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * (double)sDc[q];
+          for (int q = lane; q < RR; q += 64)
+            sM[q] = sVtV[q] * ((double)sDc[q] + (MX ? (double)sDlo[q] : 0.0));
           if (lane < R) sC[lane] = sC2[lane];
           wave_sync();
           wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
@@ -1114,7 +1137,10 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       if (r < R) {
         const double wr = sigma * sC[r];
 #pragma unroll
-        for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = fmaf((float)wr, yv[rr][jj], facc[rr][jj]);
+        for (int jj = 0; jj < JW; ++jj) {
+          facc[rr][jj] = fmaf((float)wr, yv[rr][jj], facc[rr][jj]);
+          if constexpr (MX) facc[rr][jj] = fmaf((float)wr, ylo[rr][jj], facc[rr][jj]);
+        }
       }
     }
 #pragma unroll
@@ -1122,7 +1148,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       const int q = tid + 256 * i;
       if (q < RR) {
         const int r = q / R, s = q - r * R;
-        gacc[i] += sigma * sC[r] * sC[s] * (double)sDc[q];
+        gacc[i] += sigma * sC[r] * sC[s] * ((double)sDc[q] + (MX ? (double)sDlo[q] : 0.0));
       }
     }
     if (tid == 0) {
@@ -1144,6 +1170,10 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
         for (int jj = 0; jj < JW; ++jj) {
           const int j = lane + 64 * jj;
           if (r < R && j < J) Ynx[r * J + j] = yv[rr][jj];
+          if constexpr (MX) {
+            float *Ycnx = a.Yc + ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
+            if (r < R && j < J) Ycnx[r * J + j] = ylo[rr][jj];
+          }
         }
       }
       float *Dnx = a.D + ((int64_t)(1 - b) * a.K_cap + k) * RR;
@@ -1151,6 +1181,9 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int q = tid + 256 * i;
         if (q < RR) Dnx[q] = sDc[q];
+        if constexpr (MX) {
+          if (q < RR) a.Dc[((int64_t)(1 - b) * a.K_cap + k) * RR + q] = sDlo[q];
+        }
       }
     }
   }
@@ -1268,16 +1301,20 @@ __global__ void k_f64_to_f32(int64_t count, const double *src, float *dst) {
 __global__ void k_export_state(int J, int R, int K, int64_t step, double lambda, const float *Y,
                                const float *D, const double *n, const uint8_t *cur,
                                const int32_t *tlast, int64_t K_cap, double *Yo, double *Do,
-                               double *no) {
+                               double *no, const float *Yc, const float *Dc) {
   const int k = blockIdx.x;
   if (k >= K) return;
   const int b = cur[k];
   const double s = pow(lambda, (double)(step - tlast[k]));
   const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R, YS = y_stride(J, R);
-  for (int e = threadIdx.x; e < RJ; e += 256)
-    Yo[k * RJ + e] = s * (double)Y[((int64_t)b * K_cap + k) * YS + e];
-  for (int e = threadIdx.x; e < RR; e += 256)
-    Do[k * RR + e] = s * (double)D[((int64_t)b * K_cap + k) * RR + e];
+  for (int e = threadIdx.x; e < RJ; e += 256) {
+    const int64_t i = ((int64_t)b * K_cap + k) * YS + e;
+    Yo[k * RJ + e] = s * ((double)Y[i] + (Yc ? (double)Yc[i] : 0.0));
+  }
+  for (int e = threadIdx.x; e < RR; e += 256) {
+    const int64_t i = ((int64_t)b * K_cap + k) * RR + e;
+    Do[k * RR + e] = s * ((double)D[i] + (Dc ? (double)Dc[i] : 0.0));
+  }
   if (threadIdx.x == 0) no[k] = s * n[(int64_t)b * K_cap + k];
 }
 
@@ -1479,10 +1516,11 @@ int launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s) {
 
 int launch_export_state(int J, int R, int K, int64_t step, double lambda, const float *Y,
                         const float *D, const double *n, const uint8_t *cur, const int32_t *tlast,
-                        int64_t K_cap, double *Yo, double *Do, double *no, hipStream_t s) {
+                        int64_t K_cap, double *Yo, double *Do, double *no, const float *Yc, const float *Dc,
+                        hipStream_t s) {
   if (K <= 0) return 0;
   hipLaunchKernelGGL(k_export_state, dim3(K), dim3(256), 0, s, J, R, K, step, lambda, Y, D, n, cur,
-                     tlast, K_cap, Yo, Do, no);
+                     tlast, K_cap, Yo, Do, no, Yc, Dc);
   return (int)hipGetLastError();
 }
 

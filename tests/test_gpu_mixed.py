@@ -119,3 +119,71 @@ def test_precision_workload_error_table():
         print(f"  {p:6s}", {k: f"{v:.2e}" for k, v in worst[p].items()}, flush=True)
     assert worst["fp32"]["fit"] <= 1e-5
     assert worst["mixed"]["fit"] <= 1e-3
+
+
+def _long_history(seed=11, J=88, R=10, K=8, I=4000):
+    """K slices of I planted rows each: the running sums are large, so the
+    increments of a few rows scaled by 1e-3 fall below their float32 resolution."""
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal((J, R))
+    W = rng.uniform(0.5, 1.5, (K, R))
+    U = rng.standard_normal((K * I, R))
+    X = np.concatenate([(U[k * I:(k + 1) * I] * W[k]) @ V.T for k in range(K)])
+    X += 0.01 * rng.standard_normal(X.shape)
+    ptr = np.arange(K + 1, dtype=np.int64) * I
+    rows = []
+    for t in range(30):
+        u = rng.standard_normal((2, R))
+        rows.append((1e-3 * ((u * W[0]) @ V.T + 0.01 * rng.standard_normal((2, J)))).astype(np.float32))
+    return ptr, X.astype(np.float32), U.astype(np.float32), W.astype(np.float32), V.astype(np.float32), rows
+
+
+def test_mixed_running_sums_keep_increments_below_fp32_resolution(tmp_path):
+    """lambda = 1 and thirty updates of two rows each to slice 0, whose running
+    sums hold 4000 rows: every increment of Y_0 and D_0 is about 1e-9 of the
+    sum, under half a float32 ulp.  The compensated running sums of the mixed
+    path keep them: the change of Y_0 and D_0 over the stream matches the
+    oracle's to the BF16 bound of the increments (2e-2), where the plain
+    float32 path drops most of it.  A checkpoint of the mixed context carries
+    the compensation words and resumes bit for bit."""
+    from paper_2305_18376_amd.dash import Dash, PREC_FP32, PREC_MIXED
+    ptr, X, U, W, V, rows = _long_history()
+    J, R, K = X.shape[1], U.shape[1], W.shape[0]
+    o = DashOracle(J, R, 1.0)
+    o.init_from_factors([X[ptr[k]:ptr[k + 1]] for k in range(K)], [U[ptr[k]:ptr[k + 1]] for k in range(K)], W, V)
+    gs = {}
+    for p, prec in (("fp32", PREC_FP32), ("mixed", PREC_MIXED)):
+        g = Dash(J, R, lam=1.0, max_slices=64, max_rows=1 << 12, max_groups=64, precision=prec)
+        g.init_from_factors(ptr, dev(X), dev(U), dev(W), dev(V))
+        gs[p] = g
+    before = {p: g.get_state() for p, g in gs.items()}
+    o_before = o.state()
+    for t, x in enumerate(rows):
+        o.update([(0, x)])
+        for p, g in gs.items():
+            g.ingest_rows(np.array([0], np.int32), np.array([0, x.shape[0]], np.int64), dev(x))
+            rep = g.update()
+            assert rep["committed"] == 1
+        if t == 14:
+            path = tmp_path / "mixed.ck"
+            gs["mixed"].save(path)
+            resumed = Dash(J, R, lam=1.0, max_slices=64, max_rows=1 << 12, max_groups=64, precision=PREC_MIXED)
+            resumed.load(path)
+            np.testing.assert_array_equal(resumed.get_state()["Y"], gs["mixed"].get_state()["Y"])
+    resumed_rows = rows[15:]
+    for x in resumed_rows:
+        resumed.ingest_rows(np.array([0], np.int32), np.array([0, x.shape[0]], np.int64), dev(x))
+        resumed.update()
+    ost = o.state()
+    errs = {}
+    for p, g in gs.items():
+        st = g.get_state()
+        errs[p] = {k: relerr(st[k][0] - before[p][k][0], ost[k][0] - o_before[k][0]) for k in ("Y", "D")}
+    print("change of Y_0, D_0 over the stream, relative error:",
+          {p: {k: f"{v:.2e}" for k, v in e.items()} for p, e in errs.items()}, flush=True)
+    assert errs["mixed"]["Y"] <= 2e-2 and errs["mixed"]["D"] <= 2e-2, errs
+    # the scenario really is below float32 resolution: the plain path loses it
+    assert errs["fp32"]["Y"] >= 0.1, errs
+    s1, s2 = gs["mixed"].get_state(), resumed.get_state()
+    for key in s1:
+        np.testing.assert_array_equal(s1[key], s2[key])
