@@ -55,7 +55,9 @@ typedef struct dash_config {
   double init_tol;           /* stop when |d loss| <= init_tol * loss                   */
   int32_t precision;         /* DASH_PREC_FP32, or DASH_PREC_MIXED: the new rows' products
                                 (Lemma 1's x V (V^T V)^{-1} and U_new^T X_new, U_new^T U_new)
-                                on BF16 MFMA with FP32 sums; state FP32, R x R FP64   */
+                                on BF16 MFMA with FP32 sums; the running sums Y_k, D_k
+                                FP32 plus an FP32 compensation word each, folded in
+                                FP64 (twice the state bytes); R x R solves FP64       */
   int32_t stats_mode;        /* DASH_STATS_EXACT                                         */
   int64_t max_slices;        /* capacity in slices (K never exceeds it)                  */
   int64_t max_rows_per_update;   /* capacity in rows staged for one update               */

@@ -734,13 +734,88 @@ __device__ __forceinline__ f32x4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, con
 // the dD tile w of the (R / 16)^2 rank-tile pairs
 constexpr int kMxTiles = 8;
 
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One 16 x 16 tile of X P: rows xrow (lane's row of the 16-row tile, stride
+// XS in LDS, zero rows beyond the block), columns 16 nt .. 16 nt + 15 of P
+// (J x R, LDS); columns >= R come out as garbage and are dropped by the
+// caller.  v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; BF16 (16x16x32): A[l % 16][8 (l / 16) + i], i < 8.
+template <bool MX>
+__device__ __forceinline__ f32x4 rows_times_p(const float *xrow, const float *sP, int J, int R, int nt,
+                                               int lane) {
+  const int n = min(nt * 16 + (lane & 15), R - 1);
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (MX) {
+    const int lk = (lane >> 4) * 8;
+    for (int ks = 0; ks < J; ks += 32) {
+      bf16x8 av, bv;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int kk = ks + lk + q;
+        av[q] = (__bf16)((kk < J) ? xrow[kk] : 0.f);
+        bv[q] = (__bf16)((kk < J) ? sP[kk * R + n] : 0.f);
+      }
+      acc0 = mfma_bf16(av, bv, acc0);
+    }
+  } else {
+    const int lq = lane >> 4;
+    int ks = 0;
+    // two independent chains; the tail (J % 8) goes to the first
+    for (; ks + 8 <= J; ks += 8) {
+      const float a0 = xrow[ks + lq], a1 = xrow[ks + 4 + lq];
+      const float b0 = sP[(ks + lq) * R + n], b1 = sP[(ks + 4 + lq) * R + n];
+      acc0 = mfma_f32(a0, b0, acc0);
+      acc1 = mfma_f32(a1, b1, acc1);
+    }
+    for (; ks < J; ks += 4) {
+      const int kk = ks + lq;
+      const float a0 = (kk < J) ? xrow[kk] : 0.f;
+      const float b0 = (kk < J) ? sP[kk * R + n] : 0.f;
+      acc0 = mfma_f32(a0, b0, acc0);
+    }
+  }
+  return acc0 + acc1;
+}
+
+// dY += U^T X, dD += U^T U in FP32 on MFMA (16x16x4) for one staged block
+// (rows >= m are zero in sX and sU; mp = m rounded up to 16).  Same tile
+// ownership as the BF16 version below.
+__device__ __forceinline__ void accum_block_f32(const float *sX, const float *sU, int XS, int mp, int J,
+                                                int R, f32x4 (&accY)[kMxTiles], f32x4 &accD, int tid) {
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
+  const int li = lane & 15, lq = lane >> 4;
+  const int r0c = min(li, R - 1), r1c = min(16 + li, R - 1);
+  for (int ks = 0; ks < mp; ks += 4) {
+    const float *urow = sU + (ks + lq) * (R + 1);
+    const float au0 = urow[r0c], au1 = urow[r1c];
+    const float *xrow = sX + (ks + lq) * XS;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int nt = wv + 4 * c;
+      if (nt < NT) {
+        const float bx = xrow[min(nt * 16 + li, J - 1)];
+        accY[2 * c] = mfma_f32(au0, bx, accY[2 * c]);
+        if (MT > 1) accY[2 * c + 1] = mfma_f32(au1, bx, accY[2 * c + 1]);
+      }
+    }
+    if (wv < MT * MT) {
+      const int mt = wv / MT, st = wv - mt * MT;
+      accD = mfma_f32(mt == 0 ? au0 : au1, st == 0 ? au0 : au1, accD);
+    }
+  }
+}
+
 // dY += U^T X, dD += U^T U on MFMA for one staged block (rows >= m are zero
 // in both sX and sU; mp = m rounded up to 32).  The U^T operand of a rank
 // tile is loaded once per 32-row step and serves every column tile, and, as
 // the B operand of dD, the rank-tile pairs too.
 __device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU, int XS, int mp, int J,
-                                               int R, f32x4 (&accY)[kMxTiles], f32x4 &accD) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+                                               int R, f32x4 (&accY)[kMxTiles], f32x4 &accD, int tid) {
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
   const int li = lane & 15, lk = (lane >> 4) * 8;
   for (int ks = 0; ks < mp; ks += 32) {
@@ -770,6 +845,76 @@ __device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU,
     }
   }
 }
+
+// Copy m contiguous rows of J floats from HBM into sX (row stride XS) with the
+// 256 threads of the block; m * J <= 8192.  Every load of a thread is issued
+// before its first LDS store, so the block waits for one memory latency, not
+// one per element.  Float4 loads when the rows allow them.  With SQ the
+// thread's sum of squares of what it loaded is returned (FP64).
+template <bool SQ>
+__device__ __forceinline__ double stage_rows(const float *__restrict__ src, int m, int J, int XS, float *sX,
+                                             int tid) {
+  double sq = 0.0;
+  const int n = m * J;
+  if ((J & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    const int n4 = n >> 2;
+#pragma unroll 1
+    for (int i0 = 0; i0 < 8; i0 += 4) {
+      if (tid + 256 * i0 >= n4) break;
+      float4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = tid + 256 * (i0 + i);
+        v[i] = (q < n4) ? reinterpret_cast<const float4 *>(src)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = tid + 256 * (i0 + i);
+        if (q < n4) {
+          const int e = 4 * q, row = e / J, col = e - row * J;
+          float *d = sX + row * XS + col;
+          d[0] = v[i].x;
+          d[1] = v[i].y;
+          d[2] = v[i].z;
+          d[3] = v[i].w;
+        }
+        if constexpr (SQ) {
+          sq = fma((double)v[i].x, (double)v[i].x, sq);
+          sq = fma((double)v[i].y, (double)v[i].y, sq);
+          sq = fma((double)v[i].z, (double)v[i].z, sq);
+          sq = fma((double)v[i].w, (double)v[i].w, sq);
+        }
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int i0 = 0; i0 < 32; i0 += 8) {
+      if (tid + 256 * i0 >= n) break;
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * (i0 + i);
+        v[i] = (e < n) ? src[e] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * (i0 + i);
+        if (e < n) {
+          const int row = e / J;
+          sX[row * XS + (e - row * J)] = v[i];
+        }
+        if constexpr (SQ) sq = fma((double)v[i], (double)v[i], sq);
+      }
+    }
+  }
+  return sq;
+}
+
+// padded rank of the block variant's register solve (R <= 4 RW)
+template <int RW>
+struct BlockRM {
+  static constexpr int value = RW <= 2 ? 8 : (RW == 3 ? 12 : (RW == 4 ? 16 : (RW <= 6 ? 24 : 32)));
+};
 
 // dY += U^T X and dD += U^T U for one staged block of m rows (block variant).
 template <int RW, int JW>
@@ -858,16 +1003,52 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   const int gend = a.chunk_gptr[chunk + 1];
   const int plen = partial_len(J, R);
 
+  // weights W(k,:) the sweep starts from (1 for a new slice in the first pass)
+  auto load_w = [&](int k) -> double {
+    return (k >= Kp && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + threadIdx.x];
+  };
+  double wnext = (tid < R && k0 < k1) ? load_w(k0) : 0.0;
+
   for (int k = k0; k < k1; ++k) {
+    // the thread index, opaque to the compiler inside the loop: per-thread
+    // address arithmetic is redone per slice instead of being hoisted out of
+    // the loop into registers
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int gb = g;
     while (g < gend && a.groups[g].slice == k) ++g;
     const bool touched = g > gb;
     const bool is_new = k >= Kp;
-    __syncthreads();
-    if (tid < R) {
-      const double w = (is_new && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + tid];
-      sW[tid] = w;
+    // the stored Y_k and D_k are loaded first: their latency overlaps the
+    // row phase
+    const int b = a.cur[(int64_t)gcur * a.K_cap + k];
+    const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
+    const int64_t ybase = ((int64_t)b * a.K_cap + k) * a.ys;
+    const int64_t dbase = ((int64_t)b * a.K_cap + k) * RR;
+    float yo[RW][JW];
+    float yl[MX ? RW : 1][MX ? JW : 1];
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) {
+      const int r = wv + 4 * rr;
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) {
+        const int j = lane + 64 * jj;
+        const bool in = !is_new && r < R && j < J;
+        yo[rr][jj] = in ? a.Y[ybase + r * J + j] : 0.f;
+        if constexpr (MX) yl[rr][jj] = in ? a.Yc[ybase + r * J + j] : 0.f;
+      }
     }
+    float dold[4], dlo[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      const bool in = !is_new && q < RR;
+      dold[i] = in ? a.D[dbase + q] : 0.f;
+      dlo[i] = (MX && in) ? a.Dc[dbase + q] : 0.f;
+    }
+    __syncthreads();
+    if (tid < R) sW[tid] = wnext;
     __syncthreads();
     if (tid < R) {
       double top = 0.0;
@@ -875,6 +1056,8 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       const double w = sW[tid];
       sWinv[tid] = (fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
     }
+    // the next slice's weights, in flight during this slice
+    if (tid < R && k + 1 < k1) wnext = load_w(k + 1);
 
     float dY[RW][JW];
     float dD[4] = {0.f, 0.f, 0.f, 0.f};
@@ -884,228 +1067,159 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) dY[rr][jj] = 0.f;
 
-    if constexpr (MX) {
-      if (touched && a.mode == 0) {
-        // Lemma 1 and the accumulation on BF16 MFMA (FP32 sums)
-        f32x4 accY[kMxTiles];
-        f32x4 accD = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const int li = lane & 15, lk = (lane >> 4) * 8;
-        const int NTu = (R + 15) >> 4;
-        for (int gi = gb; gi < g; ++gi) {
-          const Group gr = a.groups[gi];
-          for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
-            const int m = min(MB, gr.nrows - r0);
-            const int mp = (m + 31) & ~31;
-            __syncthreads();
-            const float *src = gr.src + (int64_t)r0 * J;
-            for (int e = tid; e < mp * J; e += 256) {
-              const int row = e / J, col = e - row * J;
-              const float x = (row < m) ? src[e] : 0.f;
-              sX[row * XS + col] = x;
-              dn = fma((double)x, (double)x, dn);
-            }
-            __syncthreads();
-            // u = (x P) * (1/w): wave w takes rows 16w .. 16w+15 of the block
-            if (16 * wv < mp) {
-              f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-              const int row = 16 * wv + li;
-              for (int ks = 0; ks < J; ks += 32) {
-                bf16x8 av;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                  const int kk = ks + lk + q;
-                  av[q] = (__bf16)((kk < J) ? sX[row * XS + kk] : 0.f);
-                }
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                  if (nt >= NTu) break;
-                  const int n = nt * 16 + li;
-                  bf16x8 bv;
-#pragma unroll
-                  for (int q = 0; q < 8; ++q) {
-                    const int kk = ks + lk + q;
-                    bv[q] = (__bf16)((kk < J && n < R) ? sP[kk * R + n] : 0.f);
-                  }
-                  acc[nt] = mfma_bf16(av, bv, acc[nt]);
-                }
-              }
-#pragma unroll
-              for (int nt = 0; nt < 2; ++nt) {
-                if (nt >= NTu) break;
-                const int n = nt * 16 + li;
-                if (n < R) {
-                  const float wi = sWinv[n];
-#pragma unroll
-                  for (int q = 0; q < 4; ++q) {
-                    const int rr = 16 * wv + (lane >> 4) * 4 + q;
-                    const float u = (rr < m) ? acc[nt][q] * wi : 0.f;
-                    sU[rr * (R + 1) + n] = u;
-                    if (a.last_pass && rr < m) a.U_out[(gr.out_row + r0 + rr) * R + n] = u;
-                  }
-                }
-              }
-            }
-            __syncthreads();
-            accum_block_mx(sX, sU, XS, mp, J, R, accY, accD);
-          }
-        }
-        // hand the tiles to the [rank][column] register layout through LDS
-        __syncthreads();
-        float *sDY = sX;   // R x J (the row block is dead)
-        float *sDD = sU;   // R x R
-        {
-          const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
-#pragma unroll
-          for (int i = 0; i < kMxTiles; ++i) {
-            const int c = i >> 1, mt = i & 1;
-            const int nt = wv + 4 * c;
-            if (nt >= NT || mt >= MT) continue;
-            const int j = nt * 16 + li;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int r = mt * 16 + (lane >> 4) * 4 + q;
-              if (r < R && j < J) sDY[r * J + j] = accY[i][q];
-            }
-          }
-          if (wv < MT * MT) {
-            const int mt = wv / MT, st = wv - mt * MT;
-            const int c = st * 16 + li;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int r = mt * 16 + (lane >> 4) * 4 + q;
-              if (r < R && c < R) sDD[r * R + c] = accD[q];
-            }
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int rr = 0; rr < RW; ++rr) {
-          const int r = wv + 4 * rr;
-#pragma unroll
-          for (int jj = 0; jj < JW; ++jj) {
-            const int j = lane + 64 * jj;
-            dY[rr][jj] = (r < R && j < J) ? sDY[r * J + j] : 0.f;
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int q = tid + 256 * i;
-          dD[i] = (q < RR) ? sDD[q] : 0.f;
-        }
-        // ||x||^2 of the slice's rows, summed over the block in wave order
-        dn = wave_sum(dn);
-        __syncthreads();
-        if (lane == 0) sTmp[wv] = dn;
-        __syncthreads();
-        dn = (wv == 0) ? ((sTmp[0] + sTmp[1]) + sTmp[2]) + sTmp[3] : 0.0;
-        __syncthreads();
-      }
-    } else {
     if (touched && a.mode == 0) {
-        for (int gi = gb; gi < g; ++gi) {
-          const Group gr = a.groups[gi];
-          for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
-            const int m = min(MB, gr.nrows - r0);
-            __syncthreads();
-            const float *src = gr.src + (int64_t)r0 * J;
-            for (int e = tid; e < m * J; e += 256) {
-              const int row = e / J, col = e - row * J;
-              sX[row * XS + col] = src[e];
-            }
-            __syncthreads();
-            if (lane < m) {
-              float tacc[RW];
+      // Lemma 1 and the accumulation of the new rows on MFMA: FP32
+      // (16x16x4) in the float32 path, BF16 (16x16x32, FP32 sums) in the
+      // mixed path.  The tiles of dY = U^T X and dD = U^T U stay in the
+      // waves' accumulators over all blocks of the slice.
+      f32x4 accY[kMxTiles];
+      f32x4 accD = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-              for (int rr = 0; rr < RW; ++rr) tacc[rr] = 0.f;
-              float nx = 0.f;
-              const float *xr = sX + lane * XS;
-              for (int j = 0; j < J; ++j) {
-                const float xv = xr[j];
-                nx = fmaf(xv, xv, nx);
+      for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int NTu = (R + 15) >> 4;
+      for (int gi = gb; gi < g; ++gi) {
+        const Group gr = a.groups[gi];
+        for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
+          const int m = min(MB, gr.nrows - r0);
+          // rows of the block the MFMA tiles cover (zero beyond m)
+          const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
+          __syncthreads();
+          dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
+          for (int e = tid; e < (mp - m) * J; e += 256) {
+            const int row = e / J;
+            sX[(m + row) * XS + (e - row * J)] = 0.f;
+          }
+          __syncthreads();
+          // u = (x P) * (1/w): jobs (row tile, rank tile), wave w takes w and w + 4
+          const int jobs = (mp >> 4) * NTu;
 #pragma unroll
-                for (int rr = 0; rr < RW; ++rr) {
-                  const int r = wv + 4 * rr;
-                  if (r < R) tacc[rr] = fmaf(xv, sP[j * R + r], tacc[rr]);
+          for (int jb = 0; jb < 2; ++jb) {
+            const int job = wv + 4 * jb;
+            if (job < jobs) {
+              const int rt = job / NTu, nt = job - rt * NTu;
+              const f32x4 acc = rows_times_p<MX>(sX + (16 * rt + (lane & 15)) * XS, sP, J, R, nt, lane);
+              const int n = nt * 16 + (lane & 15);
+              if (n < R) {
+                const float wi = sWinv[n];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int rr = 16 * rt + (lane >> 4) * 4 + q;
+                  const float u = (rr < m) ? acc[q] * wi : 0.f;
+                  sU[rr * (R + 1) + n] = u;
+                  if (a.last_pass && rr < m) a.U_out[(gr.out_row + r0 + rr) * R + n] = u;
                 }
               }
-#pragma unroll
-              for (int rr = 0; rr < RW; ++rr) {
-                const int r = wv + 4 * rr;
-                if (r < R) {
-                  const float u = tacc[rr] * sWinv[r];
-                  sU[lane * (R + 1) + r] = u;
-                  if (a.last_pass) a.U_out[(gr.out_row + r0 + lane) * R + r] = u;
-                }
-              }
-              if (wv == 0) dn += (double)nx;
             }
-            __syncthreads();
-            accum_block<RW, JW>(sX, sU, XS, m, J, R, dY, dD);
+          }
+          __syncthreads();
+          if constexpr (MX)
+            accum_block_mx(sX, sU, XS, mp, J, R, accY, accD, tid);
+          else
+            accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
+        }
+      }
+      // hand the tiles to the [rank][column] register layout through LDS
+      __syncthreads();
+      float *sDY = sX;   // R x J (the row block is dead)
+      float *sDD = sU;   // R x R
+      {
+        const int li = lane & 15;
+        const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
+#pragma unroll
+        for (int i = 0; i < kMxTiles; ++i) {
+          const int c = i >> 1, mt = i & 1;
+          const int nt = wv + 4 * c;
+          if (nt >= NT || mt >= MT) continue;
+          const int j = nt * 16 + li;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = mt * 16 + (lane >> 4) * 4 + q;
+            if (r < R && j < J) sDY[r * J + j] = accY[i][q];
           }
         }
-        if (wv == 0) dn = wave_sum(dn);
+        if (wv < MT * MT) {
+          const int mt = wv / MT, st = wv - mt * MT;
+          const int c = st * 16 + li;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = mt * 16 + (lane >> 4) * 4 + q;
+            if (r < R && c < R) sDD[r * R + c] = accD[q];
+          }
+        }
       }
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < RW; ++rr) {
+        const int r = wv + 4 * rr;
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+          const int j = lane + 64 * jj;
+          dY[rr][jj] = (r < R && j < J) ? sDY[r * J + j] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = tid + 256 * i;
+        dD[i] = (q < RR) ? sDD[q] : 0.f;
+      }
+      // ||x||^2 of the slice's rows, summed over the block in wave order
+      dn = wave_sum(dn);
+      __syncthreads();
+      if (lane == 0) sTmp[wv] = dn;
+      __syncthreads();
+      dn = (wv == 0) ? ((sTmp[0] + sTmp[1]) + sTmp[2]) + sTmp[3] : 0.0;
+      __syncthreads();
     }
 
-    const int b = a.cur[(int64_t)gcur * a.K_cap + k];
-    const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
     const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
     const float s_old_f = (float)s_old;
-    const float *Yst = a.Y + ((int64_t)b * a.K_cap + k) * a.ys;
     float yv[RW][JW];
-    float ylo[RW][JW];   // compensation (mixed precision): Y_k = yv + ylo
+    double cpart[RW];   // row r of diag(Y_k V) before the cross-lane sum
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
       const int r = wv + 4 * rr;
+      cpart[rr] = 0.0;
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) {
         const int j = lane + 64 * jj;
-        const float yo = (!is_new && r < R && j < J) ? Yst[r * J + j] : 0.f;
+        const bool in = r < R && j < J;
         if constexpr (MX) {
-          // compensated running sum: (hi, lo) folded in FP64 and split again
-          const float *Ycst = a.Yc + ((int64_t)b * a.K_cap + k) * a.ys;
-          const float yl = (!is_new && r < R && j < J) ? Ycst[r * J + j] : 0.f;
-          const double v = touched ? s_old * ((double)yo + (double)yl) + (double)dY[rr][jj]
-                                   : (double)yo + (double)yl;
+          // compensated running sum: (hi, lo) folded in FP64 and split again;
+          // the new low word goes straight to the next buffer, the high word
+          // stays for F (whose FP32 sum does not resolve the low word)
+          const double v = touched ? s_old * ((double)yo[rr][jj] + (double)yl[rr][jj]) + (double)dY[rr][jj]
+                                   : (double)yo[rr][jj] + (double)yl[rr][jj];
           yv[rr][jj] = (float)v;
-          ylo[rr][jj] = (float)(v - (double)yv[rr][jj]);
+          if (touched && a.mode == 0 && in)
+            a.Yc[((int64_t)(1 - b) * a.K_cap + k) * a.ys + r * J + j] = (float)(v - (double)yv[rr][jj]);
+          if (in) cpart[rr] = fma(v, (double)sVt[r * J + j], cpart[rr]);
         } else {
-          yv[rr][jj] = touched ? fmaf(s_old_f, yo, dY[rr][jj]) : yo;
-          ylo[rr][jj] = 0.f;
+          yv[rr][jj] = touched ? fmaf(s_old_f, yo[rr][jj], dY[rr][jj]) : yo[rr][jj];
+          if (in) cpart[rr] = fma((double)yv[rr][jj], (double)sVt[r * J + j], cpart[rr]);
         }
       }
     }
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
       const int r = wv + 4 * rr;
-      double part = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
-        const int j = lane + 64 * jj;
-        if (r < R && j < J) part += ((double)yv[rr][jj] + (double)ylo[rr][jj]) * (double)sVt[r * J + j];
-      }
-      part = wave_sum(part);
+      const double part = wave_sum(cpart[rr]);
       if (lane == 0 && r < R) {
         sC[r] = part;
         sC2[r] = part;
       }
     }
-    const float *Dst = a.D + ((int64_t)b * a.K_cap + k) * RR;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int q = tid + 256 * i;
       if (q < RR) {
-        const float dold = is_new ? 0.f : Dst[q];
         if constexpr (MX) {
-          const float dl = is_new ? 0.f : a.Dc[((int64_t)b * a.K_cap + k) * RR + q];
-          const double v = touched ? s_old * ((double)dold + (double)dl) + (double)dD[i] : (double)dold + (double)dl;
+          const double v = touched ? s_old * ((double)dold[i] + (double)dlo[i]) + (double)dD[i]
+                                   : (double)dold[i] + (double)dlo[i];
           sDc[q] = (float)v;
           sDlo[q] = (float)(v - (double)sDc[q]);
           sM[q] = sVtV[q] * v;
         } else {
-          const float dc = touched ? fmaf(s_old_f, dold, dD[i]) : dold;
+          const float dc = touched ? fmaf(s_old_f, dold[i], dD[i]) : dold[i];
           sDc[q] = dc;
           sM[q] = sVtV[q] * (double)dc;
         }
@@ -1114,14 +1228,18 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
     __syncthreads();
     if (a.mode == 0) {
       if (wv == 0) {
-        if (!wave_cholesky(sM, R)) {
-          for (int q = lane; q < RR; q += 64)
-            sM[q] = sVtV[q] * ((double)sDc[q] + (MX ? (double)sDlo[q] : 0.0));
-          if (lane < R) sC[lane] = sC2[lane];
-          wave_sync();
-          wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
+        // Lemma 2: Gauss-Jordan in registers (lane r holds row r), the
+        // Cholesky acceptance rule; the pseudo-inverse when it fails
+        constexpr int RM = BlockRM<RW>::value;
+        double m[RM];
+#pragma unroll
+        for (int c = 0; c < RM; ++c) m[c] = (lane < R && c < R) ? sM[lane * R + c] : 0.0;
+        double rhs[1] = {lane < R ? sC2[lane] : 0.0};
+        double dpiv;
+        if (wave_gj_reg<RM, 1>(m, rhs, dpiv, R)) {
+          if (lane < R) sC[lane] = rhs[0] / dpiv;
         } else {
-          wave_chol_apply(sM, sC, R);
+          wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
         }
       }
       __syncthreads();
@@ -1137,10 +1255,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       if (r < R) {
         const double wr = sigma * sC[r];
 #pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
-          facc[rr][jj] = fmaf((float)wr, yv[rr][jj], facc[rr][jj]);
-          if constexpr (MX) facc[rr][jj] = fmaf((float)wr, ylo[rr][jj], facc[rr][jj]);
-        }
+        for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = fmaf((float)wr, yv[rr][jj], facc[rr][jj]);
       }
     }
 #pragma unroll
@@ -1170,10 +1285,6 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
         for (int jj = 0; jj < JW; ++jj) {
           const int j = lane + 64 * jj;
           if (r < R && j < J) Ynx[r * J + j] = yv[rr][jj];
-          if constexpr (MX) {
-            float *Ycnx = a.Yc + ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
-            if (r < R && j < J) Ycnx[r * J + j] = ylo[rr][jj];
-          }
         }
       }
       float *Dnx = a.D + ((int64_t)(1 - b) * a.K_cap + k) * RR;
