@@ -913,7 +913,7 @@ __device__ __forceinline__ double stage_rows(const float *__restrict__ src, int 
 // padded rank of the block variant's register solve (R <= 4 RW)
 template <int RW>
 struct BlockRM {
-  static constexpr int value = RW <= 2 ? 8 : (RW == 3 ? 12 : (RW == 4 ? 16 : (RW <= 6 ? 24 : 32)));
+  static constexpr int value = RW <= 2 ? 8 : 4 * RW;
 };
 
 // dY += U^T X and dD += U^T U for one staged block of m rows (block variant).
@@ -952,6 +952,7 @@ template <int RW, int JW, bool MX>
 __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sflag;
+  __shared__ double sDn[4];   // the waves' sums of ||x||^2 of the current slice
   const StepHeader *h = a.hdr;
   const int chunk = blockIdx.x;
   if (chunk >= h->n_chunks) return;
@@ -1020,41 +1021,47 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
     while (g < gend && a.groups[g].slice == k) ++g;
     const bool touched = g > gb;
     const bool is_new = k >= Kp;
-    // the stored Y_k and D_k are loaded first: their latency overlaps the
-    // row phase
+    // the stored Y_k and D_k (and the compensation words of the mixed path)
+    // are loaded ahead of their use: in the float32 path before the row
+    // phase, whose work hides their latency; the mixed path, short of
+    // registers there, issues them between the row products and the hand-off
     const int b = a.cur[(int64_t)gcur * a.K_cap + k];
     const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
     const int64_t ybase = ((int64_t)b * a.K_cap + k) * a.ys;
     const int64_t dbase = ((int64_t)b * a.K_cap + k) * RR;
     float yo[RW][JW];
     float yl[MX ? RW : 1][MX ? JW : 1];
-#pragma unroll
-    for (int rr = 0; rr < RW; ++rr) {
-      const int r = wv + 4 * rr;
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
-        const int j = lane + 64 * jj;
-        const bool in = !is_new && r < R && j < J;
-        yo[rr][jj] = in ? a.Y[ybase + r * J + j] : 0.f;
-        if constexpr (MX) yl[rr][jj] = in ? a.Yc[ybase + r * J + j] : 0.f;
-      }
-    }
     float dold[4], dlo[4];
+    auto load_state = [&]() {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + 256 * i;
-      const bool in = !is_new && q < RR;
-      dold[i] = in ? a.D[dbase + q] : 0.f;
-      dlo[i] = (MX && in) ? a.Dc[dbase + q] : 0.f;
-    }
-    __syncthreads();
-    if (tid < R) sW[tid] = wnext;
-    __syncthreads();
-    if (tid < R) {
-      double top = 0.0;
-      for (int r = 0; r < R; ++r) top = fmax(top, fabs(sW[r]));
-      const double w = sW[tid];
-      sWinv[tid] = (fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
+      for (int rr = 0; rr < RW; ++rr) {
+        const int r = wv + 4 * rr;
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+          const int j = lane + 64 * jj;
+          const bool in = !is_new && r < R && j < J;
+          yo[rr][jj] = in ? a.Y[ybase + r * J + j] : 0.f;
+          if constexpr (MX) yl[rr][jj] = in ? a.Yc[ybase + r * J + j] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = tid + 256 * i;
+        const bool in = !is_new && q < RR;
+        dold[i] = in ? a.D[dbase + q] : 0.f;
+        dlo[i] = (MX && in) ? a.Dc[dbase + q] : 0.f;
+      }
+    };
+    if constexpr (!MX) load_state();
+    __syncthreads();   // the previous slice is done with sW, sWinv, sDn
+    if (wv == 0) {
+      // w and its guarded reciprocal (readers sit behind the next barrier)
+      const double w = (lane < R) ? wnext : 0.0;
+      const double top = wave_max(fabs(w));
+      if (lane < R) {
+        sW[lane] = w;
+        sWinv[lane] = (fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
+      }
     }
     // the next slice's weights, in flight during this slice
     if (tid < R && k + 1 < k1) wnext = load_w(k + 1);
@@ -1067,15 +1074,15 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
 #pragma unroll
       for (int jj = 0; jj < JW; ++jj) dY[rr][jj] = 0.f;
 
-    if (touched && a.mode == 0) {
-      // Lemma 1 and the accumulation of the new rows on MFMA: FP32
-      // (16x16x4) in the float32 path, BF16 (16x16x32, FP32 sums) in the
-      // mixed path.  The tiles of dY = U^T X and dD = U^T U stay in the
-      // waves' accumulators over all blocks of the slice.
-      f32x4 accY[kMxTiles];
-      f32x4 accD = {0.f, 0.f, 0.f, 0.f};
+    // Lemma 1 and the accumulation of the new rows on MFMA: FP32 (16x16x4)
+    // in the float32 path, BF16 (16x16x32, FP32 sums) in the mixed path.
+    // The tiles of dY = U^T X and dD = U^T U stay in the waves' accumulators
+    // over all blocks of the slice.
+    f32x4 accY[kMxTiles];
+    f32x4 accD = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (touched && a.mode == 0) {
       const int NTu = (R + 15) >> 4;
       for (int gi = gb; gi < g; ++gi) {
         const Group gr = a.groups[gi];
@@ -1118,6 +1125,9 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
             accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
         }
       }
+    }
+    if constexpr (MX) load_state();
+    if (touched && a.mode == 0) {
       // hand the tiles to the [rank][column] register layout through LDS
       __syncthreads();
       float *sDY = sX;   // R x J (the row block is dead)
@@ -1162,13 +1172,10 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
         const int q = tid + 256 * i;
         dD[i] = (q < RR) ? sDD[q] : 0.f;
       }
-      // ||x||^2 of the slice's rows, summed over the block in wave order
+      // ||x||^2 of the slice's rows: wave sums, added in wave order by
+      // thread 0 behind the barrier ahead of the solve
       dn = wave_sum(dn);
-      __syncthreads();
-      if (lane == 0) sTmp[wv] = dn;
-      __syncthreads();
-      dn = (wv == 0) ? ((sTmp[0] + sTmp[1]) + sTmp[2]) + sTmp[3] : 0.0;
-      __syncthreads();
+      if (lane == 0) sDn[wv] = dn;
     }
 
     const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
@@ -1268,7 +1275,8 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
     }
     if (tid == 0) {
       const double nold = is_new ? 0.0 : a.n[(int64_t)b * a.K_cap + k];
-      const double ncur = s_old * nold + dn;
+      const double dn_all = (touched && a.mode == 0) ? ((sDn[0] + sDn[1]) + sDn[2]) + sDn[3] : 0.0;
+      const double ncur = s_old * nold + dn_all;
       nacc += ncur;
       if (touched && a.mode == 0) a.n[(int64_t)(1 - b) * a.K_cap + k] = ncur;
       if (a.mode == 0) {
@@ -1516,7 +1524,7 @@ static int launch_block_t(const PassArgs &a, int n_chunks, hipStream_t s) {
 
 size_t fused_pass_lds(int variant, int J, int R) {
   const size_t sweep = (variant == kPassWave) ? wave_lds(J, R).bytes : pass_lds(J, R).bytes;
-  const size_t cap = 160 * 1024;
+  const size_t cap = 160 * 1024 - 1024;   // the kernels' static LDS (flags, small sums) stays under 1 KiB
   const size_t with_v = std::max(sweep, finish_launch_lds(J, R));
   if (with_v <= cap) return with_v;
   const size_t base = std::max(sweep, finish_lds_bytes(J, R));
