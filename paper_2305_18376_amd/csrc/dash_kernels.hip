@@ -277,6 +277,21 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(PassArgs a, int mode)
 // Untouched slices solve on their stored (undecayed) Y_k, D_k -- w_k does not
 // depend on the common factor lambda^dt -- and enter F, G with sigma = lambda^dt.
 // ---------------------------------------------------------------------------
+// MFMA tiles.  v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; v_mfma_f32_16x16x32_bf16: A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16] (i < 8), BF16-rounded operands; both return
+// C[4 (l / 16) + i][l % 16] (i < 4) with FP32 accumulation.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 constexpr int kWaveRows = 16;   // rows per staged block
 constexpr int kWaveWarps = 8;   // waves per workgroup
 
@@ -335,7 +350,6 @@ __host__ __device__ inline WaveLds wave_lds(int J, int R) {
 template <int EPT, int DQ>
 __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
   constexpr int RC = DQ == 1 ? 8 : DQ == 2 ? 12 : 16;  // == wave_rc(R): R <= RC
-  constexpr int RPL = RC / 4;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sflag;
   const StepHeader *h = a.hdr;
@@ -440,12 +454,13 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
     double dn = 0.0;
 #pragma unroll
     for (int i = 0; i < DQ; ++i) dD[i] = 0.f;
-    // dY = U_new^T X_new as an R x J register tile: lane = column j (two
-    // 64-column halves), RC rows
-    float dy[RC][2];
+    // dY = U_new^T X_new as MFMA tiles (16 ranks x 16 columns each): lane
+    // holds dY[4 (lane / 16) + i][16 t + lane % 16] in accY[t]
+    f32x4 accY[8];
 #pragma unroll
-    for (int r = 0; r < RC; ++r) dy[r][0] = dy[r][1] = 0.f;
-    const int j0 = min(lane, J - 1), j1 = min(lane + 64, J - 1);
+    for (int t = 0; t < 8; ++t) accY[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int NT = (J + 15) >> 4;
+    const int li = lane & 15, lq = lane >> 4;
 
     if (touched && a.mode == 0) {
       for (int g = gb; g < ge; ++g) {
@@ -480,40 +495,52 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
               if (e < tot) sX[row * XS + (e - row * J)] = buf[i];
             }
           }
+          // zero rows m .. m rounded up to 4: the accumulation MFMAs take
+          // four rows at a time
+          for (int e = tot + lane; e < (((m + 3) & ~3) * J); e += 64) {
+            const int row = (int)(((float)e + 0.5f) * invJ);
+            sX[row * XS + (e - row * J)] = 0.f;
+          }
           wave_sync();
           {
-            // Lemma 1: u = (x P) * (1/w); lane (row, q) owns ranks q*RPL .. q*RPL+RPL-1.
-            // Rows >= m of the block hold stale values whose results are unused.
-            const int row = lane >> 2, rb = (lane & 3) * RPL;
-            float t[RPL];
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) t[i] = 0.f;
-            const float *xr = sX + row * XS;
-            const float *pc = sP + rb;
-#pragma unroll 4
-            for (int j = 0; j < J; ++j) {
-              const float xv = xr[j];
-#pragma unroll
-              for (int i = 0; i < RPL; ++i) t[i] = fmaf(xv, pc[j * RC + i], t[i]);
+            // Lemma 1 on MFMA: the 16 x RC tile U = (X P) * (1/w); u is set
+            // to 0 on rows >= m of the block, whatever stale X holds there
+            const float *xr = sX + li * XS;
+            const int n = min(li, RC - 1);
+            f32x4 t0 = {0.f, 0.f, 0.f, 0.f}, t1 = {0.f, 0.f, 0.f, 0.f};
+            int ks = 0;
+            for (; ks + 8 <= J; ks += 8) {
+              t0 = mfma_f32(xr[ks + lq], sP[(ks + lq) * RC + n], t0);
+              t1 = mfma_f32(xr[ks + 4 + lq], sP[(ks + 4 + lq) * RC + n], t1);
             }
+            for (; ks < J; ks += 4) {
+              const int kk = ks + lq;
+              t0 = mfma_f32(kk < J ? xr[kk] : 0.f, kk < J ? sP[kk * RC + n] : 0.f, t0);
+            }
+            const f32x4 t = t0 + t1;
+            if (li < RC) {
+              const float wi = sWinv[li];
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-              const float u = t[i] * sWinv[rb + i];
-              sU[row * RC + rb + i] = u;
-              if (a.last_pass && row < m && rb + i < R) a.U_out[(out_row + r0 + row) * R + rb + i] = u;
+              for (int i = 0; i < 4; ++i) {
+                const int row = 4 * lq + i;
+                const float u = (row < m) ? t[i] * wi : 0.f;
+                sU[row * RC + li] = u;
+                if (a.last_pass && row < m && li < R) a.U_out[(out_row + r0 + row) * R + li] = u;
+              }
             }
           }
           wave_sync();
-          // dY += u^T x (lane = column), dD += u^T u (lane = entry), padded ranks are zero
-#pragma unroll 2
-          for (int row = 0; row < m; ++row) {
-            const float x0 = sX[row * XS + j0], x1 = sX[row * XS + j1];
-            const float *ur = sU + row * RC;
+          // dY += U^T X on MFMA over the block's rows in steps of 4 (u = 0
+          // on rows >= m); dD += u^T u (lane = entry), padded ranks are zero
+          {
+            const int rn = min(li, RC - 1);
+            const int mp = (m + 3) & ~3;
+            for (int ks = 0; ks < mp; ks += 4) {
+              const float au = (li < RC) ? sU[(ks + lq) * RC + rn] : 0.f;
+              const float *xrow = sX + (ks + lq) * XS;
 #pragma unroll
-            for (int r = 0; r < RC; ++r) {
-              const float u = ur[r];
-              dy[r][0] = fmaf(u, x0, dy[r][0]);
-              dy[r][1] = fmaf(u, x1, dy[r][1]);
+              for (int t = 0; t < 8; ++t)
+                if (t < NT) accY[t] = mfma_f32(au, xrow[min(16 * t + li, J - 1)], accY[t]);
             }
           }
 #pragma unroll
@@ -533,10 +560,12 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
     wave_sync();
     float *sDY = sProd;
 #pragma unroll
-    for (int r = 0; r < RC; ++r) {
-      if (r < R) {
-        if (lane < J) sDY[r * J + lane] = dy[r][0];
-        if (lane + 64 < J) sDY[r * J + lane + 64] = dy[r][1];
+    for (int t = 0; t < 8; ++t) {
+      const int j = 16 * t + li;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 4 * lq + i;
+        if (t < NT && r < R && j < J) sDY[r * J + j] = accY[t][i];
       }
     }
     if (RJ + lane < YS) sDY[RJ + lane] = 0.f;
@@ -722,21 +751,10 @@ __host__ __device__ inline PassLds pass_lds(int J, int R, bool with_finish = tru
 // B[8 (l / 16) + i][l % 16] (i < 8) and receives C[4 (l / 16) + i][l % 16]
 // (i < 4); products of BF16-rounded operands, FP32 accumulation.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f32x4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
 // the mixed-precision tiles of one slice: wave w owns the dY column tiles
 // w, w+4, w+8, w+12 (16 columns each) for both rank tiles (accY[2 c + mt]), and
 // the dD tile w of the (R / 16)^2 rank-tile pairs
 constexpr int kMxTiles = 8;
-
-__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 // One 16 x 16 tile of X P: rows xrow (lane's row of the 16-row tile, stride
 // XS in LDS, zero rows beyond the block), columns 16 nt .. 16 nt + 15 of P
