@@ -42,13 +42,15 @@ WORKLOAD_TEXT = {
 }
 
 
-def algorithmic_bytes(M, K, K_t, J, R):
+def algorithmic_bytes(M, K, K_t, J, R, words=1):
     """Bytes one update pass must move (the per-pass model of the design notes):
     new rows read, U_new written, every slice's Y_k / D_k / n_k / W row read,
-    touched slices' Y_k / D_k / n_k written, every W row written."""
+    touched slices' Y_k / D_k / n_k written, every W row written.  `words` = 2
+    counts the compensation word the mixed path keeps beside each Y_k / D_k
+    entry."""
     return (M * J * 4 + M * R * 4
-            + K * (R * J * 4 + R * R * 4 + 8 + R * 8)
-            + K_t * (R * J * 4 + R * R * 4 + 8)
+            + K * (words * (R * J * 4 + R * R * 4) + 8 + R * 8)
+            + K_t * (words * (R * J * 4 + R * R * 4) + 8)
             + K * R * 8)
 
 
@@ -201,7 +203,8 @@ def main():
     for i in range(K_):
         b = batches[W_ + i]
         s = W_ + i + 1
-        nb = algorithmic_bytes(b.M, wl.K_at(s), b.n_groups + b.n_new, wl.J, wl.R) * wl.n_iter
+        nb = algorithmic_bytes(b.M, wl.K_at(s), b.n_groups + b.n_new, wl.J, wl.R,
+                               words=2 if args.precision == "mixed" else 1) * wl.n_iter
         bytes_all += nb
         if args.sample_every > 0 and s % args.sample_every == 0:
             bytes_pass += nb

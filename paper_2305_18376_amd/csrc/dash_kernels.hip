@@ -869,25 +869,27 @@ __device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU,
 // before its first LDS store, so the block waits for one memory latency, not
 // one per element.  Float4 loads when the rows allow them.  With SQ the
 // thread's sum of squares of what it loaded is returned (FP64).
-template <bool SQ>
+template <bool SQ, int NTH = 256>
 __device__ __forceinline__ double stage_rows(const float *__restrict__ src, int m, int J, int XS, float *sX,
                                              int tid) {
+  // NTH threads (tid < NTH) copy m * J <= 8192 floats
   double sq = 0.0;
   const int n = m * J;
   if ((J & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
     const int n4 = n >> 2;
+    constexpr int PER = (2048 + NTH - 1) / NTH;
 #pragma unroll 1
-    for (int i0 = 0; i0 < 8; i0 += 4) {
-      if (tid + 256 * i0 >= n4) break;
+    for (int i0 = 0; i0 < PER; i0 += 4) {
+      if (tid + NTH * i0 >= n4) break;
       float4 v[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int q = tid + 256 * (i0 + i);
+        const int q = tid + NTH * (i0 + i);
         v[i] = (q < n4) ? reinterpret_cast<const float4 *>(src)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int q = tid + 256 * (i0 + i);
+        const int q = tid + NTH * (i0 + i);
         if (q < n4) {
           const int e = 4 * q, row = e / J, col = e - row * J;
           float *d = sX + row * XS + col;
@@ -905,18 +907,19 @@ __device__ __forceinline__ double stage_rows(const float *__restrict__ src, int 
       }
     }
   } else {
+    constexpr int PER = (8192 + NTH - 1) / NTH;
 #pragma unroll 1
-    for (int i0 = 0; i0 < 32; i0 += 8) {
-      if (tid + 256 * i0 >= n) break;
+    for (int i0 = 0; i0 < PER; i0 += 8) {
+      if (tid + NTH * i0 >= n) break;
       float v[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int e = tid + 256 * (i0 + i);
+        const int e = tid + NTH * (i0 + i);
         v[i] = (e < n) ? src[e] : 0.f;
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int e = tid + 256 * (i0 + i);
+        const int e = tid + NTH * (i0 + i);
         if (e < n) {
           const int row = e / J;
           sX[row * XS + (e - row * J)] = v[i];
@@ -1027,6 +1030,8 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
     return (k >= Kp && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + threadIdx.x];
   };
   double wnext = (tid < R && k0 < k1) ? load_w(k0) : 0.0;
+  bool pre = false;      // the slice's first row block is already in sX
+  double dn_pre = 0.0;   // this thread's ||x||^2 of that block
 
   for (int k = k0; k < k1; ++k) {
     // the thread index, opaque to the compiler inside the loop: per-thread
@@ -1109,10 +1114,16 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
           // rows of the block the MFMA tiles cover (zero beyond m)
           const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
           __syncthreads();
-          dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
-          for (int e = tid; e < (mp - m) * J; e += 256) {
-            const int row = e / J;
-            sX[(m + row) * XS + (e - row * J)] = 0.f;
+          if (pre && gi == gb && r0 == 0) {
+            // staged by waves 1-3 during the previous slice's solve
+            dn += dn_pre;
+            dn_pre = 0.0;
+          } else {
+            dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
+            for (int e = tid; e < (mp - m) * J; e += 256) {
+              const int row = e / J;
+              sX[(m + row) * XS + (e - row * J)] = 0.f;
+            }
           }
           __syncthreads();
           // u = (x P) * (1/w): jobs (row tile, rank tile), wave w takes w and w + 4
@@ -1251,6 +1262,8 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       }
     }
     __syncthreads();
+    // the next slice has rows: its first block is staged during this solve
+    const bool next_pre = a.mode == 0 && k + 1 < k1 && g < gend && a.groups[g].slice == k + 1;
     if (a.mode == 0) {
       if (wv == 0) {
         // Lemma 2: Gauss-Jordan in registers (lane r holds row r), the
@@ -1266,6 +1279,17 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
         } else {
           wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
         }
+      } else if (next_pre) {
+        // meanwhile waves 1-3 stage the next slice's first row block (the
+        // row buffer is free from here to that slice's row phase)
+        const Group gn = a.groups[g];
+        const int m1 = min(MB, gn.nrows);
+        const int mp1 = MX ? (m1 + 31) & ~31 : (m1 + 15) & ~15;
+        dn_pre = stage_rows<true, 192>(gn.src, m1, J, XS, sX, tid - 64);
+        for (int e = tid - 64; e < (mp1 - m1) * J; e += 192) {
+          const int row = e / J;
+          sX[(m1 + row) * XS + (e - row * J)] = 0.f;
+        }
       }
       __syncthreads();
       if (tid < R) a.W[((int64_t)wout * a.K_cap + k) * R + tid] = sC[tid];
@@ -1273,6 +1297,7 @@ __global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
       if (tid < R) sC[tid] = sW[tid];
       __syncthreads();
     }
+    pre = next_pre;
     const double sigma = touched ? 1.0 : s_old;
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
