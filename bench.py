@@ -336,8 +336,9 @@ def serve_main(args):
     polls until all of them are committed.  Latency = host time from the tick
     that cut an update to the poll that saw it committed."""
     import torch
-    from paper_2305_18376_amd.dash import DashServer
+    from paper_2305_18376_amd.dash import DashServer, PREC_FP32, PREC_MIXED
     n_streams, T = 64, args.ticks
+    prec = PREC_MIXED if args.precision == "mixed" else PREC_FP32
     t0 = time.time()
     streams = serve_streams(n_streams, T)
     t_gen = time.time() - t0
@@ -347,7 +348,7 @@ def serve_main(args):
     views = []
     for d in streams:
         sid, g = srv.open(d["J"], d["R"], lam=d["lam"], max_slices=d["K_max"] + 8, max_rows=4096,
-                          max_groups=4096)
+                          max_groups=4096, precision=prec)
         g.init_from_factors(d["ptr0"], to(d["X0"]), to(d["U0"]), to(d["W"]), to(d["V"]))
         dbat = [(ids, ptr, to(X) if X.shape[0] else None, None if new is None else to(new))
                 for ids, ptr, X, new in d["batches"]]
@@ -381,7 +382,8 @@ def serve_main(args):
            "value": rows_done / t_run, "unit": "rows/s", "n_gpus": 1, "streams": n_streams,
            "ticks": T - warm, "warmup": warm, "higher_is_better": True,
            "latency_ms": {"p50": float(np.percentile(lat, 50)) / 1e3, "p99": float(np.percentile(lat, 99)) / 1e3},
-           "ms_per_tick": 1e3 * t_run / (T - warm), "dtype": "f32", "data": "synthetic",
+           "ms_per_tick": 1e3 * t_run / (T - warm),
+           "dtype": "f32" if args.precision == "fp32" else "bf16-mfma/f32", "data": "synthetic",
            "config": {"workload": "64 streams, J~U{32,64,128,256}, R~U{8,16,32}, K0~U{100..300}, "
                                   "Poisson(50) rows/tick over Zipf(1.2) slices, new slice p=0.05/tick",
                       "budget_gb": 200, "closed_loop": True},

@@ -864,15 +864,15 @@ __device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU,
   }
 }
 
-// Copy m contiguous rows of J floats from HBM into sX (row stride XS) with the
-// 256 threads of the block; m * J <= 8192.  Every load of a thread is issued
-// before its first LDS store, so the block waits for one memory latency, not
-// one per element.  Float4 loads when the rows allow them.  With SQ the
-// thread's sum of squares of what it loaded is returned (FP64).
+// Copy m contiguous rows of J floats from HBM into sX (row stride XS) with NTH
+// threads (tid < NTH); m * J <= 8192.  A thread's loads go out in batches of
+// four float4 (eight floats) before its LDS stores, so the copy waits for a few
+// memory latencies, not one per element.  Float4 loads when the rows allow
+// them.  With SQ the thread's sum of squares of what it loaded is returned
+// (FP64).
 template <bool SQ, int NTH = 256>
 __device__ __forceinline__ double stage_rows(const float *__restrict__ src, int m, int J, int XS, float *sX,
                                              int tid) {
-  // NTH threads (tid < NTH) copy m * J <= 8192 floats
   double sq = 0.0;
   const int n = m * J;
   if ((J & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {

@@ -211,6 +211,35 @@ def test_edge_cases_multi_group_new_slice_rows_and_small_blocks():
         np.testing.assert_array_equal(before[key], after[key])
 
 
+@pytest.mark.parametrize("J,R,n_iter", [(130, 20, 1), (96, 24, 2), (256, 32, 1)])
+def test_block_variant_long_groups_and_neighbours(J, R, n_iter):
+    """The workgroup-per-slice sweep: row groups longer than one staged block
+    (64 rows up to J = 128, 32 beyond), a slice extended by two groups,
+    consecutive touched slices (the next slice's first block is staged while
+    the current one solves), rows appended to a slice created in the same
+    update, blocks with fewer rows than R, untouched slices between; J = 130
+    takes the scalar row staging, the others float4 loads."""
+    Dash = _dash()
+    cfg = random_stream(17, K0=12, J=J, R=R, steps=0, n_iter=n_iter)
+    o, g = start_pair(cfg, Dash)
+    rng = np.random.default_rng(18)
+    Vt = cfg["V"]
+
+    def blk(k, m):
+        U = rng.standard_normal((m, R))
+        return ((U * rng.uniform(0.5, 1.5, R)) @ Vt.T + 0.05 * rng.standard_normal((m, J))).astype(np.float32)
+
+    for step in range(2):
+        news = [blk(0, 3), blk(0, 70)]
+        K = 12 + 2 * step
+        groups = [(1, blk(1, 150)), (2, blk(2, 5)), (3, blk(3, 65)), (4, blk(4, 2)), (1, blk(1, 33)),
+                  (7, blk(7, 1)), (8, blk(8, 97)), (K, blk(K, 4)), (K + 1, blk(K + 1, 40))]
+        feed(g, groups, news, J)
+        rep = g.update()
+        r = o.update(groups, news)
+        check_step(g, o, r, rep, tag=f"block J={J} R={R} step {step}")
+
+
 def test_errors_leave_state_unchanged_and_numeric_rollback():
     from paper_2305_18376_amd.dash import DashError, E_INVALID_ARG, E_NUMERIC, E_CAPACITY
     Dash = _dash()
