@@ -111,7 +111,7 @@ def main():
                          "(reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the update would shard by slice with one all-reduce of F, G per pass).", file=sys.stderr)
         sys.exit(2)
 
