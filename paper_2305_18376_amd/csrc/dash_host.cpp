@@ -126,6 +126,7 @@ struct dash_ctx {
   bool spans_on = false;                   // collect every reaped update's device span
   std::vector<float> spans;                // spans (ms) of the reaped updates
   int chunk_override = 0;
+  int block_per_cu = 2;     // resident block-variant workgroups per CU (chunking)
   std::vector<int> order;  // scratch
   // profiling: event pairs around launches, folded into stats on read
   bool profiling = false;   // events around this update's launches
@@ -176,7 +177,13 @@ int choose_chunk(const dash_ctx *c, int K) {
     while ((K + ch - 1) / ch > kMaxChunks) ++ch;
     return ch;
   }
-  const int ch = pass_chunk(c->sched.variant, K, c->n_cu) * c->sched.spread;
+  int ch = pass_chunk(c->sched.variant, K, c->n_cu);
+  if (c->sched.variant == kPassBlock && c->block_per_cu == 1) {
+    // one resident workgroup per CU: one round of workgroups, not two
+    const int n = std::max(1, c->n_cu);
+    ch = std::max(ch, (K + n - 1) / n);
+  }
+  ch *= c->sched.spread;
   int out = std::max(1, std::min(ch, K));
   while ((K + out - 1) / out > kMaxChunks) ++out;
   return out;
@@ -611,6 +618,13 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->sched = Schedule{c->variant, 1, c->fused_lds > 0 ? 1 : 0};
   if (const char *e = std::getenv("DASH_DESC_FETCH")) c->desc_fetch = std::atoi(e) != 0;
   if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
+  {
+    // the block sweep keeps two workgroups per CU unless its registers (mixed
+    // path, or more than 24 ranks: over 256 per lane) or its LDS allow one
+    const size_t lds = fused_pass_lds(kPassBlock, cfg->J, cfg->R) + 1024;
+    const bool regs_one = cfg->precision == DASH_PREC_MIXED || cfg->R > 24;
+    c->block_per_cu = (regs_one || 2 * lds > 160 * 1024) ? 1 : 2;
+  }
   auto bail = [&](dash_status s) {
     dash_destroy(c);
     return s;
