@@ -30,9 +30,12 @@ in the design notes of the repository):
     verbatim: the old part of c_k, F, G is the value stored at the previous
     update, scaled by lambda.
   * a new slice's S_k, needed by Lemma 1 before it exists, starts at the identity.
-  * singular systems: Cholesky, with an eigen pseudo-inverse (cutoff 1e-12 of
-    the largest eigenvalue) when a pivot is not positive enough; 1/w := 0 for
-    |w| <= 1e-12 max|w|.
+  * singular systems (S_k V^T V S_k of Lemma 1, V^T V * D_k of Lemma 2, G of
+    Lemma 3): Cholesky, with the eigen pseudo-inverse (cutoff 1e-12 of the
+    largest eigenvalue) when a pivot is not positive enough.  Every solve is
+    then the minimum-norm least-squares solution of its sub-problem; in
+    particular a zero weight in S_k is not inverted (Lemma 1 is written with
+    S_k V^T V S_k, not with S_k^{-1}).
   * an update with no rows is a no-op (no decay).
   * the initial decomposition (Sec. 3.2.1 "Initialization") is PARAFAC2-ALS:
     V0 = top-R eigenvectors of sum_k X_k^T X_k (sign: largest-magnitude entry of
@@ -50,7 +53,6 @@ from scipy.linalg import cho_solve
 
 PIVOT_REL = 1e-12      # Cholesky pivot threshold, relative to the largest diagonal entry
 EIG_CUTOFF = 1e-12     # pseudo-inverse / inverse-square-root eigenvalue cutoff (relative)
-W_CUTOFF = 1e-12       # 1/w := 0 below this fraction of max|w|
 
 
 # ---------------------------------------------------------------------------
@@ -90,16 +92,6 @@ def inv_sqrt_psd(P: np.ndarray):
     keep = lam > EIG_CUTOFF * top if top > 0 else np.zeros_like(lam, dtype=bool)
     Zk = Z[:, keep]
     return (Zk / np.sqrt(lam[keep])) @ Zk.T, Zk @ Zk.T
-
-
-def safe_reciprocal(w: np.ndarray) -> np.ndarray:
-    """Entry-wise 1/w with 0 for entries that are negligible relative to max|w|."""
-    w = np.asarray(w, dtype=np.float64)
-    top = np.max(np.abs(w)) if w.size else 0.0
-    out = np.zeros_like(w)
-    nz = np.abs(w) > W_CUTOFF * top
-    out[nz] = 1.0 / w[nz]
-    return out
 
 
 def top_eigvecs(Gm: np.ndarray, R: int) -> np.ndarray:
@@ -360,9 +352,11 @@ class DashOracle:
         for it in range(self.n_iter):
             V_in, W_in = self.V.copy(), self.W.copy()
             VtV = self.V.T @ self.V
-            # Lemma 1: U_new = X_new V S_k (S_k V^T V S_k)^{-1} = X_new V (V^T V)^{-1} S_k^{-1}
-            B = spd_solve(VtV, np.eye(R))
-            Un = {k: X @ self.V @ B @ np.diag(safe_reciprocal(self.W[k])) for k, X in Xn.items()}
+            # Lemma 1: U_new = X_new V S_k (S_k V^T V S_k)^{-1}, one R x R system per slice
+            Un = {}
+            for k, X in Xn.items():
+                S = np.diag(self.W[k])
+                Un[k] = spd_solve(S @ VtV @ S, (X @ self.V @ S).T).T
             # Lemma 2 with eq. [obtain_CandD]
             Y, D = list(Yo), list(Do)
             for k, U in Un.items():
