@@ -58,7 +58,15 @@ typedef struct dash_config {
                                 on BF16 MFMA with FP32 sums; the running sums Y_k, D_k
                                 FP32 plus an FP32 compensation word each, folded in
                                 FP64 (twice the state bytes); R x R solves FP64       */
-  int32_t stats_mode;        /* DASH_STATS_EXACT                                         */
+  int32_t stats_mode;        /* DASH_STATS_EXACT: Lemmas 2-3 evaluated exactly from the
+                                running sums Y_k = sum lambda^age U^T X, D_k with the
+                                current V, S_k (reads every Y_k each pass);
+                                DASH_STATS_LAGGED: Algorithm 1's recursions
+                                (eq. [obtain_CandC], [obtain_FandF], [obtain_FandG]):
+                                c_k, F, G keep the terms of past updates as they were
+                                computed, scaled by lambda, so a pass reads only the new
+                                rows and each slice's D_k, c_k; the reported fit then
+                                evaluates eq. [new_loss] with those F, G                */
   int64_t max_slices;        /* capacity in slices (K never exceeds it)                  */
   int64_t max_rows_per_update;   /* capacity in rows staged for one update               */
   int64_t max_groups_per_update; /* capacity in row groups staged for one update         */
@@ -79,6 +87,14 @@ typedef struct dash_update_report {
   double sum_n;      /* sum over slices of the forgetting-weighted squared norms    */
   double device_us;  /* device time of the update: from its first launch starting
                         to its final phase ending (device realtime clock)       */
+  /* anomaly scores (dash_anomaly on, else 0), Sec. 3.4 with the threshold of
+     Sec. 4.5: */
+  double te;            /* tensor-level error (Definition 2): mean over the slices
+                           that received rows of their se_k (Definition 1)        */
+  double te_threshold;  /* mean + population std of the previous `window` te of
+                           this context (+inf while there is none)             */
+  int32_t te_anomaly;   /* 1 if te > te_threshold                               */
+  int32_t n_anomalies;  /* slices whose se_k exceeded their own moving threshold */
 } dash_update_report;
 
 typedef struct dash_init_report {
@@ -263,6 +279,27 @@ dash_status dash_graph(dash_ctx *ctx, int32_t enable);
  * dash_spans(ctx, 0) stops; either call clears the list. */
 dash_status dash_spans(dash_ctx *ctx, int32_t enable);
 dash_status dash_spans_read(dash_ctx *ctx, float *ms, int32_t cap, int32_t *n);
+
+/* Anomaly scores (Sec. 3.4, Definitions 1-2; threshold of Sec. 4.5): with
+ * window >= 1 every later update also computes, with its updated S_k and V,
+ *   se_k = sum_{i,j} |X_{k,new} - U_{k,new} S_k V^T|_{ij} / (I_{k,new} J)
+ * for each slice that received rows, flags the slices whose se_k exceeds the
+ * mean plus the population standard deviation of that slice's previous
+ * `window` scores, and reports te (the mean of se_k) with the same threshold
+ * over the context's previous te (dash_update_report).  The kernel re-reads
+ * the update's rows (J floats per row) after the final phase; updates with
+ * scores on are launched directly (no graph replay).  window = 0 turns the
+ * scores off; enabling clears every history.  Allocates its buffers here.
+ * Errors: DASH_E_INVALID_ARG (window < 0), DASH_E_OUT_OF_MEMORY. */
+dash_status dash_anomaly(dash_ctx *ctx, int32_t window);
+
+/* The slice-level scores of the last committed update that was scored: for
+ * at most cap of its slices, in ascending slice id, slice[i] (host int32),
+ * se[i] (host float) and flag[i] (host int32, 1 = anomaly); *n receives the
+ * count.  Waits for outstanding updates.  Errors: DASH_E_BAD_STATE when
+ * scores are off, DASH_E_INVALID_ARG. */
+dash_status dash_get_slice_errors(dash_ctx *ctx, int32_t *slice, float *se, int32_t *flag, int32_t cap,
+                                  int32_t *n);
 
 /* Device bytes that dash_create allocates for cfg (the admission footprint of
  * a served stream).  Errors: DASH_E_INVALID_ARG. */

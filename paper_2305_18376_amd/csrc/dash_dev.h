@@ -13,16 +13,16 @@ constexpr int kMaxR = 32;             // rank limit: one wave64 owns an R x R fa
 constexpr int kMaxJ = 256;            // column limit: a row of Y_k is <= 4 floats per lane
 constexpr double kPivotRel = 1e-12;   // Cholesky pivot threshold relative to max diagonal
 constexpr double kEigCutoff = 1e-12;  // pseudo-inverse / inverse-sqrt eigenvalue cutoff
-constexpr double kWCutoff = 1e-12;    // 1/w := 0 below this fraction of max|w|
 constexpr int kReportRing = 64;       // pinned report slots (updates in flight)
 constexpr int kMaxChunks = 4096;      // bound on sweep chunks (partials memory)
 constexpr int kChunksPerRGroup = 16;  // first-level reduction fan-in
 
 // Per-update descriptor block, written by the host into pinned memory and
-// copied to the device once per update (one hipMemcpyAsync):
-//   StepHeader | int32 chunk_gptr[n_chunks+1] | Group groups[n_groups]
+// copied to the device by a fetch kernel once per update:
+//   StepHeader | int32 chunk_gptr[n_chunks+1] | Group groups[n_groups] | Item items[n_items]
 // Groups are sorted by slice (ingest order within a slice); chunk c covers
-// slices [c*chunk, (c+1)*chunk) and its groups start at chunk_gptr[c].
+// slices [c*chunk, (c+1)*chunk) and its groups start at chunk_gptr[c].  Items
+// list the touched slices, most rows first.
 struct StepHeader {
   int32_t K;          // slices after the update
   int32_t K_prev;     // slices before it (ids >= K_prev are new)
@@ -31,10 +31,19 @@ struct StepHeader {
   int32_t chunk;      // slices per chunk
   int32_t n_rgroups;  // first-level reduction groups of chunk partials
   int32_t chunks_per_rgroup;
-  int32_t pad;
+  int32_t n_items;    // touched slices (split sweep: the row stage's work items)
   int64_t step;       // 1-based index of this update (the committed index for evaluations)
   int64_t M;          // rows in the update
   void *report;       // device-visible pointer to this update's pinned report slot
+  int32_t n_chunks2;  // split sweep: solve-stage chunks (chunk2 slices each)
+  int32_t chunk2;     // a sweep chunk is (chunk / chunk2) solve chunks
+  int32_t seq;        // enqueue sequence number (never reused, rolled-back updates included)
+  int32_t pad;
+};
+
+// One touched slice of an update: its row groups are groups[g0 .. g1).
+struct Item {
+  int32_t slice, g0, g1, rows;
 };
 
 struct Group {        // contiguous rows of one slice, in the caller's buffer
@@ -59,22 +68,27 @@ struct Report {
   int32_t K, committed;
   double fit, loss, sum_n;
   uint64_t t_start, t_end;   // device realtime clock (100 MHz) at the update's first and last launch
-  int32_t done, pad;
+  double te;                 // tensor-level error of the update (anomaly scores on)
+  int32_t n_anomalies;       // slices flagged by the slice-level threshold
+  int32_t done;
 };
 constexpr double kRealtimeMHz = 100.0;
 
 // One "V bundle": everything a pass needs from V, double-buffered.
 //   V64  [J][R]  float64 master
 //   VtV  [R][R]  float64 V^T V
+//   piv  [R]     float64 elimination pivots of V^T V (the squares of its Cholesky
+//                diagonal; all 0 when V^T V failed the acceptance rule)
 //   Vt32 [R][J]  float32 V^T   (for c_k = diag(Y_k V))
-//   P32  [J][R]  float32 V (V^T V)^{-1}  (Lemma 1 projector)
+//   P32  [J][R]  float32 V (V^T V)^{-1}  (Lemma 1 projector; pseudo-inverse if singular)
 struct VBundleView {
-  double *V64, *VtV;
+  double *V64, *VtV, *piv;
   float *Vt32, *P32;
 };
 
 __host__ __device__ inline int64_t vb_bytes(int J, int R) {
-  int64_t b = (int64_t)J * R * 8 + (int64_t)R * R * 8 + (int64_t)R * J * 4 + (int64_t)J * R * 4;
+  int64_t b = (int64_t)J * R * 8 + (int64_t)R * R * 8 + (int64_t)R * 8 + (int64_t)R * J * 4 +
+              (int64_t)J * R * 4;
   return (b + 255) / 256 * 256;
 }
 
@@ -82,7 +96,8 @@ __host__ __device__ inline VBundleView vb_view(char *base, int J, int R) {
   VBundleView v;
   v.V64 = (double *)base;
   v.VtV = v.V64 + (int64_t)J * R;
-  v.Vt32 = (float *)(v.VtV + (int64_t)R * R);
+  v.piv = v.VtV + (int64_t)R * R;
+  v.Vt32 = (float *)(v.piv + R);
   v.P32 = v.Vt32 + (int64_t)R * J;
   return v;
 }
@@ -127,13 +142,48 @@ struct PassArgs {
   int mixed;           // 1: Lemma 1 and the row accumulation on BF16 MFMA (FP32 sums)
   int stamp_start;     // 1: the first pass's workgroup 0 stamps the report's start time
   int lds_bytes;       // dynamic LDS of the sweep launch
+  // split sweep (row stage, solve stage, F stage, final phase)
+  const Item *items;   // [n_items] touched slices, heaviest first
+  double *cbuf;        // [K_cap][R] c_k of the touched slices of the current pass
+  double *part2;       // [n_chunks2][R*R + 1] solve-stage partials (G, sum n)
+  int32_t *tag;        // [K_cap] seq of the update that last touched the slice
+  int32_t *queue;      // row-stage counters (zero between launches): [0] work queue,
+                       // [1] deferred slices, [2] their work queue
+  int32_t *slow_list;  // [K_cap] items deferred to Lemma 1's pseudo-inverse form
+  int lagged;          // DASH_STATS_LAGGED: Algorithm 1's recursions for c_k, F, G
+  double *cst;         // lagged: [2][K_cap][R] stored c_k (buffer by cur)
+  double *FG;          // lagged: [2][R*J + R*R] F^T then G (buffer by gcur)
+  int defer_done;      // 1: the final phase leaves the report's done flag to the anomaly scores
 };
 
-// Kernel variants of the sweep.
-enum { kPassWave = 0, kPassBlock = 1 };
+// Buffers of the anomaly scores (dash_anomaly): per touched slice of the last
+// scored update se, flag, slice id ([G_cap] each, in item order), per slice a
+// ring of its previous errors ([K_cap][window]) and their count, a ticket.
+struct AnomalyArgs {
+  float *se;
+  int32_t *flag;
+  int32_t *sid;
+  float *hist;
+  int32_t *hcnt;
+  int32_t *ticket;
+  int window;
+};
+int launch_slice_errors(const PassArgs &a, const AnomalyArgs &x, int n_blocks, hipStream_t s);
 
-// Launchers (dash_kernels.hip).
-// Choose the sweep variant for (J, R); returns kPassWave or kPassBlock.
+// One workgroup of a launch that serves several contexts (a serving tick): the
+// context's pass arguments (device copy) and the workgroup's index among that
+// context's workgroups.  Launches for one context pass no map: workgroup i of
+// the launch is its workgroup i.
+struct BlockMap {
+  const PassArgs *args;
+  int32_t local;
+  int32_t pad;
+};
+
+// Kernel variants of the sweep: one fused launch with one wave per slice, or
+// the split sweep (row stage, solve stage, F stage, final phase).
+enum { kPassWave = 0, kPassSplit = 1 };
+
 // Arguments of the initial-decomposition kernels (PARAFAC2-ALS, Sec. 3.2.1).
 struct InitArgs {
   int J, R, K;
@@ -166,10 +216,45 @@ int launch_init_start(const InitArgs &a, hipStream_t s);
 int launch_init_iteration(const InitArgs &a, hipStream_t s);
 int launch_init_handoff(const InitArgs &a, hipStream_t s);
 
-int pass_variant(int J, int R, int precision);
+// Launchers (dash_kernels.hip).
+// Default sweep variant for (J, R, precision, stats mode): kPassWave or kPassSplit.
+int pass_variant(int J, int R, int precision, int lagged);
 // Slices per workgroup for a variant and slice count.
 int pass_chunk(int variant, int K, int n_cu);
 int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s);
+// Split sweep launchers (dash_split.hip).  Row stage: n_blocks persistent
+// workgroups pulling touched slices from a.queue, then a small launch for the
+// slices whose Lemma 1 system needs the pseudo-inverse; solve stage: n_chunks2
+// workgroups; F stage: n_chunks workgroups (each sums its solve chunks' G, n
+// and arrives at the two-level reduction; the final phase is a separate launch).
+// The kernels read their arguments from device memory: `args` (a context's
+// PassArgs, device copy) with map = NULL, or map[n_blocks] (several contexts
+// of one kernel class: a = the host copy of any of them, for the template
+// choice).  The row stage's deferred-slice launch takes kSlowBlocks
+// workgroups per context.
+constexpr int kSlowBlocks = 32;
+// lds: dynamic LDS of the launch (0: the layout of a; a launch for several
+// contexts passes the largest of theirs).
+int launch_split_rows(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
+                      size_t lds = 0);
+int launch_split_rows_slow(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks,
+                           hipStream_t s, size_t lds = 0);
+int split_rows_blocks_per_cu(int J, int R, int mixed);
+int launch_split_solve(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
+                       size_t lds = 0);
+int launch_split_fsum(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
+                      size_t lds = 0);
+int launch_finish_dev(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, int mode,
+                      hipStream_t s, size_t lds = 0);
+size_t split_rows_lds(int J, int R);
+size_t split_solve_lds(int J, int R);
+size_t split_fsum_lds(int J, int R, int lagged);
+size_t finish_dev_lds(int J, int R);
+// Kernel classes (launches that may share contexts): equal keys, one launch.
+int split_rows_class(int J, int R, int mixed);
+int split_solve_class(int R);
+int split_fsum_class(int J, int R, int lagged, int mixed);
+int finish_class(int R);
 // Copy bytes (a multiple of 16 not required) from a device-visible pinned host
 // block to device memory with a kernel on stream s.
 int launch_fetch(const char *src_mapped, char *dst, size_t bytes, void *report, hipStream_t s);

@@ -28,6 +28,7 @@ using namespace dash;
 namespace {
 
 constexpr int kStages = 4;             // pinned descriptor blocks in rotation
+constexpr int kMaxChunks2 = 8192;      // bound on solve-stage chunks of the split sweep
 
 struct PendingGroup {
   int32_t slice;
@@ -43,6 +44,8 @@ struct InFlight {
   int slot;
   int cand;        // autotuning candidate the update ran with, or -1
   double bytes;    // its algorithmic bytes (the autotuner's cost unit)
+  int n_items;     // slices that received rows
+  bool scored;     // anomaly scores were computed
 };
 
 // How an update is launched: sweep variant, slices per wave (or workgroup)
@@ -78,11 +81,28 @@ struct dash_ctx {
   double *partials = nullptr;
   double *gpart = nullptr;
   int32_t *counters = nullptr;
+  // split sweep
+  double *cbuf = nullptr;    // [K_cap][R] c_k of touched slices
+  double *part2 = nullptr;   // [kMaxChunks2][R*R+1]
+  int32_t *tag = nullptr;    // [K_cap]
+  int32_t *queue = nullptr;  // row-stage counters [4]
+  int32_t *slow_list = nullptr;   // [K_cap] deferred row-stage items
+  double *cst = nullptr;     // lagged: [2][K_cap][R]
+  double *FG = nullptr;      // lagged: [2][R*J + R*R]
+  int32_t seq = 0;           // enqueue sequence (never reused)
+  int rows_blocks = 0;       // row-stage workgroups per launch
+  size_t off_items = 0;      // descriptor offset of the items of the update being built
+  int n_items = 0, n_chunks2 = 0, chunk2 = 0;
+  // anomaly scores (dash_anomaly)
+  int anom_window = 0;
+  AnomalyArgs anom{};
+  std::deque<double> te_hist;   // te of committed scored updates (the last anom_window)
+  int anom_n_last = -1;         // slices scored by the last committed scored update
   int64_t *d_rowptr = nullptr;
   char *dstep[kStages] = {nullptr, nullptr, nullptr, nullptr};   // device copies of the stages
   char *hstage_dev[kStages] = {nullptr, nullptr, nullptr, nullptr};   // device view of the pinned stages
   bool desc_fetch = true;   // true: copy each descriptor to device memory first; false: kernels read it in place
-  size_t off_gptr = 0, off_groups = 0, step_bytes = 0;
+  size_t off_args = 0, off_gptr = 0, off_groups = 0, step_bytes = 0;   // descriptor layout
   int variant = kPassWave;
   Schedule sched{kPassWave, 1, 1};         // current schedule
   // autotuning (dash_autotune): candidates tried in turn over the next updates,
@@ -126,7 +146,6 @@ struct dash_ctx {
   bool spans_on = false;                   // collect every reaped update's device span
   std::vector<float> spans;                // spans (ms) of the reaped updates
   int chunk_override = 0;
-  int block_per_cu = 2;     // resident block-variant workgroups per CU (chunking)
   std::vector<int> order;  // scratch
   // profiling: event pairs around launches, folded into stats on read
   bool profiling = false;   // events around this update's launches
@@ -171,18 +190,35 @@ hipError_t dalloc(T **p, size_t bytes) {
   return hipMalloc((void **)p, bytes < 256 ? 256 : bytes);
 }
 
+// Split sweep chunking: F-stage chunks of c3 slices (about two workgroups per
+// CU), solve-stage chunks of c2 slices (about eight per CU); c3 is a multiple
+// of c2 so that every F-stage chunk sums whole solve chunks.
+void split_chunks(const dash_ctx *c, int K, int *c3_out, int *c2_out) {
+  const int n = std::max(1, c->n_cu);
+  int c3 = std::max(1, (K + 2 * n - 1) / (2 * n));
+  if (c->chunk_override > 0) c3 = c->chunk_override;
+  c3 *= c->sched.spread;
+  int c2 = std::max(1, std::min(c3, (K + 8 * n - 1) / (8 * n)));
+  while ((K + c2 - 1) / c2 > kMaxChunks2) ++c2;
+  c3 = std::max(c3, c2);
+  c3 = (c3 + c2 - 1) / c2 * c2;
+  while ((K + c3 - 1) / c3 > kMaxChunks) c3 += c2;
+  *c3_out = c3;
+  *c2_out = c2;
+}
+
 int choose_chunk(const dash_ctx *c, int K) {
+  if (c->sched.variant == kPassSplit) {
+    int c3, c2;
+    split_chunks(c, K, &c3, &c2);
+    return c3;
+  }
   if (c->chunk_override > 0) {
     int ch = c->chunk_override;
     while ((K + ch - 1) / ch > kMaxChunks) ++ch;
     return ch;
   }
   int ch = pass_chunk(c->sched.variant, K, c->n_cu);
-  if (c->sched.variant == kPassBlock && c->block_per_cu == 1) {
-    // one resident workgroup per CU: one round of workgroups, not two
-    const int n = std::max(1, c->n_cu);
-    ch = std::max(ch, (K + n - 1) / n);
-  }
   ch *= c->sched.spread;
   int out = std::max(1, std::min(ch, K));
   while ((K + out - 1) / out > kMaxChunks) ++out;
@@ -266,7 +302,14 @@ hipError_t stage_done(dash_ctx *c, int s) {
   return hipEventRecord(c->stage_ev[s], c->stream);
 }
 
+// Pass arguments of the update whose descriptor block sits at device address d.
+PassArgs base_args_at(const dash_ctx *c, const char *d);
+
 PassArgs base_args(const dash_ctx *c, int s) {
+  return base_args_at(c, c->desc_fetch ? c->dstep[s] : c->hstage_dev[s]);
+}
+
+PassArgs base_args_at(const dash_ctx *c, const char *d) {
   PassArgs a{};
   a.J = c->J;
   a.R = c->R;
@@ -274,7 +317,6 @@ PassArgs base_args(const dash_ctx *c, int s) {
   a.lambda = c->cfg.lambda;
   a.log2_lambda = std::log2(c->cfg.lambda);
   a.K_cap = c->K_cap;
-  const char *d = c->desc_fetch ? c->dstep[s] : c->hstage_dev[s];
   a.hdr = (const StepHeader *)d;
   a.chunk_gptr = (const int32_t *)(d + c->off_gptr);
   a.groups = (const Group *)(d + c->off_groups);
@@ -298,7 +340,86 @@ PassArgs base_args(const dash_ctx *c, int s) {
   a.mixed = c->cfg.precision == DASH_PREC_MIXED ? 1 : 0;
   a.stamp_start = c->desc_fetch ? 0 : 1;
   a.lds_bytes = flds;
+  a.items = (const Item *)(d + c->off_items);
+  a.cbuf = c->cbuf;
+  a.part2 = c->part2;
+  a.tag = c->tag;
+  a.queue = c->queue;
+  a.slow_list = c->slow_list;
+  a.lagged = c->cfg.stats_mode == DASH_STATS_LAGGED ? 1 : 0;
+  a.cst = c->cst;
+  a.FG = c->FG;
+  a.defer_done = c->anom_window > 0 ? 1 : 0;
   return a;
+}
+
+// The anomaly-score fields of a reaped update's report: te from the device,
+// its moving threshold over this context's previous te (host).
+void score_report(dash_ctx *c, const InFlight &f, const Report &r, dash_update_report *out) {
+  out->te = 0.0;
+  out->te_threshold = 0.0;
+  out->te_anomaly = 0;
+  out->n_anomalies = 0;
+  if (!f.scored || !r.committed) return;
+  out->te = r.te;
+  out->n_anomalies = r.n_anomalies;
+  double thr = INFINITY;
+  const size_t n = c->te_hist.size();
+  if (n > 0) {
+    double mean = 0.0, var = 0.0;
+    for (double v : c->te_hist) mean += v;
+    mean /= (double)n;
+    for (double v : c->te_hist) var += (v - mean) * (v - mean);
+    thr = mean + std::sqrt(var / (double)n);
+  }
+  out->te_threshold = thr;
+  out->te_anomaly = r.te > thr ? 1 : 0;
+  c->te_hist.push_back(r.te);
+  while ((int)c->te_hist.size() > c->anom_window) c->te_hist.pop_front();
+  c->anom_n_last = f.n_items;
+}
+
+// Device address of the pass arguments of pass p in the descriptor at d.
+const PassArgs *args_dev(const dash_ctx *c, const char *d, int p) {
+  return (const PassArgs *)(d + c->off_args) + p;
+}
+
+// Write the pass arguments of every pass into the descriptor block (host
+// copy blk, device address d) for the split sweep's kernels.
+void write_pass_args(const dash_ctx *c, char *blk, const char *d, int mode) {
+  PassArgs *pa = (PassArgs *)(blk + c->off_args);
+  const int n = mode == 0 ? c->cfg.n_iter : 1;
+  for (int p = 0; p < n; ++p) {
+    PassArgs a = base_args_at(c, d);
+    a.fuse = 0;
+    a.mode = mode;
+    a.pass = p;
+    a.last_pass = (mode == 0 && p == n - 1) ? 1 : 0;
+    pa[p] = a;
+  }
+}
+
+// The launches of one split-sweep pass: row stage (and its deferred slices),
+// solve stage, F stage, final phase.  a: host copy of the pass's arguments,
+// ad: their device copy.
+dash_status enqueue_split_pass(dash_ctx *c, const PassArgs &a, const PassArgs *ad, int n_items, int n_chunks2,
+                               int n_chunks) {
+  if (a.mode == 0 && n_items > 0) {
+    HIP_OR_FAIL(c, prof_begin(c, kProfPass));
+    LAUNCH_OR_FAIL(c, launch_split_rows(a, ad, nullptr, std::min(n_items, c->rows_blocks), c->stream));
+    LAUNCH_OR_FAIL(c, launch_split_rows_slow(a, ad, nullptr, kSlowBlocks, c->stream));
+    HIP_OR_FAIL(c, prof_end(c));
+  }
+  HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
+  LAUNCH_OR_FAIL(c, launch_split_solve(a, ad, nullptr, n_chunks2, c->stream));
+  HIP_OR_FAIL(c, prof_end(c));
+  HIP_OR_FAIL(c, prof_begin(c, kProfReduce));
+  LAUNCH_OR_FAIL(c, launch_split_fsum(a, ad, nullptr, n_chunks, c->stream));
+  HIP_OR_FAIL(c, prof_end(c));
+  HIP_OR_FAIL(c, prof_begin(c, kProfCommit));
+  LAUNCH_OR_FAIL(c, launch_finish_dev(a, ad, nullptr, 1, a.mode == 0 ? 0 : 2, c->stream));
+  HIP_OR_FAIL(c, prof_end(c));
+  return DASH_OK;
 }
 
 // Enqueue an evaluation sweep of the committed state (F, G with the committed
@@ -310,6 +431,8 @@ dash_status enqueue_eval(dash_ctx *c, int K) {
   StepHeader *h = stage_header(blk);
   const int ch = choose_chunk(c, K);
   const int nch = (K + ch - 1) / ch;
+  int c3 = ch, c2 = ch;
+  if (c->sched.variant == kPassSplit) split_chunks(c, K, &c3, &c2);
   std::memset(h, 0, sizeof *h);
   h->K = K;
   h->K_prev = K;
@@ -321,16 +444,28 @@ dash_status enqueue_eval(dash_ctx *c, int K) {
   h->step = c->step;
   h->M = 0;
   h->report = nullptr;
+  h->n_items = 0;
+  h->chunk2 = c2;
+  h->n_chunks2 = (K + c2 - 1) / c2;
+  h->seq = ++c->seq;
   int32_t *gptr = (int32_t *)(blk + c->off_gptr);
   for (int i = 0; i <= nch; ++i) gptr[i] = 0;
   const size_t bytes = c->off_gptr + sizeof(int32_t) * (nch + 1);
+  c->off_items = c->off_groups;
+  const char *d = c->desc_fetch ? c->dstep[s] : c->hstage_dev[s];
+  if (c->sched.variant == kPassSplit) write_pass_args(c, blk, d, 1);
   HIP_OR_FAIL(c, upload_stage(c, s, bytes, false, nullptr));
   PassArgs a = base_args(c, s);
   a.pass = 0;
   a.last_pass = 0;
   a.mode = 1;
-  LAUNCH_OR_FAIL(c, launch_pass(a, c->sched.variant, nch, c->stream));
-  if (!a.fuse) LAUNCH_OR_FAIL(c, launch_finish(a, 2, c->stream));
+  if (c->sched.variant == kPassSplit) {
+    a.fuse = 0;
+    if (dash_status st = enqueue_split_pass(c, a, args_dev(c, d, 0), 0, h->n_chunks2, nch)) return st;
+  } else {
+    LAUNCH_OR_FAIL(c, launch_pass(a, c->sched.variant, nch, c->stream));
+    if (!a.fuse) LAUNCH_OR_FAIL(c, launch_finish(a, 2, c->stream));
+  }
   HIP_OR_FAIL(c, stage_done(c, s));
   return DASH_OK;
 }
@@ -378,11 +513,16 @@ int64_t context_footprint(const dash_config *cfg) {
   const int64_t plen = partial_len(cfg->J, cfg->R);
   const int64_t G_cap = cfg->max_groups_per_update + Kc;
   auto al = [](int64_t b) { return (b < 256 ? 256 : b + 255) / 256 * 256; };
+  const size_t off_gptr = align_up(align_up(sizeof(StepHeader), 64) + sizeof(PassArgs) * cfg->n_iter, 64);
   const int64_t step_bytes = (int64_t)align_up(
-      align_up(align_up(sizeof(StepHeader), 64) + sizeof(int32_t) * (n_chunks_cap + 1), 64) +
-          sizeof(Group) * G_cap, 256);
+      align_up(align_up(off_gptr + sizeof(int32_t) * (n_chunks_cap + 1), 64) + sizeof(Group) * G_cap, 64) +
+          sizeof(Item) * G_cap, 256);
   const int64_t carry = cfg->precision == DASH_PREC_MIXED ? al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) : 0;
-  return carry + al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) + al(8 * 2 * Kc) + al(2 * Kc) + al(4 * 2 * Kc) +
+  const int64_t lag = cfg->stats_mode == DASH_STATS_LAGGED
+                          ? al(8 * 2 * Kc * R) + al(8 * 2 * ((int64_t)cfg->J * R + R * R)) : 0;
+  const int64_t split = al(8 * Kc * R) + al(8 * std::min<int64_t>(Kc, kMaxChunks2) * (R * R + 1)) +
+                        al(4 * Kc) + al(16) + al(4 * Kc);
+  return carry + lag + split + al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) + al(8 * 2 * Kc) + al(2 * Kc) + al(4 * 2 * Kc) +
          al(8 * 2 * Kc * R) + al(2 * (int64_t)vb_bytes(cfg->J, cfg->R)) + al(sizeof(Ctl)) +
          al(4 * cfg->max_rows_per_update * R) + al(8 * n_chunks_cap * plen) +
          al(8 * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) +
@@ -425,25 +565,40 @@ void graph_reset(dash_ctx *c) {
 }
 
 // Enqueue the launches of one update (stage s, descriptor bytes, nch chunks)
-// as a graph.  The first call captures fetch -> (sweep [-> final phase]) x n_iter
-// and instantiates it; later calls rewrite every kernel node's grid and
-// arguments for this update and relaunch the same executable graph.
-dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report) {
+// as a graph.  The first call captures the update's launches -- fetch, then per
+// pass the fused sweep [and final phase], or the split sweep's row, solve, F
+// and final-phase launches -- and instantiates them; later calls rewrite every
+// kernel node's grid and arguments for this update and relaunch the same
+// executable graph.
+dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report, int n_items, int n_chunks2) {
   const int n_iter = c->cfg.n_iter;
+  const bool split = c->sched.variant == kPassSplit;
   PassArgs base = base_args(c, s);
   base.mode = 0;
+  if (split) base.fuse = 0;
   std::vector<PassArgs> args(n_iter, base);
   for (int p = 0; p < n_iter; ++p) {
     args[p].pass = p;
     args[p].last_pass = (p == n_iter - 1) ? 1 : 0;
   }
   FetchArgs fa = fetch_args(c->hstage_dev[s], c->dstep[s], bytes, report);
+  const size_t per_pass = split ? 5 : (base.fuse ? 1 : 2);
+  const size_t expect = 1 + (size_t)n_iter * per_pass;
   if (!c->gexec[s]) {
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int e = launch_fetch(c->hstage_dev[s], c->dstep[s], bytes, report, c->stream);
     for (int p = 0; p < n_iter && !e; ++p) {
-      e = launch_pass(args[p], c->sched.variant, nch, c->stream);
-      if (!e && !base.fuse) e = launch_finish(args[p], 0, c->stream);
+      if (split) {
+        const PassArgs *ad = args_dev(c, c->dstep[s], p);
+        e = launch_split_rows(args[p], ad, nullptr, std::min(n_items, c->rows_blocks), c->stream);
+        if (!e) e = launch_split_rows_slow(args[p], ad, nullptr, kSlowBlocks, c->stream);
+        if (!e) e = launch_split_solve(args[p], ad, nullptr, n_chunks2, c->stream);
+        if (!e) e = launch_split_fsum(args[p], ad, nullptr, nch, c->stream);
+        if (!e) e = launch_finish_dev(args[p], ad, nullptr, 1, 0, c->stream);
+      } else {
+        e = launch_pass(args[p], c->sched.variant, nch, c->stream);
+        if (!e && !base.fuse) e = launch_finish(args[p], 0, c->stream);
+      }
     }
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(c->stream, &g);
@@ -473,7 +628,6 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
       HIP_OR_FAIL(c, hipGraphNodeGetDependentNodes(cur, &nx, &nd));
       cur = nx;
     }
-    const size_t expect = 1 + (size_t)n_iter * (base.fuse ? 1 : 2);
     if (chain.size() != expect || count != expect) {
       (void)hipGraphDestroy(g);
       c->graph[s] = nullptr;
@@ -485,30 +639,35 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
       HIP_OR_FAIL(c, hipGraphKernelNodeGetParams(chain[i], &c->gparams[s][i]));
     HIP_OR_FAIL(c, hipGraphInstantiate(&c->gexec[s], g, nullptr, nullptr, 0));
   } else {
-    // rewrite the nodes: fetch, then per pass the sweep (and the final phase)
+    if (c->gnodes[s].size() != expect) return fail(c, DASH_E_DEVICE, "graph does not match the schedule");
+    auto set = [&](size_t i, unsigned grid, void **params) -> hipError_t {
+      hipKernelNodeParams kp = c->gparams[s][i];
+      kp.gridDim = dim3(grid);
+      kp.kernelParams = params;
+      return hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kp);
+    };
     size_t i = 0;
-    {
-      hipKernelNodeParams kp = c->gparams[s][i];
-      void *fargs[] = {&fa.src, &fa.dst, &fa.n16, &fa.src_tail, &fa.dst_tail, &fa.tail, &fa.report};
-      kp.gridDim = dim3(fa.grid);
-      kp.kernelParams = fargs;
-      HIP_OR_FAIL(c, hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kp));
-      ++i;
-    }
+    void *fargs[] = {&fa.src, &fa.dst, &fa.n16, &fa.src_tail, &fa.dst_tail, &fa.tail, &fa.report};
+    HIP_OR_FAIL(c, set(i++, fa.grid, fargs));
+    int mode0 = 0;
+    const BlockMap *nomap = nullptr;
     for (int p = 0; p < n_iter; ++p) {
-      hipKernelNodeParams kp = c->gparams[s][i];
       void *pargs[] = {&args[p]};
-      kp.gridDim = dim3(nch);
-      kp.kernelParams = pargs;
-      HIP_OR_FAIL(c, hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kp));
-      ++i;
-      if (!base.fuse) {
-        hipKernelNodeParams kf = c->gparams[s][i];
-        int mode0 = 0;
-        void *fin[] = {&args[p], &mode0};
-        kf.kernelParams = fin;
-        HIP_OR_FAIL(c, hipGraphExecKernelNodeSetParams(c->gexec[s], c->gnodes[s][i], &kf));
-        ++i;
+      void *fin[] = {&args[p], &mode0};
+      if (split) {
+        // the split kernels read their arguments from the stage's fixed
+        // descriptor slot: only the grids change
+        const PassArgs *ad = args_dev(c, c->dstep[s], p);
+        void *dargs[] = {&ad, &nomap};
+        void *dfin[] = {&ad, &nomap, &mode0};
+        HIP_OR_FAIL(c, set(i++, (unsigned)std::min(n_items, c->rows_blocks), dargs));
+        HIP_OR_FAIL(c, set(i++, (unsigned)kSlowBlocks, dargs));
+        HIP_OR_FAIL(c, set(i++, (unsigned)n_chunks2, dargs));
+        HIP_OR_FAIL(c, set(i++, (unsigned)nch, dargs));
+        HIP_OR_FAIL(c, set(i++, 1u, dfin));
+      } else {
+        HIP_OR_FAIL(c, set(i++, (unsigned)nch, pargs));
+        if (!base.fuse) HIP_OR_FAIL(c, set(i++, 1u, fin));
       }
     }
   }
@@ -600,7 +759,7 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
       cfg->max_groups_per_update < 1 || cfg->max_init_rows < 0)
     return DASH_E_INVALID_ARG;
   if ((cfg->precision != DASH_PREC_FP32 && cfg->precision != DASH_PREC_MIXED) ||
-      cfg->stats_mode != DASH_STATS_EXACT)
+      (cfg->stats_mode != DASH_STATS_EXACT && cfg->stats_mode != DASH_STATS_LAGGED))
     return DASH_E_INVALID_ARG;
   dash_ctx *c = new (std::nothrow) dash_ctx();
   if (!c) return DASH_E_OUT_OF_MEMORY;
@@ -611,20 +770,15 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->M_cap = cfg->max_rows_per_update;
   c->G_cap = cfg->max_groups_per_update + c->K_cap;  // new slices are groups too
   c->N_init_cap = cfg->max_init_rows;
-  c->variant = pass_variant(cfg->J, cfg->R, cfg->precision);
+  c->variant = pass_variant(cfg->J, cfg->R, cfg->precision, cfg->stats_mode == DASH_STATS_LAGGED);
+  if (const char *e = std::getenv("DASH_VARIANT"))
+    if (std::atoi(e) == kPassSplit) c->variant = kPassSplit;
   c->fused_lds = (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
   if (const char *e = std::getenv("DASH_FUSE"))
     if (std::atoi(e) == 0) c->fused_lds = 0;
   c->sched = Schedule{c->variant, 1, c->fused_lds > 0 ? 1 : 0};
   if (const char *e = std::getenv("DASH_DESC_FETCH")) c->desc_fetch = std::atoi(e) != 0;
   if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
-  {
-    // the block sweep keeps two workgroups per CU unless its registers (mixed
-    // path, or more than 24 ranks: over 256 per lane) or its LDS allow one
-    const size_t lds = fused_pass_lds(kPassBlock, cfg->J, cfg->R) + 1024;
-    const bool regs_one = cfg->precision == DASH_PREC_MIXED || cfg->R > 24;
-    c->block_per_cu = (regs_one || 2 * lds > 160 * 1024) ? 1 : 2;
-  }
   auto bail = [&](dash_status s) {
     dash_destroy(c);
     return s;
@@ -632,6 +786,9 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   if (hipSetDevice(cfg->device) != hipSuccess) return bail(DASH_E_DEVICE);
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess)
     return bail(DASH_E_DEVICE);
+  // persistent row-stage workgroups: as many as can be resident
+  c->rows_blocks = std::max(1, c->n_cu) *
+                   std::max(1, split_rows_blocks_per_cu(cfg->J, cfg->R, cfg->precision == DASH_PREC_MIXED));
   if (cfg->stream) {
     c->stream = (hipStream_t)cfg->stream;
   } else {
@@ -655,14 +812,24 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
             dalloc(&c->partials, sizeof(double) * n_chunks_cap * plen) == hipSuccess &&
             dalloc(&c->gpart, sizeof(double) * ((n_chunks_cap + kChunksPerRGroup - 1) / kChunksPerRGroup) * plen) == hipSuccess &&
             dalloc(&c->counters, sizeof(int32_t) * (kMaxChunks + 1)) == hipSuccess &&
-            dalloc(&c->d_rowptr, sizeof(int64_t) * (Kc + 1)) == hipSuccess;
+            dalloc(&c->d_rowptr, sizeof(int64_t) * (Kc + 1)) == hipSuccess &&
+            dalloc(&c->cbuf, sizeof(double) * Kc * R) == hipSuccess &&
+            dalloc(&c->part2, sizeof(double) * std::min<int64_t>(Kc, kMaxChunks2) * (R * R + 1)) == hipSuccess &&
+            dalloc(&c->tag, sizeof(int32_t) * Kc) == hipSuccess &&
+            dalloc(&c->queue, sizeof(int32_t) * 4) == hipSuccess &&
+            dalloc(&c->slow_list, sizeof(int32_t) * Kc) == hipSuccess;
+  if (ok && cfg->stats_mode == DASH_STATS_LAGGED)
+    ok = dalloc(&c->cst, sizeof(double) * 2 * Kc * R) == hipSuccess &&
+         dalloc(&c->FG, sizeof(double) * 2 * (J * R + R * R)) == hipSuccess;
   if (ok && cfg->precision == DASH_PREC_MIXED)
     ok = dalloc(&c->Yc, sizeof(float) * 2 * Kc * YS) == hipSuccess &&
          dalloc(&c->Dc, sizeof(float) * 2 * Kc * R * R) == hipSuccess;
   if (!ok) return bail(DASH_E_OUT_OF_MEMORY);
-  c->off_gptr = align_up(sizeof(StepHeader), 64);
+  c->off_args = align_up(sizeof(StepHeader), 64);
+  c->off_gptr = align_up(c->off_args + sizeof(PassArgs) * cfg->n_iter, 64);
   c->off_groups = align_up(c->off_gptr + sizeof(int32_t) * (n_chunks_cap + 1), 64);
-  c->step_bytes = align_up(c->off_groups + sizeof(Group) * c->G_cap, 256);
+  c->off_items = c->off_groups;
+  c->step_bytes = align_up(align_up(c->off_groups + sizeof(Group) * c->G_cap, 64) + sizeof(Item) * c->G_cap, 256);
   for (int s = 0; s < kStages; ++s) {
     if (dalloc(&c->dstep[s], c->step_bytes) != hipSuccess) return bail(DASH_E_OUT_OF_MEMORY);
     if (hipHostMalloc((void **)&c->hstage[s], c->step_bytes, hipHostMallocMapped) != hipSuccess)
@@ -683,6 +850,10 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
       (c->Dc && hipMemsetAsync(c->Dc, 0, sizeof(float) * 2 * Kc * R * R, c->stream) != hipSuccess) ||
       hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * 2 * Kc, c->stream) != hipSuccess ||
       hipMemsetAsync(c->counters, 0, sizeof(int32_t) * (kMaxChunks + 1), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->tag, 0, sizeof(int32_t) * Kc, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->queue, 0, sizeof(int32_t) * 4, c->stream) != hipSuccess ||
+      (c->cst && hipMemsetAsync(c->cst, 0, sizeof(double) * 2 * Kc * R, c->stream) != hipSuccess) ||
+      (c->FG && hipMemsetAsync(c->FG, 0, sizeof(double) * 2 * (J * R + R * R), c->stream) != hipSuccess) ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(DASH_E_DEVICE);
   {
@@ -713,6 +884,19 @@ dash_status dash_destroy(dash_ctx *c) {
   (void)hipFree(c->gpart);
   (void)hipFree(c->counters);
   (void)hipFree(c->d_rowptr);
+  (void)hipFree(c->cbuf);
+  (void)hipFree(c->part2);
+  (void)hipFree(c->tag);
+  (void)hipFree(c->queue);
+  (void)hipFree(c->slow_list);
+  (void)hipFree(c->cst);
+  (void)hipFree(c->FG);
+  (void)hipFree(c->anom.se);
+  (void)hipFree(c->anom.flag);
+  (void)hipFree(c->anom.sid);
+  (void)hipFree(c->anom.hist);
+  (void)hipFree(c->anom.hcnt);
+  (void)hipFree(c->anom.ticket);
   for (int s = 0; s < kStages; ++s) {
     (void)hipFree(c->dstep[s]);
     if (c->hstage[s]) (void)hipHostFree(c->hstage[s]);
@@ -969,6 +1153,21 @@ dash_status dash_update_async(dash_ctx *c) {
     while (gi < ng && grp[gi].slice < first) ++gi;
     gptr[cidx] = gi;
   }
+  // the touched slices (split sweep's row stage), most rows first
+  const bool split = c->sched.variant == kPassSplit;
+  int n_items = 0, c3 = ch, c2 = ch;
+  c->off_items = align_up(c->off_groups + sizeof(Group) * ng, 64);
+  if (split) split_chunks(c, K, &c3, &c2);
+  {
+    Item *items = (Item *)(blk + c->off_items);
+    for (int g = 0; g < ng;) {
+      int e = g, rows = 0;
+      while (e < ng && grp[e].slice == grp[g].slice) rows += grp[e++].nrows;
+      items[n_items++] = Item{grp[g].slice, g, e, rows};
+      g = e;
+    }
+    std::stable_sort(items, items + n_items, [](const Item &x, const Item &y) { return x.rows > y.rows; });
+  }
   const int64_t step = c->step_enq + 1;
   c->profiling = c->prof_every > 0 && step % c->prof_every == 0;
   const int slot = (int)(step % kReportRing);
@@ -983,12 +1182,19 @@ dash_status dash_update_async(dash_ctx *c) {
   h->step = step;
   h->M = c->rows_pending;
   h->report = (void *)(c->dreport + slot);
+  h->n_items = n_items;
+  h->chunk2 = c2;
+  h->n_chunks2 = (K + c2 - 1) / c2;
+  h->seq = ++c->seq;
   c->hreport[slot].done = 0;
   c->hreport[slot].t_start = c->hreport[slot].t_end = 0;
-  const size_t bytes = c->off_groups + sizeof(Group) * ng;
+  const size_t bytes = c->off_items + sizeof(Item) * n_items;
+  const char *dblk = c->desc_fetch ? c->dstep[s] : c->hstage_dev[s];
+  if (split) write_pass_args(c, blk, dblk, 0);
 
   const bool tuning = !c->tune_cands.empty() && !c->tuned;
-  if (c->graph_on && !c->profiling && c->desc_fetch && !tuning) {
+  const bool scored = c->anom_window > 0;
+  if (c->graph_on && !c->profiling && c->desc_fetch && !tuning && !scored) {
     if (c->gsched.variant != c->sched.variant || c->gsched.spread != c->sched.spread ||
         c->gsched.fuse != c->sched.fuse) {
       // captured for another schedule: drop the graphs once nothing runs them
@@ -996,7 +1202,7 @@ dash_status dash_update_async(dash_ctx *c) {
       graph_reset(c);
       c->gsched = c->sched;
     }
-    if (dash_status st = graph_update(c, s, bytes, nch, h->report)) return st;
+    if (dash_status st = graph_update(c, s, bytes, nch, h->report, n_items, h->n_chunks2)) return st;
   } else {
     HIP_OR_FAIL(c, upload_stage(c, s, bytes, true, h->report));
     PassArgs a = base_args(c, s);
@@ -1004,6 +1210,11 @@ dash_status dash_update_async(dash_ctx *c) {
     for (int p = 0; p < c->cfg.n_iter; ++p) {
       a.pass = p;
       a.last_pass = (p == c->cfg.n_iter - 1) ? 1 : 0;
+      if (split) {
+        a.fuse = 0;
+        if (dash_status st = enqueue_split_pass(c, a, args_dev(c, dblk, p), n_items, h->n_chunks2, nch)) return st;
+        continue;
+      }
       HIP_OR_FAIL(c, prof_begin(c, kProfPass));
       LAUNCH_OR_FAIL(c, launch_pass(a, c->sched.variant, nch, c->stream));
       HIP_OR_FAIL(c, prof_end(c));
@@ -1013,15 +1224,24 @@ dash_status dash_update_async(dash_ctx *c) {
         HIP_OR_FAIL(c, prof_end(c));
       }
     }
+    if (scored) {
+      // Definitions 1-2 with the committed factors; this kernel publishes the report
+      a.last_pass = 1;
+      LAUNCH_OR_FAIL(c, launch_slice_errors(a, c->anom, std::min(std::max(n_items, 1), 2 * std::max(1, c->n_cu)),
+                                            c->stream));
+    }
   }
   HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
   c->profiling = false;
   {
-    const double J = c->J, R = c->R, M = (double)c->rows_pending, Kt = (double)ng;
+    int touched = 0;
+    for (int g = 0; g < ng; ++g)
+      if (g == 0 || grp[g].slice != grp[g - 1].slice) ++touched;
+    const double J = c->J, R = c->R, M = (double)c->rows_pending, Kt = (double)touched;
     const double bytes = c->cfg.n_iter * (M * J * 4 + M * R * 4 + K * (R * J * 4 + R * R * 4 + 8 + R * 8) +
                                           Kt * (R * J * 4 + R * R * 4 + 8) + K * R * 8);
-    c->inflight.push_back({step, Kp, K, c->rows_pending, slot, cand, bytes});
+    c->inflight.push_back({step, Kp, K, c->rows_pending, slot, cand, bytes, n_items, scored});
   }
   c->K_enq = K;
   c->step_enq = step;
@@ -1046,6 +1266,8 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
       c->K = f.K_after;
       c->step = f.step;
       c->m_last = f.rows;
+      dash_update_report tmp{};
+      score_report(c, f, r, &tmp);
       if (rep) {
         rep->step = r.step;
         rep->rows = r.rows;
@@ -1055,6 +1277,10 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
         rep->loss = r.loss;
         rep->sum_n = r.sum_n;
         rep->device_us = device_us(r);
+        rep->te = tmp.te;
+        rep->te_threshold = tmp.te_threshold;
+        rep->te_anomaly = tmp.te_anomaly;
+        rep->n_anomalies = tmp.n_anomalies;
       }
     } else if (!failed) {
       failed = true;
@@ -1068,6 +1294,8 @@ dash_status dash_wait(dash_ctx *c, dash_update_report *rep) {
         rep->loss = r.loss;
         rep->sum_n = r.sum_n;
         rep->device_us = device_us(r);
+        rep->te = rep->te_threshold = 0.0;
+        rep->te_anomaly = rep->n_anomalies = 0;
       }
     }
   }
@@ -1118,7 +1346,66 @@ dash_status dash_poll(dash_ctx *c, dash_update_report *reps, int32_t cap, int32_
     o.loss = r.loss;
     o.sum_n = r.sum_n;
     o.device_us = device_us(r);
+    score_report(c, f, r, &o);
   }
+  return DASH_OK;
+}
+
+dash_status dash_anomaly(dash_ctx *c, int32_t window) {
+  if (!c || window < 0) return DASH_E_INVALID_ARG;
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  AnomalyArgs &x = c->anom;
+  (void)hipFree(x.se);
+  (void)hipFree(x.flag);
+  (void)hipFree(x.sid);
+  (void)hipFree(x.hist);
+  (void)hipFree(x.hcnt);
+  (void)hipFree(x.ticket);
+  x = AnomalyArgs{};
+  c->anom_window = 0;
+  c->te_hist.clear();
+  c->anom_n_last = -1;
+  if (window == 0) return DASH_OK;
+  const bool ok = dalloc(&x.se, sizeof(float) * c->G_cap) == hipSuccess &&
+                  dalloc(&x.flag, sizeof(int32_t) * c->G_cap) == hipSuccess &&
+                  dalloc(&x.sid, sizeof(int32_t) * c->G_cap) == hipSuccess &&
+                  dalloc(&x.hist, sizeof(float) * c->K_cap * window) == hipSuccess &&
+                  dalloc(&x.hcnt, sizeof(int32_t) * c->K_cap) == hipSuccess &&
+                  dalloc(&x.ticket, sizeof(int32_t)) == hipSuccess;
+  if (!ok) {
+    (void)dash_anomaly(c, 0);
+    return fail(c, DASH_E_OUT_OF_MEMORY, "anomaly-score buffers");
+  }
+  HIP_OR_FAIL(c, hipMemsetAsync(x.hcnt, 0, sizeof(int32_t) * c->K_cap, c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(x.ticket, 0, sizeof(int32_t), c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  x.window = window;
+  c->anom_window = window;
+  return DASH_OK;
+}
+
+dash_status dash_get_slice_errors(dash_ctx *c, int32_t *slice, float *se, int32_t *flag, int32_t cap, int32_t *n) {
+  if (!c || !n || cap < 0 || (cap > 0 && (!slice || !se || !flag))) return DASH_E_INVALID_ARG;
+  if (c->anom_window == 0) return fail(c, DASH_E_BAD_STATE, "anomaly scores are off");
+  if (dash_status s = dash_wait(c, nullptr)) return s;
+  *n = 0;
+  const int m = c->anom_n_last;
+  if (m <= 0) return DASH_OK;
+  std::vector<float> s_se(m);
+  std::vector<int32_t> s_fl(m), s_id(m);
+  HIP_OR_FAIL(c, hipMemcpy(s_se.data(), c->anom.se, sizeof(float) * m, hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(c, hipMemcpy(s_fl.data(), c->anom.flag, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(c, hipMemcpy(s_id.data(), c->anom.sid, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return s_id[x] < s_id[y]; });
+  const int out = std::min(m, cap);
+  for (int i = 0; i < out; ++i) {
+    slice[i] = s_id[ord[i]];
+    se[i] = s_se[ord[i]];
+    flag[i] = s_fl[ord[i]];
+  }
+  *n = out;
   return DASH_OK;
 }
 
@@ -1134,7 +1421,7 @@ dash_status dash_autotune(dash_ctx *c, int32_t trials) {
   c->sched = Schedule{c->variant, 1, fl > 0 ? 1 : 0};
   if (trials == 0) return DASH_OK;
   std::vector<int> variants{c->variant};
-  if (c->variant == kPassWave) variants.push_back(kPassBlock);
+  if (c->variant == kPassWave) variants.push_back(kPassSplit);
   for (int v : variants)
     for (int spread : {1, 2})
       for (int fuse : {1, 0}) {

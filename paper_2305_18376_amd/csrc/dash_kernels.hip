@@ -1,10 +1,12 @@
-// gfx950 kernels of the streaming PARAFAC2 update (DASH).
+// gfx950 kernels of the streaming PARAFAC2 update (DASH): the final phase of a
+// pass and the fused one-wave-per-slice sweep.
 //
-// One update = one launch per ALS pass.  Every workgroup sweeps a chunk of
+// Fused sweep: one launch per ALS pass.  Every workgroup sweeps a chunk of
 // slices (Lemma 1 on their new rows, the forgetting-factor fold, Lemma 2) and
 // writes an F/G/n partial; the last workgroup to arrive reduces the partials in
 // a fixed order, solves Lemma 3 and prepares the next pass's V operands, and
-// on the last pass commits the update.  See dash_dev.h for layouts.
+// on the last pass commits the update.  The split sweep (dash_split.hip) runs
+// the same pass as four launches.  See dash_dev.h for layouts.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -12,6 +14,7 @@
 
 #include "dash_dev.h"
 #include "dash_math.h"
+#include "dash_tiles.h"
 
 namespace dash {
 
@@ -78,6 +81,20 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   }
   __syncthreads();
   if (mode != 1) sum_n = sRed[kFinishRed - 1];
+  if (mode == 0 && a.lagged) {
+    // Algorithm 1's recursions (eq. [obtain_FandF], [obtain_FandG]): the old
+    // terms are the committed F, G scaled by lambda; the partials hold the
+    // new rows' terms
+    const double *fg = a.FG + (int64_t)gcur * (RJ + RR);
+    for (int e = tid; e < RJ + RR; e += nt) sF[e] = fma(a.lambda, fg[e], sF[e]);
+    __syncthreads();
+  }
+  if (a.lagged && mode != 1) {
+    // the lagged F, G of this pass (committed with it), or, evaluating the
+    // initial state, the exact ones the recursions start from
+    double *fg = a.FG + (int64_t)(mode == 0 ? 1 - gcur : gcur) * (RJ + RR);
+    for (int e = tid; e < RJ + RR; e += nt) fg[e] = sF[e];
+  }
   double vf = 0.0;
   if (mode == 0) {
     // Lemma 3: V = F G^{-1}
@@ -133,9 +150,13 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
       vo.VtV[q] = acc;
     }
     __syncthreads();
-    if (!block_spd_inverse<RM>(sVtV, sB, R) && lane == 0) sFlag[2] = 0;
+    if (!block_spd_inverse<RM>(sVtV, sB, R, vo.piv) && lane == 0) sFlag[2] = 0;
     __syncthreads();
-    if (!sFlag[2]) block_pinv_of(sVtV, sB, sGi, sZ, R, sRot, sPair);
+    if (!sFlag[2]) {
+      // no pivots: every slice's Lemma 1 system takes the pseudo-inverse form
+      if (tid < R) vo.piv[tid] = 0.0;
+      block_pinv_of(sVtV, sB, sGi, sZ, R, sRot, sPair);
+    }
     for (int e = tid; e < J * R; e += nt) {
       const int j = e / R, c = e - j * R;
       double acc = 0.0;
@@ -195,50 +216,12 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
       a.ctl->poison = 1;
     a.ctl->ok = 1;  // reset for the next update
     // the host polls `done`: every other field must be visible before it
-    __threadfence_system();
-    rep->done = 1;
+    // (with anomaly scores on, their kernel sets it after this launch)
+    if (!a.defer_done) {
+      __threadfence_system();
+      rep->done = 1;
+    }
   }
-}
-
-// Arrival of a workgroup whose chunk partial is written: the last of each group
-// of kChunksPerRGroup chunks to arrive sums the group's partials in chunk order
-// into gpart (a first reduction level inside the sweep launch; the final phase
-// does the second).  With a.fuse, the last group reducer to finish takes a
-// second ticket and returns true: it then runs the final phase.  Every ticket is
-// reset by the workgroup that drew the last number, so all are zero again when
-// the launch ends.
-__device__ bool arrive(const PassArgs &a, const StepHeader *h, int chunk, int *sflag) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int plen = partial_len(a.J, a.R);
-  const int cpr = h->chunks_per_rgroup;
-  const int rg = chunk / cpr;
-  const int c0 = rg * cpr, c1 = min(h->n_chunks, c0 + cpr);
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const int old = atomicAdd(&a.counters[rg], 1);
-    *sflag = (old == c1 - c0 - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!*sflag) return false;
-  __threadfence();
-  for (int e = tid; e < plen; e += nt) a.gpart[(int64_t)rg * plen + e] = ordered_sum(a.partials, plen, e, c0, c1);
-  if (!a.fuse) {
-    if (tid == 0) a.counters[rg] = 0;
-    return false;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    a.counters[rg] = 0;
-    __threadfence();
-    const int old = atomicAdd(&a.counters[kMaxChunks], 1);
-    *sflag = (old == h->n_rgroups - 1) ? 1 : 0;
-    if (*sflag) a.counters[kMaxChunks] = 0;
-  }
-  __syncthreads();
-  if (!*sflag) return false;
-  __threadfence();
-  return true;
 }
 
 // R bucket of the final phase's register eliminations
@@ -260,6 +243,15 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(PassArgs a, int mode)
   finish_pass<RM>(a, h, mode == 1 ? 0 : h->n_rgroups, mode, smem, finish_launch_lds(a.J, a.R));
 }
 
+// The same with its arguments in device memory (one workgroup per context).
+template <int RM>
+__global__ __launch_bounds__(kFinishThreads) void k_finish_dev(const PassArgs *args, const BlockMap *map, int mode) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  const StepHeader *h = a.hdr;
+  finish_pass<RM>(a, h, mode == 1 ? 0 : h->n_rgroups, mode, smem, finish_launch_lds(a.J, a.R));
+}
+
 // ---------------------------------------------------------------------------
 // Sweep variant 1: one wave per slice ("wave" variant, R*J <= 2048, J <= 128).
 // 8 waves per workgroup; wave w handles slices k0+w, k0+w+8, ... of the chunk.
@@ -277,21 +269,6 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(PassArgs a, int mode)
 // Untouched slices solve on their stored (undecayed) Y_k, D_k -- w_k does not
 // depend on the common factor lambda^dt -- and enter F, G with sigma = lambda^dt.
 // ---------------------------------------------------------------------------
-// MFMA tiles.  v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; v_mfma_f32_16x16x32_bf16: A[l % 16][8 (l / 16) + i] and
-// B[8 (l / 16) + i][l % 16] (i < 8), BF16-rounded operands; both return
-// C[4 (l / 16) + i][l % 16] (i < 4) with FP32 accumulation.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f32x4 mfma_bf16(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
 constexpr int kWaveRows = 16;   // rows per staged block
 constexpr int kWaveWarps = 8;   // waves per workgroup
 
@@ -323,7 +300,8 @@ __host__ __device__ inline WaveLds wave_lds(int J, int R) {
   // per-wave region: small vectors, then a union of the row block, the
   // products of diag(Y_k V), and the solve scratch
   size_t w = 0;
-  L.oSmall = w; w += (size_t)(R + 1) * 8 * 3 + (size_t)RC * 4;   // sW, sC, sC2 (f64, R+1), sWinv (f32, RC)
+  // sW, sC, sC2 (f64, R+1), sWinv (f32, RC), sZf (f32, RC x RC: Lemma 1's pseudo-inverse form)
+  L.oSmall = w; w += (size_t)(R + 1) * 8 * 3 + (size_t)RC * 4 + (size_t)RC * RC * 4;
   w = align_up(w, 16);
   const size_t blk = w;
   L.oX = blk;
@@ -374,6 +352,7 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
   double *sC = sW + (R + 1);
   double *sC2 = sC + (R + 1);
   float *sWinv = (float *)(sC2 + (R + 1));
+  float *sZf = sWinv + RC;
   float *sX = (float *)(wbase + L.oX);
   float *sU = (float *)(wbase + L.oU);
   float *sProd = (float *)(wbase + L.oProd);
@@ -405,6 +384,9 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
   const int k0 = chunk * h->chunk;
   const int k1 = min(K, k0 + h->chunk);
   const int g0 = a.chunk_gptr[chunk], g1 = a.chunk_gptr[chunk + 1];
+  // pivots and diagonal of V^T V for Lemma 1's acceptance rule (lane r)
+  const double pivl = lane < R ? vb.piv[lane] : 0.0;
+  const double arrl = lane < R ? vb.VtV[lane * R + lane] : 0.0;
 
   for (int k = k0 + wv; k < k1; k += kWaveWarps) {
     const bool is_new = k >= Kp;
@@ -442,13 +424,17 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
       }
     }
     const bool touched = gb >= 0;
+    // Lemma 1's system S_k V^T V S_k: the division by w when it passes the
+    // acceptance rule, else its pseudo-inverse form u = t Z
+    const bool regular = lemma1_regular(w, pivl, arrl, R);
     {
       if (lane < R) sW[lane] = w;
-      const double top = wave_max(fabs(w));
-      if (lane < RC) sWinv[lane] = (lane < R && fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
+      if (lane < RC) sWinv[lane] = (lane < R && regular) ? (float)(1.0 / w) : 0.f;
       if (lane == 0) sC[R] = 0.0;   // weight of the padding elements of Y_k
     }
     wave_sync();
+    const bool slow = !regular && touched && a.mode == 0;
+    if (slow) lemma1_pinv_matrix(sVtV, sW, R, sM, sZ, sTmp, sRot, sPair, sZf, RC);
 
     float dD[DQ];
     double dn = 0.0;
@@ -518,7 +504,32 @@ __global__ __launch_bounds__(512) void k_pass_wave(PassArgs a) {
               t0 = mfma_f32(kk < J ? xr[kk] : 0.f, kk < J ? sP[kk * RC + n] : 0.f, t0);
             }
             const f32x4 t = t0 + t1;
-            if (li < RC) {
+            if (slow) {
+              // u = t Z: the tile goes through LDS so every lane sees whole rows
+              if (li < RC) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sU[(4 * lq + i) * RC + li] = (li < R) ? t[i] : 0.f;
+              }
+              wave_sync();
+              float uq[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int row = 4 * lq + i;
+                float acc = 0.f;
+                if (li < R)
+                  for (int mm = 0; mm < R; ++mm) acc = fmaf(sU[row * RC + mm], sZf[mm * RC + li], acc);
+                uq[i] = (row < m && li < R) ? acc : 0.f;
+              }
+              wave_sync();
+              if (li < RC) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const int row = 4 * lq + i;
+                  sU[row * RC + li] = uq[i];
+                  if (a.last_pass && row < m && li < R) a.U_out[(out_row + r0 + row) * R + li] = uq[i];
+                }
+              }
+            } else if (li < RC) {
               const float wi = sWinv[li];
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
@@ -745,198 +756,6 @@ __host__ __device__ inline PassLds pass_lds(int J, int R, bool with_finish = tru
   return L;
 }
 
-// ---------------------------------------------------------------------------
-// Mixed precision (BF16 MFMA) row products of the block variant.
-// v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][8 (l / 16) + i] and
-// B[8 (l / 16) + i][l % 16] (i < 8) and receives C[4 (l / 16) + i][l % 16]
-// (i < 4); products of BF16-rounded operands, FP32 accumulation.
-// ---------------------------------------------------------------------------
-// the mixed-precision tiles of one slice: wave w owns the dY column tiles
-// w, w+4, w+8, w+12 (16 columns each) for both rank tiles (accY[2 c + mt]), and
-// the dD tile w of the (R / 16)^2 rank-tile pairs
-constexpr int kMxTiles = 8;
-
-// One 16 x 16 tile of X P: rows xrow (lane's row of the 16-row tile, stride
-// XS in LDS, zero rows beyond the block), columns 16 nt .. 16 nt + 15 of P
-// (J x R, LDS); columns >= R come out as garbage and are dropped by the
-// caller.  v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; BF16 (16x16x32): A[l % 16][8 (l / 16) + i], i < 8.
-template <bool MX>
-__device__ __forceinline__ f32x4 rows_times_p(const float *xrow, const float *sP, int J, int R, int nt,
-                                               int lane) {
-  const int n = min(nt * 16 + (lane & 15), R - 1);
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  if constexpr (MX) {
-    const int lk = (lane >> 4) * 8;
-    for (int ks = 0; ks < J; ks += 32) {
-      bf16x8 av, bv;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int kk = ks + lk + q;
-        av[q] = (__bf16)((kk < J) ? xrow[kk] : 0.f);
-        bv[q] = (__bf16)((kk < J) ? sP[kk * R + n] : 0.f);
-      }
-      acc0 = mfma_bf16(av, bv, acc0);
-    }
-  } else {
-    const int lq = lane >> 4;
-    int ks = 0;
-    // two independent chains; the tail (J % 8) goes to the first
-    for (; ks + 8 <= J; ks += 8) {
-      const float a0 = xrow[ks + lq], a1 = xrow[ks + 4 + lq];
-      const float b0 = sP[(ks + lq) * R + n], b1 = sP[(ks + 4 + lq) * R + n];
-      acc0 = mfma_f32(a0, b0, acc0);
-      acc1 = mfma_f32(a1, b1, acc1);
-    }
-    for (; ks < J; ks += 4) {
-      const int kk = ks + lq;
-      const float a0 = (kk < J) ? xrow[kk] : 0.f;
-      const float b0 = (kk < J) ? sP[kk * R + n] : 0.f;
-      acc0 = mfma_f32(a0, b0, acc0);
-    }
-  }
-  return acc0 + acc1;
-}
-
-// dY += U^T X, dD += U^T U in FP32 on MFMA (16x16x4) for one staged block
-// (rows >= m are zero in sX and sU; mp = m rounded up to 16).  Same tile
-// ownership as the BF16 version below.
-__device__ __forceinline__ void accum_block_f32(const float *sX, const float *sU, int XS, int mp, int J,
-                                                int R, f32x4 (&accY)[kMxTiles], f32x4 &accD, int tid) {
-  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
-  const int li = lane & 15, lq = lane >> 4;
-  const int r0c = min(li, R - 1), r1c = min(16 + li, R - 1);
-  for (int ks = 0; ks < mp; ks += 4) {
-    const float *urow = sU + (ks + lq) * (R + 1);
-    const float au0 = urow[r0c], au1 = urow[r1c];
-    const float *xrow = sX + (ks + lq) * XS;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int nt = wv + 4 * c;
-      if (nt < NT) {
-        const float bx = xrow[min(nt * 16 + li, J - 1)];
-        accY[2 * c] = mfma_f32(au0, bx, accY[2 * c]);
-        if (MT > 1) accY[2 * c + 1] = mfma_f32(au1, bx, accY[2 * c + 1]);
-      }
-    }
-    if (wv < MT * MT) {
-      const int mt = wv / MT, st = wv - mt * MT;
-      accD = mfma_f32(mt == 0 ? au0 : au1, st == 0 ? au0 : au1, accD);
-    }
-  }
-}
-
-// dY += U^T X, dD += U^T U on MFMA for one staged block (rows >= m are zero
-// in both sX and sU; mp = m rounded up to 32).  The U^T operand of a rank
-// tile is loaded once per 32-row step and serves every column tile, and, as
-// the B operand of dD, the rank-tile pairs too.
-__device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU, int XS, int mp, int J,
-                                               int R, f32x4 (&accY)[kMxTiles], f32x4 &accD, int tid) {
-  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
-  const int li = lane & 15, lk = (lane >> 4) * 8;
-  for (int ks = 0; ks < mp; ks += 32) {
-    bf16x8 au[2];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      const int r = mt * 16 + li;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) au[mt][q] = (__bf16)((r < R) ? sU[(ks + lk + q) * (R + 1) + r] : 0.f);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int nt = wv + 4 * c;
-      if (nt < NT) {
-        const int j = min(nt * 16 + li, J - 1);
-        bf16x8 bv;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) bv[q] = (__bf16)sX[(ks + lk + q) * XS + j];
-        accY[2 * c] = mfma_bf16(au[0], bv, accY[2 * c]);
-        if (MT > 1) accY[2 * c + 1] = mfma_bf16(au[1], bv, accY[2 * c + 1]);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (wv < MT * MT) {
-      const int mt = wv / MT, st = wv - mt * MT;
-      accD = mfma_bf16(mt == 0 ? au[0] : au[1], st == 0 ? au[0] : au[1], accD);
-    }
-  }
-}
-
-// Copy m contiguous rows of J floats from HBM into sX (row stride XS) with NTH
-// threads (tid < NTH); m * J <= 8192.  A thread's loads go out in batches of
-// four float4 (eight floats) before its LDS stores, so the copy waits for a few
-// memory latencies, not one per element.  Float4 loads when the rows allow
-// them.  With SQ the thread's sum of squares of what it loaded is returned
-// (FP64).
-template <bool SQ, int NTH = 256>
-__device__ __forceinline__ double stage_rows(const float *__restrict__ src, int m, int J, int XS, float *sX,
-                                             int tid) {
-  double sq = 0.0;
-  const int n = m * J;
-  if ((J & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-    const int n4 = n >> 2;
-    constexpr int PER = (2048 + NTH - 1) / NTH;
-#pragma unroll 1
-    for (int i0 = 0; i0 < PER; i0 += 4) {
-      if (tid + NTH * i0 >= n4) break;
-      float4 v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = tid + NTH * (i0 + i);
-        v[i] = (q < n4) ? reinterpret_cast<const float4 *>(src)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = tid + NTH * (i0 + i);
-        if (q < n4) {
-          const int e = 4 * q, row = e / J, col = e - row * J;
-          float *d = sX + row * XS + col;
-          d[0] = v[i].x;
-          d[1] = v[i].y;
-          d[2] = v[i].z;
-          d[3] = v[i].w;
-        }
-        if constexpr (SQ) {
-          sq = fma((double)v[i].x, (double)v[i].x, sq);
-          sq = fma((double)v[i].y, (double)v[i].y, sq);
-          sq = fma((double)v[i].z, (double)v[i].z, sq);
-          sq = fma((double)v[i].w, (double)v[i].w, sq);
-        }
-      }
-    }
-  } else {
-    constexpr int PER = (8192 + NTH - 1) / NTH;
-#pragma unroll 1
-    for (int i0 = 0; i0 < PER; i0 += 8) {
-      if (tid + NTH * i0 >= n) break;
-      float v[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int e = tid + NTH * (i0 + i);
-        v[i] = (e < n) ? src[e] : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int e = tid + NTH * (i0 + i);
-        if (e < n) {
-          const int row = e / J;
-          sX[row * XS + (e - row * J)] = v[i];
-        }
-        if constexpr (SQ) sq = fma((double)v[i], (double)v[i], sq);
-      }
-    }
-  }
-  return sq;
-}
-
-// padded rank of the block variant's register solve (R <= 4 RW)
-template <int RW>
-struct BlockRM {
-  static constexpr int value = RW <= 2 ? 8 : 4 * RW;
-};
-
 // dY += U^T X and dD += U^T U for one staged block of m rows (block variant).
 template <int RW, int JW>
 __device__ __forceinline__ void accum_block(const float *sX, const float *sU, int XS, int m, int J,
@@ -969,406 +788,6 @@ __device__ __forceinline__ void accum_block(const float *sX, const float *sU, in
   }
 }
 
-template <int RW, int JW, bool MX>
-__global__ __launch_bounds__(256) void k_pass_block(PassArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int sflag;
-  __shared__ double sDn[4];   // the waves' sums of ||x||^2 of the current slice
-  const StepHeader *h = a.hdr;
-  const int chunk = blockIdx.x;
-  if (chunk >= h->n_chunks) return;
-  if (a.stamp_start && chunk == 0 && threadIdx.x == 0 && a.pass == 0 && a.mode == 0 && h->report)
-    ((Report *)h->report)->t_start = __builtin_amdgcn_s_memrealtime();
-  const int J = a.J, R = a.R;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int K = h->K, Kp = h->K_prev;
-  const int64_t step = h->step;
-  const int gcur = a.ctl->gcur;
-  const int win = (a.pass == 0) ? gcur : 1 - gcur;
-  const int wout = 1 - gcur;
-  const VBundleView vb = vb_view(a.vb + (int64_t)win * a.vb_stride, J, R);
-  const PassLds L = pass_lds(J, R);
-  float *sP = (float *)(smem + L.oP);
-  float *sVt = (float *)(smem + L.oVt);
-  float *sX = (float *)(smem + L.oX);
-  float *sU = (float *)(smem + L.oU);
-  double *sW = (double *)(smem + L.oW);
-  float *sWinv = (float *)(smem + L.oWinv);
-  double *sC = (double *)(smem + L.oC);
-  double *sC2 = (double *)(smem + L.oC2);
-  double *sM = (double *)(smem + L.oM);
-  float *sDc = (float *)(smem + L.oDc);
-  float *sDlo = (float *)(smem + L.oDlo);
-  double *sVtV = (double *)(smem + L.oVtV);
-  double *sZ = (double *)(smem + L.oZ);
-  double *sTmp = (double *)(smem + L.oTmp);
-  double *sRot = (double *)(smem + L.oRot);
-  int *sPair = (int *)(smem + L.oPair);
-  const int XS = L.XS, MB = L.MB;
-  const int RR = R * R;
-
-  for (int e = tid; e < J * R; e += 256) sP[e] = vb.P32[e];
-  for (int e = tid; e < R * J; e += 256) sVt[e] = vb.Vt32[e];
-  for (int e = tid; e < RR; e += 256) sVtV[e] = vb.VtV[e];
-
-  float facc[RW][JW];   // F^T partial of the chunk (the chunk partials are summed in FP64)
-  double gacc[4] = {0.0, 0.0, 0.0, 0.0};
-  double nacc = 0.0;
-#pragma unroll
-  for (int rr = 0; rr < RW; ++rr)
-#pragma unroll
-    for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = 0.f;
-
-  const int k0 = chunk * h->chunk;
-  const int k1 = min(K, k0 + h->chunk);
-  int g = a.chunk_gptr[chunk];
-  const int gend = a.chunk_gptr[chunk + 1];
-  const int plen = partial_len(J, R);
-
-  // weights W(k,:) the sweep starts from (1 for a new slice in the first pass)
-  auto load_w = [&](int k) -> double {
-    return (k >= Kp && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + threadIdx.x];
-  };
-  double wnext = (tid < R && k0 < k1) ? load_w(k0) : 0.0;
-  bool pre = false;      // the slice's first row block is already in sX
-  double dn_pre = 0.0;   // this thread's ||x||^2 of that block
-
-  for (int k = k0; k < k1; ++k) {
-    // the thread index, opaque to the compiler inside the loop: per-thread
-    // address arithmetic is redone per slice instead of being hoisted out of
-    // the loop into registers
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int gb = g;
-    while (g < gend && a.groups[g].slice == k) ++g;
-    const bool touched = g > gb;
-    const bool is_new = k >= Kp;
-    // the stored Y_k and D_k (and the compensation words of the mixed path)
-    // are loaded ahead of their use: in the float32 path before the row
-    // phase, whose work hides their latency; the mixed path, short of
-    // registers there, issues them between the row products and the hand-off
-    const int b = a.cur[(int64_t)gcur * a.K_cap + k];
-    const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
-    const int64_t ybase = ((int64_t)b * a.K_cap + k) * a.ys;
-    const int64_t dbase = ((int64_t)b * a.K_cap + k) * RR;
-    float yo[RW][JW];
-    float yl[MX ? RW : 1][MX ? JW : 1];
-    float dold[4], dlo[4];
-    auto load_state = [&]() {
-#pragma unroll
-      for (int rr = 0; rr < RW; ++rr) {
-        const int r = wv + 4 * rr;
-#pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
-          const int j = lane + 64 * jj;
-          const bool in = !is_new && r < R && j < J;
-          yo[rr][jj] = in ? a.Y[ybase + r * J + j] : 0.f;
-          if constexpr (MX) yl[rr][jj] = in ? a.Yc[ybase + r * J + j] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = tid + 256 * i;
-        const bool in = !is_new && q < RR;
-        dold[i] = in ? a.D[dbase + q] : 0.f;
-        dlo[i] = (MX && in) ? a.Dc[dbase + q] : 0.f;
-      }
-    };
-    if constexpr (!MX) load_state();
-    __syncthreads();   // the previous slice is done with sW, sWinv, sDn
-    if (wv == 0) {
-      // w and its guarded reciprocal (readers sit behind the next barrier)
-      const double w = (lane < R) ? wnext : 0.0;
-      const double top = wave_max(fabs(w));
-      if (lane < R) {
-        sW[lane] = w;
-        sWinv[lane] = (fabs(w) > kWCutoff * top) ? (float)(1.0 / w) : 0.f;
-      }
-    }
-    // the next slice's weights, in flight during this slice
-    if (tid < R && k + 1 < k1) wnext = load_w(k + 1);
-
-    float dY[RW][JW];
-    float dD[4] = {0.f, 0.f, 0.f, 0.f};
-    double dn = 0.0;
-#pragma unroll
-    for (int rr = 0; rr < RW; ++rr)
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) dY[rr][jj] = 0.f;
-
-    // Lemma 1 and the accumulation of the new rows on MFMA: FP32 (16x16x4)
-    // in the float32 path, BF16 (16x16x32, FP32 sums) in the mixed path.
-    // The tiles of dY = U^T X and dD = U^T U stay in the waves' accumulators
-    // over all blocks of the slice.
-    f32x4 accY[kMxTiles];
-    f32x4 accD = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (touched && a.mode == 0) {
-      const int NTu = (R + 15) >> 4;
-      for (int gi = gb; gi < g; ++gi) {
-        const Group gr = a.groups[gi];
-        for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
-          const int m = min(MB, gr.nrows - r0);
-          // rows of the block the MFMA tiles cover (zero beyond m)
-          const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
-          __syncthreads();
-          if (pre && gi == gb && r0 == 0) {
-            // staged by waves 1-3 during the previous slice's solve
-            dn += dn_pre;
-            dn_pre = 0.0;
-          } else {
-            dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
-            for (int e = tid; e < (mp - m) * J; e += 256) {
-              const int row = e / J;
-              sX[(m + row) * XS + (e - row * J)] = 0.f;
-            }
-          }
-          __syncthreads();
-          // u = (x P) * (1/w): jobs (row tile, rank tile), wave w takes w and w + 4
-          const int jobs = (mp >> 4) * NTu;
-#pragma unroll
-          for (int jb = 0; jb < 2; ++jb) {
-            const int job = wv + 4 * jb;
-            if (job < jobs) {
-              const int rt = job / NTu, nt = job - rt * NTu;
-              const f32x4 acc = rows_times_p<MX>(sX + (16 * rt + (lane & 15)) * XS, sP, J, R, nt, lane);
-              const int n = nt * 16 + (lane & 15);
-              if (n < R) {
-                const float wi = sWinv[n];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  const int rr = 16 * rt + (lane >> 4) * 4 + q;
-                  const float u = (rr < m) ? acc[q] * wi : 0.f;
-                  sU[rr * (R + 1) + n] = u;
-                  if (a.last_pass && rr < m) a.U_out[(gr.out_row + r0 + rr) * R + n] = u;
-                }
-              }
-            }
-          }
-          __syncthreads();
-          if constexpr (MX)
-            accum_block_mx(sX, sU, XS, mp, J, R, accY, accD, tid);
-          else
-            accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
-        }
-      }
-    }
-    if constexpr (MX) load_state();
-    if (touched && a.mode == 0) {
-      // hand the tiles to the [rank][column] register layout through LDS
-      __syncthreads();
-      float *sDY = sX;   // R x J (the row block is dead)
-      float *sDD = sU;   // R x R
-      {
-        const int li = lane & 15;
-        const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
-#pragma unroll
-        for (int i = 0; i < kMxTiles; ++i) {
-          const int c = i >> 1, mt = i & 1;
-          const int nt = wv + 4 * c;
-          if (nt >= NT || mt >= MT) continue;
-          const int j = nt * 16 + li;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int r = mt * 16 + (lane >> 4) * 4 + q;
-            if (r < R && j < J) sDY[r * J + j] = accY[i][q];
-          }
-        }
-        if (wv < MT * MT) {
-          const int mt = wv / MT, st = wv - mt * MT;
-          const int c = st * 16 + li;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int r = mt * 16 + (lane >> 4) * 4 + q;
-            if (r < R && c < R) sDD[r * R + c] = accD[q];
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int rr = 0; rr < RW; ++rr) {
-        const int r = wv + 4 * rr;
-#pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
-          const int j = lane + 64 * jj;
-          dY[rr][jj] = (r < R && j < J) ? sDY[r * J + j] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = tid + 256 * i;
-        dD[i] = (q < RR) ? sDD[q] : 0.f;
-      }
-      // ||x||^2 of the slice's rows: wave sums, added in wave order by
-      // thread 0 behind the barrier ahead of the solve
-      dn = wave_sum(dn);
-      if (lane == 0) sDn[wv] = dn;
-    }
-
-    const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
-    const float s_old_f = (float)s_old;
-    float yv[RW][JW];
-    double cpart[RW];   // row r of diag(Y_k V) before the cross-lane sum
-#pragma unroll
-    for (int rr = 0; rr < RW; ++rr) {
-      const int r = wv + 4 * rr;
-      cpart[rr] = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
-        const int j = lane + 64 * jj;
-        const bool in = r < R && j < J;
-        if constexpr (MX) {
-          // compensated running sum: (hi, lo) folded in FP64 and split again;
-          // the new low word goes straight to the next buffer, the high word
-          // stays for F (whose FP32 sum does not resolve the low word)
-          const double v = touched ? s_old * ((double)yo[rr][jj] + (double)yl[rr][jj]) + (double)dY[rr][jj]
-                                   : (double)yo[rr][jj] + (double)yl[rr][jj];
-          yv[rr][jj] = (float)v;
-          if (touched && a.mode == 0 && in)
-            a.Yc[((int64_t)(1 - b) * a.K_cap + k) * a.ys + r * J + j] = (float)(v - (double)yv[rr][jj]);
-          if (in) cpart[rr] = fma(v, (double)sVt[r * J + j], cpart[rr]);
-        } else {
-          yv[rr][jj] = touched ? fmaf(s_old_f, yo[rr][jj], dY[rr][jj]) : yo[rr][jj];
-          if (in) cpart[rr] = fma((double)yv[rr][jj], (double)sVt[r * J + j], cpart[rr]);
-        }
-      }
-    }
-#pragma unroll
-    for (int rr = 0; rr < RW; ++rr) {
-      const int r = wv + 4 * rr;
-      const double part = wave_sum(cpart[rr]);
-      if (lane == 0 && r < R) {
-        sC[r] = part;
-        sC2[r] = part;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + 256 * i;
-      if (q < RR) {
-        if constexpr (MX) {
-          const double v = touched ? s_old * ((double)dold[i] + (double)dlo[i]) + (double)dD[i]
-                                   : (double)dold[i] + (double)dlo[i];
-          sDc[q] = (float)v;
-          sDlo[q] = (float)(v - (double)sDc[q]);
-          sM[q] = sVtV[q] * v;
-        } else {
-          const float dc = touched ? fmaf(s_old_f, dold[i], dD[i]) : dold[i];
-          sDc[q] = dc;
-          sM[q] = sVtV[q] * (double)dc;
-        }
-      }
-    }
-    __syncthreads();
-    // the next slice has rows: its first block is staged during this solve
-    const bool next_pre = a.mode == 0 && k + 1 < k1 && g < gend && a.groups[g].slice == k + 1;
-    if (a.mode == 0) {
-      if (wv == 0) {
-        // Lemma 2: Gauss-Jordan in registers (lane r holds row r), the
-        // Cholesky acceptance rule; the pseudo-inverse when it fails
-        constexpr int RM = BlockRM<RW>::value;
-        double m[RM];
-#pragma unroll
-        for (int c = 0; c < RM; ++c) m[c] = (lane < R && c < R) ? sM[lane * R + c] : 0.0;
-        double rhs[1] = {lane < R ? sC2[lane] : 0.0};
-        double dpiv;
-        if (wave_gj_reg<RM, 1>(m, rhs, dpiv, R)) {
-          if (lane < R) sC[lane] = rhs[0] / dpiv;
-        } else {
-          wave_pinv_apply(sM, sC, R, sZ, sTmp, sRot, sPair);
-        }
-      } else if (next_pre) {
-        // meanwhile waves 1-3 stage the next slice's first row block (the
-        // row buffer is free from here to that slice's row phase)
-        const Group gn = a.groups[g];
-        const int m1 = min(MB, gn.nrows);
-        const int mp1 = MX ? (m1 + 31) & ~31 : (m1 + 15) & ~15;
-        dn_pre = stage_rows<true, 192>(gn.src, m1, J, XS, sX, tid - 64);
-        for (int e = tid - 64; e < (mp1 - m1) * J; e += 192) {
-          const int row = e / J;
-          sX[(m1 + row) * XS + (e - row * J)] = 0.f;
-        }
-      }
-      __syncthreads();
-      if (tid < R) a.W[((int64_t)wout * a.K_cap + k) * R + tid] = sC[tid];
-    } else {
-      if (tid < R) sC[tid] = sW[tid];
-      __syncthreads();
-    }
-    pre = next_pre;
-    const double sigma = touched ? 1.0 : s_old;
-#pragma unroll
-    for (int rr = 0; rr < RW; ++rr) {
-      const int r = wv + 4 * rr;
-      if (r < R) {
-        const double wr = sigma * sC[r];
-#pragma unroll
-        for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = fmaf((float)wr, yv[rr][jj], facc[rr][jj]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + 256 * i;
-      if (q < RR) {
-        const int r = q / R, s = q - r * R;
-        gacc[i] += sigma * sC[r] * sC[s] * ((double)sDc[q] + (MX ? (double)sDlo[q] : 0.0));
-      }
-    }
-    if (tid == 0) {
-      const double nold = is_new ? 0.0 : a.n[(int64_t)b * a.K_cap + k];
-      const double dn_all = (touched && a.mode == 0) ? ((sDn[0] + sDn[1]) + sDn[2]) + sDn[3] : 0.0;
-      const double ncur = s_old * nold + dn_all;
-      nacc += ncur;
-      if (touched && a.mode == 0) a.n[(int64_t)(1 - b) * a.K_cap + k] = ncur;
-      if (a.mode == 0) {
-        a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(touched ? 1 - b : b);
-        a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = touched ? (int32_t)step : tl;
-      }
-    }
-    if (touched && a.mode == 0) {
-      float *Ynx = a.Y + ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
-#pragma unroll
-      for (int rr = 0; rr < RW; ++rr) {
-        const int r = wv + 4 * rr;
-#pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
-          const int j = lane + 64 * jj;
-          if (r < R && j < J) Ynx[r * J + j] = yv[rr][jj];
-        }
-      }
-      float *Dnx = a.D + ((int64_t)(1 - b) * a.K_cap + k) * RR;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int q = tid + 256 * i;
-        if (q < RR) Dnx[q] = sDc[q];
-        if constexpr (MX) {
-          if (q < RR) a.Dc[((int64_t)(1 - b) * a.K_cap + k) * RR + q] = sDlo[q];
-        }
-      }
-    }
-  }
-
-  double *part = a.partials + (int64_t)chunk * plen;
-#pragma unroll
-  for (int rr = 0; rr < RW; ++rr) {
-    const int r = wv + 4 * rr;
-#pragma unroll
-    for (int jj = 0; jj < JW; ++jj) {
-      const int j = lane + 64 * jj;
-      if (r < R && j < J) part[r * J + j] = (double)facc[rr][jj];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int q = tid + 256 * i;
-    if (q < RR) part[R * J + q] = gacc[i];
-  }
-  if (tid == 0) part[R * J + RR] = nacc;
-  if (arrive(a, h, chunk, &sflag))
-    finish_pass<FinishBucket<4 * RW>::value>(a, h, h->n_rgroups, a.mode == 0 ? 0 : 2, smem, (size_t)a.lds_bytes);
-}
 
 // ---------------------------------------------------------------------------
 // k_accum_given_u: helper terms of the initial tensor from given U rows
@@ -1521,11 +940,12 @@ static inline int dq_of(int R) {
   return 4;   // R <= 16
 }
 
-int pass_variant(int J, int R, int precision) {
-  if (precision != 0) return kPassBlock;   // the BF16 MFMA row phase lives in the block variant
-  // the per-wave register tiles fit without spilling up to R = 16
-  if (J <= 128 && R <= 16 && R * J <= 2048 && wave_lds(J, R).bytes <= 150 * 1024) return kPassWave;
-  return kPassBlock;
+int pass_variant(int J, int R, int precision, int lagged) {
+  // the fused sweep: float32 exact mode, per-wave register tiles that fit
+  // without spilling (R <= 16)
+  if (precision == 0 && !lagged && J <= 128 && R <= 16 && R * J <= 2048 && wave_lds(J, R).bytes <= 150 * 1024)
+    return kPassWave;
+  return kPassSplit;
 }
 
 int pass_chunk(int variant, int K, int n_cu) {
@@ -1552,21 +972,9 @@ static int launch_wave_t(const PassArgs &a, int n_chunks, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-template <int RW, int JW>
-static int launch_block_t(const PassArgs &a, int n_chunks, hipStream_t s) {
-  const size_t bytes = a.fuse ? (size_t)a.lds_bytes : pass_lds(a.J, a.R).bytes;
-  if (a.mixed) {   // one instantiation covers every shape (R <= 32, J <= 256)
-    if (int e = allow_lds(k_pass_block<8, 4, true>, bytes)) return e;
-    hipLaunchKernelGGL((k_pass_block<8, 4, true>), dim3(n_chunks), dim3(256), bytes, s, a);
-  } else {
-    if (int e = allow_lds(k_pass_block<RW, JW, false>, bytes)) return e;
-    hipLaunchKernelGGL((k_pass_block<RW, JW, false>), dim3(n_chunks), dim3(256), bytes, s, a);
-  }
-  return (int)hipGetLastError();
-}
-
 size_t fused_pass_lds(int variant, int J, int R) {
-  const size_t sweep = (variant == kPassWave) ? wave_lds(J, R).bytes : pass_lds(J, R).bytes;
+  if (variant != kPassWave) return 0;   // the split sweep ends in a separate final-phase launch
+  const size_t sweep = wave_lds(J, R).bytes;
   const size_t cap = 160 * 1024 - 1024;   // the kernels' static LDS (flags, small sums) stays under 1 KiB
   const size_t with_v = std::max(sweep, finish_launch_lds(J, R));
   if (with_v <= cap) return with_v;
@@ -1594,16 +1002,7 @@ int launch_pass(const PassArgs &a, int variant, int n_chunks, hipStream_t s) {
       default: return (int)hipErrorInvalidValue;
     }
   }
-  if (a.mixed) return launch_block_t<8, 4>(a, n_chunks, s);
-  switch (rw_of(a.R) * 8 + jw_of(a.J)) {
-#define C(RW, JW) case RW * 8 + JW: return launch_block_t<RW, JW>(a, n_chunks, s);
-    C(1, 1) C(1, 2) C(1, 3) C(1, 4) C(2, 1) C(2, 2) C(2, 3) C(2, 4)
-    C(3, 1) C(3, 2) C(3, 3) C(3, 4) C(4, 1) C(4, 2) C(4, 3) C(4, 4)
-    C(5, 1) C(5, 2) C(5, 3) C(5, 4) C(6, 1) C(6, 2) C(6, 3) C(6, 4)
-    C(7, 1) C(7, 2) C(7, 3) C(7, 4) C(8, 1) C(8, 2) C(8, 3) C(8, 4)
-#undef C
-    default: return (int)hipErrorInvalidValue;
-  }
+  return (int)hipErrorInvalidValue;   // the split sweep has launchers of its own
 }
 
 template <int RM>
@@ -1612,6 +1011,30 @@ static int launch_finish_t(const PassArgs &a, int mode, hipStream_t s) {
   if (int e = allow_lds(k_finish<RM>, bytes)) return e;
   hipLaunchKernelGGL((k_finish<RM>), dim3(1), dim3(kFinishThreads), bytes, s, a, mode);
   return (int)hipGetLastError();
+}
+
+template <int RM>
+static int launch_finish_dev_t(const PassArgs *args, const BlockMap *map, int n_blocks, int mode, size_t bytes,
+                               hipStream_t s) {
+  if (int e = allow_lds(k_finish_dev<RM>, bytes)) return e;
+  hipLaunchKernelGGL((k_finish_dev<RM>), dim3(n_blocks), dim3(kFinishThreads), bytes, s, args, map, mode);
+  return (int)hipGetLastError();
+}
+
+int finish_class(int R) { return R <= 8 ? 8 : R <= 12 ? 12 : R <= 16 ? 16 : R <= 24 ? 24 : 32; }
+size_t finish_dev_lds(int J, int R) { return finish_launch_lds(J, R); }
+
+int launch_finish_dev(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, int mode,
+                      hipStream_t s, size_t lds) {
+  if (n_blocks <= 0) return 0;
+  const size_t bytes = lds ? lds : finish_launch_lds(a.J, a.R);
+  switch (finish_class(a.R)) {
+    case 8: return launch_finish_dev_t<8>(args, map, n_blocks, mode, bytes, s);
+    case 12: return launch_finish_dev_t<12>(args, map, n_blocks, mode, bytes, s);
+    case 16: return launch_finish_dev_t<16>(args, map, n_blocks, mode, bytes, s);
+    case 24: return launch_finish_dev_t<24>(args, map, n_blocks, mode, bytes, s);
+    default: return launch_finish_dev_t<32>(args, map, n_blocks, mode, bytes, s);
+  }
 }
 
 int launch_finish(const PassArgs &a, int mode, hipStream_t s) {

@@ -48,6 +48,12 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long x = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)x, l);
@@ -250,8 +256,10 @@ __device__ __forceinline__ bool wave_gj_reg(double (&m)[RM], double (&b)[NB], do
 // elimination, hence takes the same acceptance decision; the return value is
 // that decision on waves 0..3 and true elsewhere (the caller combines it
 // through LDS and synchronises the block before reading Ainv).
+// With piv, wave 0 also stores the elimination pivots (piv[i] = lane i's d,
+// the Schur complement diagonal) when the elimination is accepted.
 template <int RM>
-__device__ bool block_spd_inverse(const double *A, double *Ainv, int n) {
+__device__ bool block_spd_inverse(const double *A, double *Ainv, int n, double *piv = nullptr) {
   constexpr int NB = RM / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (wv >= 4) return true;
@@ -263,6 +271,7 @@ __device__ bool block_spd_inverse(const double *A, double *Ainv, int n) {
   for (int k = 0; k < NB; ++k) rhs[k] = (lane == wv * NB + k) ? 1.0 : 0.0;
   double d;
   if (!wave_gj_reg<RM, NB>(m, rhs, d, n)) return false;
+  if (piv && wv == 0 && lane < n) piv[lane] = d;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int col = wv * NB + k;

@@ -1,0 +1,987 @@
+// Split sweep of one ALS pass of the DASH update on gfx950 (Algorithm 1 with
+// Lemmas 1-3), as four launches on the context's stream:
+//
+//   row stage   k_rows:   the touched slices, most rows first, pulled from a
+//                         device work queue by persistent workgroups.  Lemma 1
+//                         on the new rows (MFMA), the new-row sums dY = U^T X,
+//                         dD = U^T U, dn = sum ||x||^2, the fold under the
+//                         forgetting factor (eq. [obtain_CandD]) into the spare
+//                         state buffer, and c_k = diag(Y_k V) (Lemma 2) -- or,
+//                         in lagged mode, its recursion (eq. [obtain_CandC]).
+//   solve stage k_solve:  every slice, one wave each: c_k of the untouched
+//                         slices from their stored Y_k, Lemma 2's system
+//                         (V^T V * D_k) w_k = c_k in FP64 (pseudo-inverse when
+//                         it fails the acceptance rule), the slice bookkeeping
+//                         of the next state, and G / sum-n partials.
+//   F stage     k_fsum:   F^T = sum_k sigma_k diag(w_k) Y_k streamed over every
+//                         slice (exact mode), or k_fsum_rows: the new rows'
+//                         terms of eq. [obtain_FandF], [obtain_FandG] (lagged
+//                         mode); chunk partials in FP64, the first level of the
+//                         fixed-order reduction by the last arrival of each group.
+//   final phase k_finish (dash_kernels.hip): Lemma 3 and, on the last pass,
+//                         the commit.
+//
+// Every slice's work stays on one workgroup (row stage) or one wave (solve
+// stage) and every sum that spans slices is a fixed-order reduction of
+// per-chunk partials, so the results do not depend on which workgroup ran a
+// slice.  Untouched slices are solved on their stored, undecayed Y_k and D_k
+// (w_k does not depend on the common factor lambda^dt) and enter F and G with
+// sigma_k = lambda^dt.  See dash_dev.h for the layouts.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "dash_dev.h"
+#include "dash_math.h"
+#include "dash_tiles.h"
+
+namespace dash {
+
+// ---------------------------------------------------------------------------
+// Row stage
+// ---------------------------------------------------------------------------
+struct RowsLds {
+  int XS, MB;
+  size_t oP, oX, oU, oZf, oW, oWinv, bytes;
+};
+
+// P (J x R), a row block (MB rows, odd stride) that is also the hand-off
+// buffer of dY (R x J) and the scratch of Lemma 1's pseudo-inverse form, the
+// U block (MB x (R+1), also dD), that form's matrix Z (R x R), w and 1/w.
+__host__ __device__ inline RowsLds rows_lds(int J, int R) {
+  RowsLds L;
+  L.XS = J | 1;
+  L.MB = (J <= 128) ? 64 : 32;
+  size_t o = 0;
+  L.oP = o;
+  o = align_up(o + (size_t)J * R * 4, 16);
+  L.oX = o;
+  size_t xb = (size_t)L.MB * L.XS * 4;
+  const size_t scr = (size_t)(2 * R * R + R + 64) * 8 + 64 * 4;
+  xb = std::max(xb, scr);
+  xb = std::max(xb, (size_t)R * J * 4);
+  o = align_up(o + xb, 16);
+  L.oU = o;
+  o = align_up(o + (size_t)L.MB * (R + 1) * 4, 16);
+  L.oZf = o;
+  o = align_up(o + (size_t)R * R * 4, 16);
+  L.oW = o;
+  o += (size_t)R * 8;
+  L.oWinv = o;
+  o += (size_t)R * 4;
+  L.bytes = align_up(o, 16);
+  return L;
+}
+
+// RW ranks x JW columns per thread in the [rank][column] layout: thread
+// (wave w, lane l) owns r = w + 4 rr (rr < RW) and j = l + 64 jj (jj < JW).
+// SLOW = false: the slices whose Lemma 1 system passes the acceptance rule;
+// the others are deferred to a list.  SLOW = true: the deferred slices, with
+// the pseudo-inverse form (a separate launch, so that its code does not weigh
+// on the registers of the common case).
+template <int RW, int JW, bool MX, bool SLOW>
+__global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const BlockMap *map) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  __shared__ int sItem, sDefer;
+  __shared__ double sDn[4];
+  const StepHeader *h = a.hdr;
+  const int J = a.J, R = a.R, RR = R * R;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int Kp = h->K_prev, n_items = h->n_items, seq = h->seq;
+  const int64_t step = h->step;
+  const int gcur = a.ctl->gcur;
+  const int win = (a.pass == 0) ? gcur : 1 - gcur;
+  const VBundleView vb = vb_view(a.vb + (int64_t)win * a.vb_stride, J, R);
+  const RowsLds L = rows_lds(J, R);
+  float *sP = (float *)(smem + L.oP);
+  float *sX = (float *)(smem + L.oX);
+  double *sScr = (double *)(smem + L.oX);   // Lemma 1 pseudo-inverse scratch (before the rows)
+  float *sU = (float *)(smem + L.oU);
+  float *sZf = (float *)(smem + L.oZf);
+  double *sW = (double *)(smem + L.oW);
+  float *sWinv = (float *)(smem + L.oWinv);
+  const int XS = L.XS, MB = L.MB;
+  const bool write_u = a.last_pass || a.lagged;
+  if (a.stamp_start && blk == 0 && tid == 0 && a.pass == 0 && h->report)
+    ((Report *)h->report)->t_start = __builtin_amdgcn_s_memrealtime();
+
+  for (int e = tid; e < J * R; e += 256) sP[e] = vb.P32[e];
+  // the entries of V^T this thread multiplies for c_k
+  float vt[RW][JW];
+#pragma unroll
+  for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+      const int r = wv + 4 * rr, j = lane + 64 * jj;
+      vt[rr][jj] = (r < R && j < J) ? vb.Vt32[r * J + j] : 0.f;
+    }
+  // pivots and diagonal of V^T V for Lemma 1's acceptance rule (wave 0, lane r)
+  const double pivl = lane < R ? vb.piv[lane] : 0.0;
+  const double arrl = lane < R ? vb.VtV[lane * R + lane] : 0.0;
+
+  for (;;) {
+    __syncthreads();   // the previous slice is done with LDS and sItem
+    if (threadIdx.x == 0) {
+      if (SLOW) {
+        const int q = atomicAdd(&a.queue[2], 1);
+        sItem = (q < __atomic_load_n(&a.queue[1], __ATOMIC_RELAXED)) ? a.slow_list[q] : n_items;
+      } else {
+        sItem = atomicAdd(&a.queue[0], 1);
+      }
+    }
+    __syncthreads();
+    const int it = sItem;
+    if (it >= n_items) break;
+    // the thread index, opaque to the compiler inside the loop: per-thread
+    // address arithmetic is redone per slice instead of being hoisted out of
+    // the loop into registers
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const Item item = a.items[it];
+    const int k = item.slice;
+    const bool is_new = k >= Kp;
+    const int b = a.cur[(int64_t)gcur * a.K_cap + k];
+    const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
+    const int64_t ybase = ((int64_t)b * a.K_cap + k) * a.ys;
+    const int64_t ynext = ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
+    const int64_t dbase = ((int64_t)b * a.K_cap + k) * RR;
+    const int64_t dnext = ((int64_t)(1 - b) * a.K_cap + k) * RR;
+    // the stored state: loaded before the rows in the float32 path (the row
+    // work hides its latency), after them in the mixed path (registers)
+    float yo[RW][JW];
+    float yl[MX ? RW : 1][MX ? JW : 1];
+    float dold[4], dlo[4];
+    auto load_state = [&]() {
+#pragma unroll
+      for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+          const int r = wv + 4 * rr, j = lane + 64 * jj;
+          const bool in = !is_new && r < R && j < J;
+          yo[rr][jj] = in ? a.Y[ybase + r * J + j] : 0.f;
+          if constexpr (MX) yl[rr][jj] = in ? a.Yc[ybase + r * J + j] : 0.f;
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = tid + 256 * i;
+        const bool in = !is_new && q < RR;
+        dold[i] = in ? a.D[dbase + q] : 0.f;
+        dlo[i] = (MX && in) ? a.Dc[dbase + q] : 0.f;
+      }
+    };
+    if (wv == 0) {
+      // the weights Lemma 1 uses (1 for a new slice's first pass) and the
+      // acceptance rule of its system S_k V^T V S_k
+      const double w = (lane < R) ? ((is_new && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + lane])
+                                  : 0.0;
+      const bool regular = SLOW || lemma1_regular(w, pivl, arrl, R);
+      if (lane < R) {
+        sW[lane] = w;
+        sWinv[lane] = regular ? (float)(1.0 / w) : 0.f;
+      }
+      if (lane == 0) {
+        sDefer = regular ? 0 : 1;
+        if (!regular) a.slow_list[atomicAdd(&a.queue[1], 1)] = it;
+      }
+    }
+    __syncthreads();
+    if (!SLOW && sDefer) continue;
+    if constexpr (!MX) load_state();
+    constexpr bool slow = SLOW;
+    if (slow) {
+      if (wv == 0)
+        lemma1_pinv_matrix(vb.VtV, sW, R, sScr, sScr + RR, sScr + 2 * RR, sScr + 2 * RR + R,
+                           (int *)(sScr + 2 * RR + R + 64), sZf, R);
+      __syncthreads();
+    }
+
+    // Lemma 1 and the new-row sums on MFMA (FP32 16x16x4, or BF16 16x16x32
+    // with FP32 sums in the mixed path); the dY, dD tiles stay in the waves'
+    // accumulators over every block of the slice
+    f32x4 accY[kMxTiles];
+    f32x4 accD = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    double dn = 0.0;
+    const int NTu = (R + 15) >> 4;
+    for (int gi = item.g0; gi < item.g1; ++gi) {
+      const Group gr = a.groups[gi];
+      for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
+        const int m = min(MB, gr.nrows - r0);
+        const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
+        __syncthreads();
+        dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
+        for (int e = tid; e < (mp - m) * J; e += 256) {
+          const int row = e / J;
+          sX[(m + row) * XS + (e - row * J)] = 0.f;
+        }
+        __syncthreads();
+        // t = x P per (row tile, rank tile): wave w takes jobs w and w + 4
+        const int jobs = (mp >> 4) * NTu;
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+          const int job = wv + 4 * jb;
+          if (job < jobs) {
+            const int rt = job / NTu, nt = job - rt * NTu;
+            const f32x4 acc = rows_times_p<MX>(sX + (16 * rt + (lane & 15)) * XS, sP, J, R, nt, lane);
+            const int n = nt * 16 + (lane & 15);
+            if (n < R) {
+              const float wi = sWinv[n];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int rr = 16 * rt + (lane >> 4) * 4 + q;
+                if (slow) {
+                  sU[rr * (R + 1) + n] = (rr < m) ? acc[q] : 0.f;
+                } else {
+                  const float u = (rr < m) ? acc[q] * wi : 0.f;
+                  sU[rr * (R + 1) + n] = u;
+                  if (write_u && rr < m) a.U_out[(gr.out_row + r0 + rr) * R + n] = u;
+                }
+              }
+            }
+          }
+        }
+        if (slow) {
+          // u = t Z, row by row (at most 8 entries per thread)
+          __syncthreads();
+          float uq[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int e = tid + 256 * i;
+            uq[i] = 0.f;
+            if (e < mp * R) {
+              const int row = e / R, n = e - row * R;
+              float acc = 0.f;
+              for (int mm = 0; mm < R; ++mm) acc = fmaf(sU[row * (R + 1) + mm], sZf[mm * R + n], acc);
+              uq[i] = (row < m) ? acc : 0.f;
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int e = tid + 256 * i;
+            if (e < mp * R) {
+              const int row = e / R, n = e - row * R;
+              sU[row * (R + 1) + n] = uq[i];
+              if (write_u && row < m) a.U_out[(gr.out_row + r0 + row) * R + n] = uq[i];
+            }
+          }
+        }
+        __syncthreads();
+        if constexpr (MX)
+          accum_block_mx(sX, sU, XS, mp, J, R, accY, accD, tid);
+        else
+          accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
+      }
+    }
+    if constexpr (MX) load_state();
+    // hand the tiles to the [rank][column] layout through LDS
+    __syncthreads();
+    float *sDY = sX;   // R x J
+    float *sDD = sU;   // R x R
+    {
+      const int li = lane & 15;
+      const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
+#pragma unroll
+      for (int i = 0; i < kMxTiles; ++i) {
+        const int c = i >> 1, mt = i & 1;
+        const int nt = wv + 4 * c;
+        if (nt >= NT || mt >= MT) continue;
+        const int j = nt * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = mt * 16 + (lane >> 4) * 4 + q;
+          if (r < R && j < J) sDY[r * J + j] = accY[i][q];
+        }
+      }
+      if (wv < MT * MT) {
+        const int mt = wv / MT, st = wv - mt * MT;
+        const int cc = st * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = mt * 16 + (lane >> 4) * 4 + q;
+          if (r < R && cc < R) sDD[r * R + cc] = accD[q];
+        }
+      }
+    }
+    dn = wave_sum(dn);
+    if (lane == 0) sDn[wv] = dn;
+    __syncthreads();
+
+    // fold: Y_k = lambda^dt Y_k,stored + dY into the spare buffer; c_k
+    const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
+    const float s_old_f = (float)s_old;
+    double cpart[RW];
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) {
+      const int r = wv + 4 * rr;
+      cpart[rr] = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) {
+        const int j = lane + 64 * jj;
+        const bool in = r < R && j < J;
+        const float dy = in ? sDY[r * J + j] : 0.f;
+        double cv;
+        if constexpr (MX) {
+          // compensated running sum: (hi, lo) folded in FP64 and split again
+          const double v = s_old * ((double)yo[rr][jj] + (double)yl[rr][jj]) + (double)dy;
+          const float hi = (float)v;
+          if (in) {
+            a.Y[ynext + r * J + j] = hi;
+            a.Yc[ynext + r * J + j] = (float)(v - (double)hi);
+          }
+          cv = a.lagged ? (double)dy : v;
+        } else {
+          const float yv = fmaf(s_old_f, yo[rr][jj], dy);
+          if (in) a.Y[ynext + r * J + j] = yv;
+          cv = a.lagged ? (double)dy : (double)yv;
+        }
+        cpart[rr] = fma(cv, (double)vt[rr][jj], cpart[rr]);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) {
+      const int r = wv + 4 * rr;
+      const double part = wave_sum(cpart[rr]);
+      if (lane == 0 && r < R) {
+        if (a.lagged) {
+          // eq. [obtain_CandC]: the stored c_k decayed, plus diag(U^T X V)
+          const double cold = is_new ? 0.0 : a.cst[((int64_t)b * a.K_cap + k) * R + r];
+          const double cc = fma(s_old, cold, part);
+          a.cst[((int64_t)(1 - b) * a.K_cap + k) * R + r] = cc;
+          a.cbuf[(int64_t)k * R + r] = cc;
+        } else {
+          a.cbuf[(int64_t)k * R + r] = part;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      if (q < RR) {
+        const float dd = sDD[q];
+        if constexpr (MX) {
+          const double v = s_old * ((double)dold[i] + (double)dlo[i]) + (double)dd;
+          const float hi = (float)v;
+          a.D[dnext + q] = hi;
+          a.Dc[dnext + q] = (float)(v - (double)hi);
+        } else {
+          a.D[dnext + q] = fmaf(s_old_f, dold[i], dd);
+        }
+      }
+    }
+    if (tid == 0) {
+      const double nold = is_new ? 0.0 : a.n[(int64_t)b * a.K_cap + k];
+      a.n[(int64_t)(1 - b) * a.K_cap + k] = s_old * nold + (((sDn[0] + sDn[1]) + sDn[2]) + sDn[3]);
+      a.tag[k] = seq;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve stage
+// ---------------------------------------------------------------------------
+struct SolveLds {
+  size_t oVtV, oWv, oVt, oScr, oComb, bytes;
+};
+
+// V^T V (FP64), the waves' weights, the waves' G / sum-n slots (4 x (R^2 + 1),
+// accumulated in place), V^T (float, R x J) and the shared pseudo-inverse scratch.
+__host__ __device__ inline SolveLds solve_lds(int J, int R) {
+  SolveLds L;
+  size_t o = 0;
+  L.oVtV = o;
+  o += (size_t)R * R * 8;
+  L.oWv = o;
+  o += (size_t)4 * R * 8;
+  L.oComb = o;
+  o += (size_t)4 * (R * R + 1) * 8;
+  o = align_up(o, 16);
+  L.oVt = o;
+  o = align_up(o + (size_t)R * J * 4, 16);
+  L.oScr = o;
+  o += (size_t)(2 * R * R + R + 3 * 64) * 8 + 64 * 4;
+  L.bytes = align_up(o, 16);
+  return L;
+}
+
+// c_r = sum_j Y_k[r][j] V[j][r] of one slice by one wave: lane l takes the
+// columns j = l + 64 jj, four ranks at a time, FP64 sums; lane r returns c_r.
+__device__ inline double slice_c(const float *__restrict__ Yk, const float *sVt, int J, int R) {
+  const int lane = threadIdx.x & 63;
+  double c = 0.0;
+  for (int r0 = 0; r0 < R; r0 += 4) {
+    float y[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int r = r0 + i, j = lane + 64 * jj;
+        y[i][jj] = (r < R && j < J) ? Yk[r * J + j] : 0.f;
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double p = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int r = r0 + i, j = lane + 64 * jj;
+        if (r < R && j < J) p = fma((double)y[i][jj], (double)sVt[r * J + j], p);
+      }
+      p = wave_sum(p);
+      if (lane == r0 + i) c = p;
+    }
+  }
+  return c;
+}
+
+// mode 0 (update pass) or 1 (evaluation of the committed state: w_k is the
+// committed W, no solve; in lagged mode c_k = diag(Y_k V) is stored as the
+// recursion's starting value).  Workgroup = one solve chunk, 4 waves, one
+// slice per wave per round.
+template <int RM>
+__global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const BlockMap *map) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  __shared__ int sFail[4];
+  constexpr int NQ = (RM * RM + 63) / 64;
+  const StepHeader *h = a.hdr;
+  const int J = a.J, R = a.R, RR = R * R;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int K = h->K, seq = h->seq;
+  const int64_t step = h->step;
+  const int gcur = a.ctl->gcur;
+  const int win = (a.pass == 0) ? gcur : 1 - gcur;
+  const int wout = 1 - gcur;
+  const bool upd = a.mode == 0;
+  const VBundleView vb = vb_view(a.vb + (int64_t)(upd ? win : gcur) * a.vb_stride, J, R);
+  const SolveLds L = solve_lds(J, R);
+  double *sVtV = (double *)(smem + L.oVtV);
+  double *sWv = (double *)(smem + L.oWv);
+  float *sVt = (float *)(smem + L.oVt);
+  double *sM = (double *)(smem + L.oScr);
+  double *sZ = sM + RR;
+  double *sx = sZ + RR;
+  double *sTmp = sx + R;
+  double *sRot = sTmp + 64;
+  int *sPair = (int *)(sRot + 128);
+  double *sComb = (double *)(smem + L.oComb);
+  const int chunk2 = blk;
+  const int k0 = chunk2 * h->chunk2;
+  const int k1 = min(K, k0 + h->chunk2);
+  // the row stage has finished: its work counter is free for the next launch
+  if (upd && chunk2 == 0 && tid < 3) a.queue[tid] = 0;
+  const bool need_c = upd ? !a.lagged : (a.lagged != 0);
+  for (int e = tid; e < RR; e += 256) sVtV[e] = vb.VtV[e];
+  for (int e = tid; e < 4 * (RR + 1); e += 256) sComb[e] = 0.0;
+  if (need_c)
+    for (int e = tid; e < R * J; e += 256) sVt[e] = vb.Vt32[e];
+  __syncthreads();
+
+  double *gslot = sComb + wv * (RR + 1);   // this wave's G and sum n
+  double nacc = 0.0;
+  const bool do_g = !a.lagged || !upd;
+
+  for (int base = k0; base < k1; base += 4) {
+    const int k = base + wv;
+    const bool valid = k < k1;
+    bool ok = true;
+    double w = 0.0, c = 0.0, sig = 0.0;
+    int b = 0, tl = 0;
+    bool touched = false;
+    const float *Dp = nullptr, *Dcp = nullptr;
+    if (valid) {
+      b = a.cur[(int64_t)gcur * a.K_cap + k];
+      tl = a.tlast[(int64_t)gcur * a.K_cap + k];
+      touched = upd && a.tag[k] == seq;
+      const int bs = touched ? 1 - b : b;
+      sig = touched ? 1.0 : exp2((double)(step - tl) * a.log2_lambda);
+      Dp = a.D + ((int64_t)bs * a.K_cap + k) * RR;
+      Dcp = a.Dc ? a.Dc + ((int64_t)bs * a.K_cap + k) * RR : nullptr;
+      if (lane == 0) nacc = fma(sig, a.n[(int64_t)bs * a.K_cap + k], nacc);
+      const float *Yk = a.Y + ((int64_t)b * a.K_cap + k) * a.ys;
+      if (upd) {
+        if (touched) c = lane < R ? a.cbuf[(int64_t)k * R + lane] : 0.0;
+        else if (a.lagged) c = lane < R ? a.cst[((int64_t)b * a.K_cap + k) * R + lane] : 0.0;
+        else c = slice_c(Yk, sVt, J, R);
+        // Lemma 2: (V^T V * D_k) w = c, Gauss-Jordan in registers (lane r holds row r)
+        double m[RM];
+#pragma unroll
+        for (int cc = 0; cc < RM; ++cc)
+          m[cc] = (lane < R && cc < R)
+                      ? sVtV[lane * R + cc] * ((double)Dp[lane * R + cc] + (Dcp ? (double)Dcp[lane * R + cc] : 0.0))
+                      : 0.0;
+        double rhs[1] = {c};
+        double dpiv;
+        ok = wave_gj_reg<RM, 1>(m, rhs, dpiv, R);
+        w = (ok && lane < R) ? rhs[0] / dpiv : 0.0;
+      } else {
+        if (a.lagged) {
+          c = slice_c(Yk, sVt, J, R);
+          if (lane < R) a.cst[((int64_t)b * a.K_cap + k) * R + lane] = c;
+        }
+        w = lane < R ? a.W[((int64_t)gcur * a.K_cap + k) * R + lane] : 0.0;
+      }
+    }
+    if (lane == 0) sFail[wv] = (valid && !ok) ? 1 : 0;
+    __syncthreads();
+    // systems that failed the acceptance rule: the eigen pseudo-inverse, one
+    // wave at a time in the shared scratch
+    for (int v = 0; v < 4; ++v) {
+      if (!sFail[v]) continue;
+      if (wv == v) {
+        for (int q = lane; q < RR; q += 64)
+          sM[q] = sVtV[q] * ((double)Dp[q] + (Dcp ? (double)Dcp[q] : 0.0));
+        if (lane < R) sx[lane] = c;
+        wave_sync();
+        wave_pinv_apply(sM, sx, R, sZ, sTmp, sRot, sPair);
+        w = lane < R ? sx[lane] : 0.0;
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      if (upd) {
+        if (lane < R) a.W[((int64_t)wout * a.K_cap + k) * R + lane] = w;
+        if (lane == 0) {
+          a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(touched ? 1 - b : b);
+          a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = touched ? (int32_t)step : tl;
+        }
+      }
+      if (do_g) {
+        // G += sigma_k diag(w_k) D_k diag(w_k)
+        double *ww = sWv + wv * R;
+        if (lane < R) ww[lane] = w;
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+          const int q = lane + 64 * i;
+          if (q < RR) {
+            const int r = q / R, s = q - r * R;
+            const double d = (double)Dp[q] + (Dcp ? (double)Dcp[q] : 0.0);
+            gslot[q] = fma(sig * ww[r] * ww[s], d, gslot[q]);
+          }
+        }
+        wave_sync();
+      }
+    }
+  }
+  // the waves' partials added in wave order
+  if (lane == 0) gslot[RR] = nacc;
+  __syncthreads();
+  double *p2 = a.part2 + (int64_t)chunk2 * (RR + 1);
+  for (int e = tid; e <= RR; e += 256)
+    p2[e] = ((sComb[e] + sComb[(RR + 1) + e]) + sComb[2 * (RR + 1) + e]) + sComb[3 * (RR + 1) + e];
+}
+
+// ---------------------------------------------------------------------------
+// F stage, exact mode: F^T = sum_k sigma_k diag(w_k) Y_k over every slice of
+// the chunk, streamed as float4 from the flat R x J layout.  512 threads; TPS
+// threads per slice (a power of two, <= 512), 512 / TPS slices side by side,
+// up to two slices per thread group in flight; each thread owns the float4
+// positions q = tq + TPS e (e < EPT) of a slice.
+// ---------------------------------------------------------------------------
+constexpr int kFsumThreads = 512;
+constexpr int kFsumBatch = 64;   // slices whose weights are staged at a time
+
+__host__ __device__ inline int fsum_tps(int ys) {
+  const int nq = ys / 4;
+  if (nq > kFsumThreads) return kFsumThreads;
+  int tps = 1;
+  while (tps < nq) tps <<= 1;
+  return tps;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, const BlockMap *map) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  const int tps = fsum_tps(a.ys);
+  __shared__ int sflag;
+  __shared__ int sb[kFsumBatch];
+  const StepHeader *h = a.hdr;
+  const int J = a.J, R = a.R, RR = R * R, RJ = R * J;
+  const int tid = threadIdx.x;
+  const int K = h->K;
+  const int64_t step = h->step;
+  const int gcur = a.ctl->gcur;
+  const bool upd = a.mode == 0;
+  const int bsel = upd ? 1 - gcur : gcur;   // bookkeeping of the pass's state
+  const int wsel = upd ? 1 - gcur : gcur;   // the pass's weights
+  const int chunk = blk;
+  const int k0 = chunk * h->chunk;
+  const int k1 = min(K, k0 + h->chunk);
+  double *sw = (double *)smem;   // [kFsumBatch][R]: sigma_k w_k
+  const int spi = kFsumThreads / tps, sg = tid / tps, tq = tid - sg * tps;
+  const int nq = a.ys >> 2;
+  // the row of each of this thread's floats (the 4 of a float4 can straddle
+  // two rows, or more when J < 4)
+  int rr[EPT][4];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int el = 4 * (tq + tps * e) + c;
+      rr[e][c] = (el < RJ) ? el / J : -1;
+    }
+  double acc[EPT][4];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[e][c] = 0.0;
+
+  for (int kb = k0; kb < k1; kb += kFsumBatch) {
+    const int nb = min(kFsumBatch, k1 - kb);
+    __syncthreads();
+    for (int e = tid; e < nb * R; e += kFsumThreads) {
+      const int i = e / R, r = e - i * R, k = kb + i;
+      const int tl = a.tlast[(int64_t)bsel * a.K_cap + k];
+      const double sig = exp2((double)(step - tl) * a.log2_lambda);
+      sw[e] = sig * a.W[((int64_t)wsel * a.K_cap + k) * R + r];
+    }
+    for (int i = tid; i < nb; i += kFsumThreads) sb[i] = a.cur[(int64_t)bsel * a.K_cap + kb + i];
+    __syncthreads();
+    // two slices per thread group in flight where the registers allow it
+    constexpr int NS = EPT <= 2 ? 2 : 1;
+    for (int i = sg; i < nb; i += NS * spi) {
+      const int i2 = i + spi;
+      const bool two = NS == 2 && i2 < nb;
+      const float4 *y1 = (const float4 *)(a.Y + ((int64_t)sb[i] * a.K_cap + kb + i) * a.ys);
+      const float4 *y2 = two ? (const float4 *)(a.Y + ((int64_t)sb[i2] * a.K_cap + kb + i2) * a.ys) : y1;
+      float4 v1[EPT], v2[EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int q = tq + tps * e;
+        v1[e] = (q < nq) ? y1[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        v2[e] = (q < nq && two) ? y2[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      const double *w1 = sw + i * R, *w2 = sw + (two ? i2 : i) * R;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const float a1[4] = {v1[e].x, v1[e].y, v1[e].z, v1[e].w};
+        const float a2[4] = {v2[e].x, v2[e].y, v2[e].z, v2[e].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int r = rr[e][c];
+          if (r >= 0) {
+            acc[e][c] = fma(w1[r], (double)a1[c], acc[e][c]);
+            if (two) acc[e][c] = fma(w2[r], (double)a2[c], acc[e][c]);
+          }
+        }
+      }
+    }
+  }
+  // the slice groups' sums added in group order
+  double *part = a.partials + (int64_t)chunk * partial_len(J, R);
+  double *scomb = (double *)smem;   // kFsumThreads x 4
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int el = 4 * (tq + tps * e);
+    if (spi == 1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (el + c < RJ) part[el + c] = acc[e][c];
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 4; ++c) scomb[tid * 4 + c] = acc[e][c];
+      __syncthreads();
+      if (sg == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (el + c < RJ) {
+            double sum = 0.0;
+            for (int g = 0; g < spi; ++g) sum += scomb[(g * tps + tq) * 4 + c];
+            part[el + c] = sum;
+          }
+        }
+      }
+    }
+  }
+  // G and sum n from the solve chunks of this chunk, in order
+  const int per = h->chunk / h->chunk2;
+  const int c2a = chunk * per, c2b = min(h->n_chunks2, c2a + per);
+  for (int e = tid; e <= RR; e += kFsumThreads) part[RJ + e] = ordered_sum(a.part2, RR + 1, e, c2a, c2b);
+  (void)arrive(a, h, chunk, &sflag);
+}
+
+// ---------------------------------------------------------------------------
+// F stage, lagged mode: the new rows' terms of eq. [obtain_FandF] and
+// [obtain_FandG], sum over touched slices of (U_k S_k)^T X_k and
+// S_k U_k^T U_k S_k with the pass's new S_k.  Workgroup c takes the items
+// c, c + n_chunks, ... (static, so the sums do not depend on scheduling).
+// ---------------------------------------------------------------------------
+template <int RW, int JW, bool MX>
+__global__ __launch_bounds__(256) void k_fsum_rows(const PassArgs *args, const BlockMap *map) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  __shared__ int sflag;
+  const StepHeader *h = a.hdr;
+  const int J = a.J, R = a.R, RR = R * R, RJ = R * J;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int gcur = a.ctl->gcur;
+  const int wout = 1 - gcur;
+  const RowsLds L = rows_lds(J, R);
+  float *sX = (float *)(smem + L.oX);
+  float *sU = (float *)(smem + L.oU);
+  double *sW = (double *)(smem + L.oW);
+  const int XS = L.XS, MB = L.MB;
+  const int chunk = blk;
+  double facc[RW][JW];
+  double gacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) facc[rr][jj] = 0.0;
+
+  for (int it = chunk; it < h->n_items; it += h->n_chunks) {
+    const Item item = a.items[it];
+    const int k = item.slice;
+    __syncthreads();
+    if (tid < R) sW[tid] = a.W[((int64_t)wout * a.K_cap + k) * R + tid];
+    f32x4 accY[kMxTiles];
+    f32x4 accD = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kMxTiles; ++i) accY[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int gi = item.g0; gi < item.g1; ++gi) {
+      const Group gr = a.groups[gi];
+      for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
+        const int m = min(MB, gr.nrows - r0);
+        const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
+        __syncthreads();
+        (void)stage_rows<false>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
+        for (int e = tid; e < (mp - m) * J; e += 256) {
+          const int row = e / J;
+          sX[(m + row) * XS + (e - row * J)] = 0.f;
+        }
+        for (int e = tid; e < mp * R; e += 256) {
+          const int row = e / R, n = e - row * R;
+          sU[row * (R + 1) + n] = (row < m) ? (float)(a.U_out[(gr.out_row + r0 + row) * R + n] * sW[n]) : 0.f;
+        }
+        __syncthreads();
+        if constexpr (MX)
+          accum_block_mx(sX, sU, XS, mp, J, R, accY, accD, tid);
+        else
+          accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
+      }
+    }
+    // the slice's tiles into the FP64 sums through LDS
+    __syncthreads();
+    float *sDY = sX, *sDD = sU;
+    {
+      const int li = lane & 15;
+      const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
+#pragma unroll
+      for (int i = 0; i < kMxTiles; ++i) {
+        const int c = i >> 1, mt = i & 1;
+        const int nt = wv + 4 * c;
+        if (nt >= NT || mt >= MT) continue;
+        const int j = nt * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = mt * 16 + (lane >> 4) * 4 + q;
+          if (r < R && j < J) sDY[r * J + j] = accY[i][q];
+        }
+      }
+      if (wv < MT * MT) {
+        const int mt = wv / MT, st = wv - mt * MT;
+        const int cc = st * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = mt * 16 + (lane >> 4) * 4 + q;
+          if (r < R && cc < R) sDD[r * R + cc] = accD[q];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) {
+        const int r = wv + 4 * rr, j = lane + 64 * jj;
+        if (r < R && j < J) facc[rr][jj] += (double)sDY[r * J + j];
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      if (q < RR) gacc[i] += (double)sDD[q];
+    }
+  }
+  double *part = a.partials + (int64_t)chunk * partial_len(J, R);
+#pragma unroll
+  for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+      const int r = wv + 4 * rr, j = lane + 64 * jj;
+      if (r < R && j < J) part[r * J + j] = facc[rr][jj];
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = tid + 256 * i;
+    if (q < RR) part[RJ + q] = gacc[i];
+  }
+  // sum n from the solve chunks of this chunk, in order
+  const int per = h->chunk / h->chunk2;
+  const int c2a = chunk * per, c2b = min(h->n_chunks2, c2a + per);
+  if (tid == 0) part[RJ + RR] = ordered_sum(a.part2, RR + 1, RR, c2a, c2b);
+  (void)arrive(a, h, chunk, &sflag);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename F>
+static int allow_lds_s(F *fn, size_t bytes) {
+  if (bytes <= 65536) return 0;
+  return (int)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static inline int rw_bucket(int R) { return R <= 8 ? 2 : (R <= 16 ? 4 : 8); }
+static inline int jw_bucket(int J) { return J <= 64 ? 1 : (J <= 128 ? 2 : 4); }
+static inline int rm_bucket(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
+static inline int ept_bucket(int ys) {
+  const int tps = fsum_tps(ys), e = (ys / 4 + tps - 1) / tps;
+  return e <= 1 ? 1 : (e <= 2 ? 2 : 4);
+}
+
+int split_rows_class(int J, int R, int mixed) { return (rw_bucket(R) * 8 + jw_bucket(J)) * 2 + (mixed ? 1 : 0); }
+int split_solve_class(int R) { return rm_bucket(R); }
+int split_fsum_class(int J, int R, int lagged, int mixed) {
+  return lagged ? 1000 + split_rows_class(J, R, mixed) : ept_bucket(y_stride(J, R));
+}
+
+size_t split_rows_lds(int J, int R) { return rows_lds(J, R).bytes; }
+size_t split_solve_lds(int J, int R) { return solve_lds(J, R).bytes; }
+size_t split_fsum_lds(int J, int R, int lagged) {
+  if (lagged) return rows_lds(J, R).bytes;
+  return std::max((size_t)kFsumBatch * R * 8, (size_t)kFsumThreads * 4 * 8);
+}
+
+template <int RW, int JW, bool MX>
+static int launch_rows_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes, hipStream_t s) {
+  if (int e = allow_lds_s(k_rows<RW, JW, MX, false>, bytes)) return e;
+  hipLaunchKernelGGL((k_rows<RW, JW, MX, false>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  return (int)hipGetLastError();
+}
+
+template <int RW, int JW, bool MX>
+static int rows_occupancy_t(int J, int R) {
+  const size_t bytes = rows_lds(J, R).bytes;
+  if (allow_lds_s(k_rows<RW, JW, MX, false>, bytes)) return 1;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows<RW, JW, MX, false>, 256, bytes) != hipSuccess ||
+      n < 1)
+    return 1;
+  return n;
+}
+
+template <int RW, int JW, bool MX>
+static int launch_fsum_rows_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes,
+                              hipStream_t s) {
+  if (int e = allow_lds_s(k_fsum_rows<RW, JW, MX>, bytes)) return e;
+  hipLaunchKernelGGL((k_fsum_rows<RW, JW, MX>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  return (int)hipGetLastError();
+}
+
+#define DASH_RW_JW_SWITCH(FN, MX, ...)                                                              \
+  switch (rw_bucket(a.R) * 8 + jw_bucket(a.J)) {                                                    \
+    case 2 * 8 + 1: return FN<2, 1, MX>(__VA_ARGS__);                                               \
+    case 2 * 8 + 2: return FN<2, 2, MX>(__VA_ARGS__);                                               \
+    case 2 * 8 + 4: return FN<2, 4, MX>(__VA_ARGS__);                                               \
+    case 4 * 8 + 1: return FN<4, 1, MX>(__VA_ARGS__);                                               \
+    case 4 * 8 + 2: return FN<4, 2, MX>(__VA_ARGS__);                                               \
+    case 4 * 8 + 4: return FN<4, 4, MX>(__VA_ARGS__);                                               \
+    case 8 * 8 + 1: return FN<8, 1, MX>(__VA_ARGS__);                                               \
+    case 8 * 8 + 2: return FN<8, 2, MX>(__VA_ARGS__);                                               \
+    case 8 * 8 + 4: return FN<8, 4, MX>(__VA_ARGS__);                                               \
+    default: return (int)hipErrorInvalidValue;                                                      \
+  }
+
+int launch_split_rows(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
+                      size_t lds) {
+  if (n_blocks <= 0) return 0;
+  const size_t bytes = lds ? lds : rows_lds(a.J, a.R).bytes;
+  if (a.mixed) {
+    DASH_RW_JW_SWITCH(launch_rows_t, true, args, map, n_blocks, bytes, s)
+  } else {
+    DASH_RW_JW_SWITCH(launch_rows_t, false, args, map, n_blocks, bytes, s)
+  }
+}
+
+int launch_split_rows_slow(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks,
+                           hipStream_t s, size_t lds) {
+  if (n_blocks <= 0) return 0;
+  // the deferred slices (Lemma 1's pseudo-inverse form): one instantiation for
+  // every shape; its workgroups leave at once when nothing was deferred
+  const size_t bytes = lds ? lds : rows_lds(a.J, a.R).bytes;
+  if (a.mixed) {
+    if (int e = allow_lds_s(k_rows<8, 4, true, true>, bytes)) return e;
+    hipLaunchKernelGGL((k_rows<8, 4, true, true>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  } else {
+    if (int e = allow_lds_s(k_rows<8, 4, false, true>, bytes)) return e;
+    hipLaunchKernelGGL((k_rows<8, 4, false, true>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  }
+  return (int)hipGetLastError();
+}
+
+int split_rows_blocks_per_cu(int J, int R, int mixed) {
+  PassArgs a{};
+  a.J = J;
+  a.R = R;
+  if (mixed) {
+    DASH_RW_JW_SWITCH(rows_occupancy_t, true, J, R)
+  } else {
+    DASH_RW_JW_SWITCH(rows_occupancy_t, false, J, R)
+  }
+}
+
+template <int RM>
+static int launch_solve_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes, hipStream_t s) {
+  if (int e = allow_lds_s(k_solve<RM>, bytes)) return e;
+  hipLaunchKernelGGL((k_solve<RM>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  return (int)hipGetLastError();
+}
+
+int launch_split_solve(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
+                       size_t lds) {
+  if (n_blocks <= 0) return 0;
+  const size_t bytes = lds ? lds : solve_lds(a.J, a.R).bytes;
+  switch (rm_bucket(a.R)) {
+    case 8: return launch_solve_t<8>(args, map, n_blocks, bytes, s);
+    case 16: return launch_solve_t<16>(args, map, n_blocks, bytes, s);
+    default: return launch_solve_t<32>(args, map, n_blocks, bytes, s);
+  }
+}
+
+template <int EPT>
+static int launch_fsum_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes, hipStream_t s) {
+  hipLaunchKernelGGL((k_fsum<EPT>), dim3(n_blocks), dim3(kFsumThreads), bytes, s, args, map);
+  return (int)hipGetLastError();
+}
+
+int launch_split_fsum(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
+                      size_t lds) {
+  if (n_blocks <= 0) return 0;
+  const size_t bytes = lds ? lds : split_fsum_lds(a.J, a.R, a.lagged && a.mode == 0);
+  if (a.lagged && a.mode == 0) {
+    if (a.mixed) {
+      DASH_RW_JW_SWITCH(launch_fsum_rows_t, true, args, map, n_blocks, bytes, s)
+    } else {
+      DASH_RW_JW_SWITCH(launch_fsum_rows_t, false, args, map, n_blocks, bytes, s)
+    }
+  }
+  switch (ept_bucket(a.ys)) {
+    case 1: return launch_fsum_t<1>(args, map, n_blocks, bytes, s);
+    case 2: return launch_fsum_t<2>(args, map, n_blocks, bytes, s);
+    default: return launch_fsum_t<4>(args, map, n_blocks, bytes, s);
+  }
+}
+
+#undef DASH_RW_JW_SWITCH
+
+}  // namespace dash

@@ -32,7 +32,9 @@ class DashConfig(C.Structure):
 
 class UpdateReport(C.Structure):
     _fields_ = [("step", C.c_int64), ("rows", C.c_int64), ("K", C.c_int32), ("committed", C.c_int32),
-                ("fit", C.c_double), ("loss", C.c_double), ("sum_n", C.c_double), ("device_us", C.c_double)]
+                ("fit", C.c_double), ("loss", C.c_double), ("sum_n", C.c_double), ("device_us", C.c_double),
+                ("te", C.c_double), ("te_threshold", C.c_double), ("te_anomaly", C.c_int32),
+                ("n_anomalies", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -101,6 +103,8 @@ _SIGS = {
     "dash_last_error": (C.c_char_p, [_P]),
     "dash_poll": (C.c_int, [_P, C.POINTER(UpdateReport), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_footprint": (C.c_int, [C.POINTER(DashConfig), C.POINTER(C.c_int64)]),
+    "dash_anomaly": (C.c_int, [_P, C.c_int32]),
+    "dash_get_slice_errors": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.POINTER(C.c_int32)]),
     "dash_spans": (C.c_int, [_P, C.c_int32]),
     "dash_graph": (C.c_int, [_P, C.c_int32]),
     "dash_autotune": (C.c_int, [_P, C.c_int32]),
@@ -134,7 +138,8 @@ def lib():
 
 
 def make_config(J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20, max_groups=65536,
-                max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10, device=0, precision=PREC_FP32):
+                max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10, device=0, precision=PREC_FP32,
+                stats_mode=STATS_EXACT):
     cfg = DashConfig()
     lib().dash_config_default(C.byref(cfg), J, R)
     cfg.lam = lam
@@ -146,6 +151,7 @@ def make_config(J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20, max
     cfg.init_max_iter = init_max_iter
     cfg.init_tol = init_tol
     cfg.precision = precision
+    cfg.stats_mode = stats_mode
     cfg.device = device
     return cfg
 
@@ -185,7 +191,7 @@ class Dash:
 
     def __init__(self, J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20,
                  max_groups=65536, max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10,
-                 device=0, stream=None, precision=PREC_FP32, _handle=None):
+                 device=0, stream=None, precision=PREC_FP32, stats_mode=STATS_EXACT, _handle=None):
         if _handle is not None:   # a context owned by a DashServer
             self._h, self._owned = _handle, False
             self.J, self.R, self.device = J, R, device
@@ -193,7 +199,7 @@ class Dash:
             return
         self._owned = True
         cfg = make_config(J, R, lam, n_iter, max_slices, max_rows, max_groups, max_init_rows, init_max_iter,
-                          init_tol, device, precision)
+                          init_tol, device, precision, stats_mode)
         import torch
         L = lib()
         if stream is None:
@@ -338,6 +344,21 @@ class Dash:
         K = W.shape[0]
         assert Y.shape == (K, self.R, self.J) and D.shape == (K, self.R, self.R) and n.shape == (K,)
         self._check(lib().dash_set_state(self._h, K, _ptr(V), _ptr(W), _ptr(Y), _ptr(D), _ptr(n)), "dash_set_state")
+
+    def anomaly(self, window=5):
+        """Score every later update (slice-level se_k, tensor-level te, moving
+        thresholds over `window` previous scores); 0 turns the scores off."""
+        self._check(lib().dash_anomaly(self._h, int(window)), "dash_anomaly")
+
+    def slice_errors(self, cap=1 << 20):
+        """(slice ids, se, flags) of the last scored update, ascending slice id."""
+        sid = np.empty(cap, np.int32)
+        se = np.empty(cap, np.float32)
+        fl = np.empty(cap, np.int32)
+        n = C.c_int32()
+        self._check(lib().dash_get_slice_errors(self._h, _ptr(sid), _ptr(se), _ptr(fl), cap, C.byref(n)),
+                    "dash_get_slice_errors")
+        return sid[: n.value].copy(), se[: n.value].copy(), fl[: n.value].copy()
 
     def profile(self, every=1):
         """Time the launches of every `every`-th update (0 or False: stop)."""

@@ -3,22 +3,20 @@ FP64 oracle.
 
 Teacher-forced tests start the library and the oracle from the same state
 (dash_set_state with the oracle's state) and compare one update element by
-element.  Tolerances follow from float32 arithmetic on the GPU:
-
-  * U_new, Y_k, D_k, n_k: normwise relative error <= 2e-6 (products of length
-    J <= 256 and R <= 32 in float32: ~sqrt(J) * 2^-24 ~ 1e-6 worst case);
-  * W and V pass through R x R solves: the bound is scaled by the condition
-    number of the systems, capped at 1e-4;
-  * fit: the loss is a difference of terms of size sum_n, so a relative
-    state error e (the largest of those of Y, D, n) moves ell = loss / sum_n
-    by about 4 e and fit = 1 - sqrt(ell) by 4 e / (2 sqrt(ell)); the bound is
-    1e-6 + 4 e / (1 - fit).
+element: every element of U_new, Y_k, D_k, n_k, W and V, and the fit, against
+its a-priori float32 bound (tests/_bounds.py: the sums of |a||b| of the
+element's products times the unit roundoff and the product length, carried
+through Lemma 2's and Lemma 3's systems componentwise, so the condition of
+each system enters the bound of its solution).  Tests with several ALS
+passes per update, or free-running streams, compare normwise: U_new, Y_k,
+D_k <= 2e-6, n_k <= 1e-6, W and V <= 1e-5.
 """
 import numpy as np
 import pytest
 
 from oracle.dash_oracle import DashOracle
 from paper_2305_18376_amd.synth import make_workload
+from tests._bounds import assert_within, update_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -60,11 +58,49 @@ def oracle_u(r):
     return np.concatenate(parts) if parts else np.zeros((0, 1))
 
 
-def check_step(g, o, r, rep, tol_w=1e-4, tag=""):
+def per_slice(groups, news, r, K_old):
+    """{slice: X_new}, {slice: U_new} of an update (rows of a slice concatenated
+    in ingest order: its new-slice block first, then its groups)."""
+    xs, us = {}, {}
+    for l, (X, U) in enumerate(zip(news, r.U_new_slices)):
+        xs.setdefault(K_old + l, []).append(np.asarray(X, np.float64))
+        us.setdefault(K_old + l, []).append(U)
+    for (k, X), U in zip(groups, r.U_groups):
+        if X.shape[0]:
+            xs.setdefault(k, []).append(np.asarray(X, np.float64))
+            us.setdefault(k, []).append(U)
+    return ({k: np.concatenate(v) for k, v in xs.items()}, {k: np.concatenate(v) for k, v in us.items()})
+
+
+def check_step(g, o, r, rep, tol_w=1e-5, tag="", pre=None, groups=None, news=None):
     st = g.get_state()
     V, W, U = g.get_factors()
     U = U.cpu().numpy()
     ost = o.state()
+    if pre is not None and o.n_iter == 1:
+        # element by element against the a-priori bounds
+        K_old = pre["W"].shape[0]
+        xs, us = per_slice(groups or [], news or [], r, K_old)
+        bnd = update_bounds(pre, ost, o.lam, xs, us)
+        # U_new bound rows in ingest order: a slice's rows keep their order across groups
+        offs = {k: 0 for k in xs}
+        rows_b = []
+        for l, X in enumerate(news or []):
+            k = K_old + l
+            rows_b.append(bnd["U"][k][offs[k]:offs[k] + X.shape[0]])
+            offs[k] += X.shape[0]
+        for k, X in groups or []:
+            if X.shape[0]:
+                rows_b.append(bnd["U"][k][offs[k]:offs[k] + X.shape[0]])
+                offs[k] += X.shape[0]
+        worst = {"U": assert_within(f"{tag} U", U, oracle_u(r), np.concatenate(rows_b))}
+        for key in ("Y", "D", "n", "W", "V"):
+            worst[key] = assert_within(f"{tag} {key}", st[key], ost[key], bnd[key])
+        worst["fit"] = abs(rep["fit"] - r.fit) / bnd["fit"] if bnd["fit"] > 0 else 0.0
+        print(tag, "error/bound", {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+        assert rep["committed"] == 1
+        assert worst["fit"] <= 1.0, worst
+        return worst
     errs = {
         "U": relerr(U, oracle_u(r)),
         "Y": relerr(st["Y"], ost["Y"]),
@@ -141,7 +177,7 @@ def test_teacher_forced_update_shapes(J, R, n_iter):
         feed(g, groups, news, J)
         rep = g.update()
         r = o.update(groups, news)
-        check_step(g, o, r, rep, tag=f"J={J} R={R} step={s}")
+        check_step(g, o, r, rep, tag=f"J={J} R={R} step={s}", pre=ost, groups=groups, news=news)
 
 
 def test_free_run_tiny_workload_tracks_oracle():
@@ -184,7 +220,7 @@ def test_teacher_forced_mid_workload_reduced():
         feed(g, b.groups(), b.new_slices(), wl.J)
         rep = g.update()
         r = o.update(b.groups(), b.new_slices())
-        check_step(g, o, r, rep, tag=f"mid300 step={s}")
+        check_step(g, o, r, rep, tag=f"mid300 step={s}", pre=ost, groups=b.groups(), news=b.new_slices())
 
 
 def test_edge_cases_multi_group_new_slice_rows_and_small_blocks():
