@@ -212,7 +212,7 @@ def main():
     achieved = bytes_pass / (pass_ms / 1e3) / 1e9 if pass_ms > 0 else None
 
     sched = g.schedule()
-    kernel = "k_pass_wave" if sched["variant"] == 0 else "k_pass_block"
+    kernel = "k_pass_wave" if sched["variant"] == 0 else "k_rows"
     out = {
         "metric": METRIC,
         "value": value,
@@ -231,7 +231,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "note": "per-update device span, back-to-back updates"},
         "kernel_us_avg": {k: (1e3 * prof[k + "_ms"] / prof[k + "_launches"]) if prof[k + "_launches"] else None
-                          for k in ("pass", "solve", "upload")},
+                          for k in ("pass", "solve", "reduce", "commit", "upload")},
         "launch": "hip graph (node parameters rewritten per update)" if args.graph else "direct",
         "schedule": sched,
         "kernel_timing": f"HIP events around the launches of every {args.sample_every}-th update "

@@ -154,6 +154,7 @@ struct PassArgs {
   double *cst;         // lagged: [2][K_cap][R] stored c_k (buffer by cur)
   double *FG;          // lagged: [2][R*J + R*R] F^T then G (buffer by gcur)
   int defer_done;      // 1: the final phase leaves the report's done flag to the anomaly scores
+  int pre_reduced;     // 1: the group partials were summed into group 0 before the final phase
 };
 
 // Buffers of the anomaly scores (dash_anomaly): per touched slice of the last
@@ -179,6 +180,16 @@ struct BlockMap {
   int32_t local;
   int32_t pad;
 };
+
+// A kernel's view of its PassArgs in device memory: the constant address space
+// tells the compiler the fields never change during the launch, so it loads
+// each where it is used (scalar loads it may repeat) instead of holding a copy
+// of the whole block in registers.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) PassArgs CPassArgs;
+#else
+typedef const PassArgs CPassArgs;
+#endif
 
 // Kernel variants of the sweep: one fused launch with one wave per slice, or
 // the split sweep (row stage, solve stage, F stage, final phase).
@@ -246,6 +257,9 @@ int launch_split_fsum(const PassArgs &a, const PassArgs *args, const BlockMap *m
                       size_t lds = 0);
 int launch_finish_dev(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, int mode,
                       hipStream_t s, size_t lds = 0);
+// The group partials summed into group 0 (one thread per partial entry).
+int reduce_groups_blocks(int J, int R);
+int launch_reduce_groups(const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s);
 size_t split_rows_lds(int J, int R);
 size_t split_solve_lds(int J, int R);
 size_t split_fsum_lds(int J, int R, int lagged);

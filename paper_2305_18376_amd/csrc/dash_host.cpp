@@ -395,6 +395,7 @@ void write_pass_args(const dash_ctx *c, char *blk, const char *d, int mode) {
     a.mode = mode;
     a.pass = p;
     a.last_pass = (mode == 0 && p == n - 1) ? 1 : 0;
+    a.pre_reduced = 1;
     pa[p] = a;
   }
 }
@@ -416,6 +417,7 @@ dash_status enqueue_split_pass(dash_ctx *c, const PassArgs &a, const PassArgs *a
   HIP_OR_FAIL(c, prof_begin(c, kProfReduce));
   LAUNCH_OR_FAIL(c, launch_split_fsum(a, ad, nullptr, n_chunks, c->stream));
   HIP_OR_FAIL(c, prof_end(c));
+  LAUNCH_OR_FAIL(c, launch_reduce_groups(ad, nullptr, reduce_groups_blocks(c->J, c->R), c->stream));
   HIP_OR_FAIL(c, prof_begin(c, kProfCommit));
   LAUNCH_OR_FAIL(c, launch_finish_dev(a, ad, nullptr, 1, a.mode == 0 ? 0 : 2, c->stream));
   HIP_OR_FAIL(c, prof_end(c));
@@ -582,7 +584,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
     args[p].last_pass = (p == n_iter - 1) ? 1 : 0;
   }
   FetchArgs fa = fetch_args(c->hstage_dev[s], c->dstep[s], bytes, report);
-  const size_t per_pass = split ? 5 : (base.fuse ? 1 : 2);
+  const size_t per_pass = split ? 6 : (base.fuse ? 1 : 2);
   const size_t expect = 1 + (size_t)n_iter * per_pass;
   if (!c->gexec[s]) {
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -594,6 +596,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
         if (!e) e = launch_split_rows_slow(args[p], ad, nullptr, kSlowBlocks, c->stream);
         if (!e) e = launch_split_solve(args[p], ad, nullptr, n_chunks2, c->stream);
         if (!e) e = launch_split_fsum(args[p], ad, nullptr, nch, c->stream);
+        if (!e) e = launch_reduce_groups(ad, nullptr, reduce_groups_blocks(c->J, c->R), c->stream);
         if (!e) e = launch_finish_dev(args[p], ad, nullptr, 1, 0, c->stream);
       } else {
         e = launch_pass(args[p], c->sched.variant, nch, c->stream);
@@ -664,6 +667,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
         HIP_OR_FAIL(c, set(i++, (unsigned)kSlowBlocks, dargs));
         HIP_OR_FAIL(c, set(i++, (unsigned)n_chunks2, dargs));
         HIP_OR_FAIL(c, set(i++, (unsigned)nch, dargs));
+        HIP_OR_FAIL(c, set(i++, (unsigned)reduce_groups_blocks(c->J, c->R), dargs));
         HIP_OR_FAIL(c, set(i++, 1u, dfin));
       } else {
         HIP_OR_FAIL(c, set(i++, (unsigned)nch, pargs));

@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish_dev(const PassArgs *a
   extern __shared__ __align__(16) unsigned char smem[];
   const PassArgs a = map ? *map[blockIdx.x].args : *args;
   const StepHeader *h = a.hdr;
-  finish_pass<RM>(a, h, mode == 1 ? 0 : h->n_rgroups, mode, smem, finish_launch_lds(a.J, a.R));
+  const int ng = mode == 1 ? 0 : (a.pre_reduced ? 1 : h->n_rgroups);
+  finish_pass<RM>(a, h, ng, mode, smem, finish_launch_lds(a.J, a.R));
 }
 
 // ---------------------------------------------------------------------------

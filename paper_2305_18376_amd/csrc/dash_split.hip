@@ -61,6 +61,9 @@ __host__ __device__ inline RowsLds rows_lds(int J, int R) {
   const size_t scr = (size_t)(2 * R * R + R + 64) * 8 + 64 * 4;
   xb = std::max(xb, scr);
   xb = std::max(xb, (size_t)R * J * 4);
+  // the waves' c_k partials after the fold: 4 waves x RW ranks x 64 lanes
+  // (RW = 8: the deferred-slice kernel is the RW = 8 instantiation for every R)
+  xb = std::max(xb, (size_t)4 * 8 * 64 * 8);
   o = align_up(o + xb, 16);
   L.oU = o;
   o = align_up(o + (size_t)L.MB * (R + 1) * 4, 16);
@@ -83,9 +86,11 @@ __host__ __device__ inline RowsLds rows_lds(int J, int R) {
 template <int RW, int JW, bool MX, bool SLOW>
 __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
   const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  const int nblk = map ? map[blockIdx.x].pad : (int)gridDim.x;   // this context's workgroups
   __shared__ int sItem, sDefer;
+  __shared__ int sNext[5];   // the next slice: item index, slice, g0, g1, rows
   __shared__ double sDn[4];
   const StepHeader *h = a.hdr;
   const int J = a.J, R = a.R, RR = R * R;
@@ -122,14 +127,34 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
   const double pivl = lane < R ? vb.piv[lane] : 0.0;
   const double arrl = lane < R ? vb.VtV[lane * R + lane] : 0.0;
 
+  // the fast kernel takes the items blk, blk + nblk, ... (heaviest first, so
+  // the static stride balances like a greedy list schedule) and reads each
+  // next item while the current one is processed
+  if (!SLOW && threadIdx.x == 0) {
+    sNext[0] = blk;
+    if (blk < n_items) {
+      const Item x = a.items[blk];
+      sNext[1] = x.slice;
+      sNext[2] = x.g0;
+      sNext[3] = x.g1;
+      sNext[4] = x.rows;
+    }
+  }
   for (;;) {
     __syncthreads();   // the previous slice is done with LDS and sItem
     if (threadIdx.x == 0) {
       if (SLOW) {
         const int q = atomicAdd(&a.queue[2], 1);
         sItem = (q < __atomic_load_n(&a.queue[1], __ATOMIC_RELAXED)) ? a.slow_list[q] : n_items;
+        if (sItem < n_items) {
+          const Item x = a.items[sItem];
+          sNext[1] = x.slice;
+          sNext[2] = x.g0;
+          sNext[3] = x.g1;
+          sNext[4] = x.rows;
+        }
       } else {
-        sItem = atomicAdd(&a.queue[0], 1);
+        sItem = sNext[0];
       }
     }
     __syncthreads();
@@ -141,8 +166,16 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const Item item = a.items[it];
+    Item item;
+    item.slice = sNext[1];
+    item.g0 = sNext[2];
+    item.g1 = sNext[3];
+    item.rows = sNext[4];
     const int k = item.slice;
+    // the next item's descriptor, in flight during this slice (thread 0)
+    Item nx{0, 0, 0, 0};
+    const int it_next = it + nblk;
+    if (!SLOW && tid == 0 && it_next < n_items) nx = a.items[it_next];
     const bool is_new = k >= Kp;
     const int b = a.cur[(int64_t)gcur * a.K_cap + k];
     const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
@@ -189,7 +222,16 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       }
     }
     __syncthreads();
-    if (!SLOW && sDefer) continue;
+    if (!SLOW && sDefer) {
+      if (tid == 0) {
+        sNext[0] = it_next;
+        sNext[1] = nx.slice;
+        sNext[2] = nx.g0;
+        sNext[3] = nx.g1;
+        sNext[4] = nx.rows;
+      }
+      continue;
+    }
     if constexpr (!MX) load_state();
     constexpr bool slow = SLOW;
     if (slow) {
@@ -343,10 +385,27 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
         cpart[rr] = fma(cv, (double)vt[rr][jj], cpart[rr]);
       }
     }
+    // c_r: each wave sums its ranks' partials across lanes through LDS (the
+    // row block, dead after the fold): lanes 8 rr .. 8 rr + 7 add eight
+    // partials each, then three exchanges
+    __syncthreads();
+    double *sCp = (double *)sX + wv * (RW * 64);
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) sCp[rr * 64 + lane] = cpart[rr];
+    wave_sync();
+    double csum = 0.0;
+    if (lane < RW * 8) {
+      const double *src = sCp + (lane >> 3) * 64 + (lane & 7) * 8;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) csum += src[u];
+    }
+    csum += __shfl_xor(csum, 1, 64);
+    csum += __shfl_xor(csum, 2, 64);
+    csum += __shfl_xor(csum, 4, 64);
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr) {
       const int r = wv + 4 * rr;
-      const double part = wave_sum(cpart[rr]);
+      const double part = __shfl(csum, rr * 8, 64);
       if (lane == 0 && r < R) {
         if (a.lagged) {
           // eq. [obtain_CandC]: the stored c_k decayed, plus diag(U^T X V)
@@ -378,6 +437,13 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       const double nold = is_new ? 0.0 : a.n[(int64_t)b * a.K_cap + k];
       a.n[(int64_t)(1 - b) * a.K_cap + k] = s_old * nold + (((sDn[0] + sDn[1]) + sDn[2]) + sDn[3]);
       a.tag[k] = seq;
+      if (!SLOW) {
+        sNext[0] = it_next;
+        sNext[1] = nx.slice;
+        sNext[2] = nx.g0;
+        sNext[3] = nx.g1;
+        sNext[4] = nx.rows;
+      }
     }
   }
 }
@@ -386,69 +452,71 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
 // Solve stage
 // ---------------------------------------------------------------------------
 struct SolveLds {
-  size_t oVtV, oWv, oVt, oScr, oComb, bytes;
+  size_t oVtV, oVt, oC, oInfo, oScr, bytes;
 };
 
-// V^T V (FP64), the waves' weights, the waves' G / sum-n slots (4 x (R^2 + 1),
-// accumulated in place), V^T (float, R x J) and the shared pseudo-inverse scratch.
+// V^T V (FP64), V^T (float, R x J), the waves' c_k (4 x R), the waves' slices
+// for the G sums (4 x (R + 4): w_k, sigma_k, D_k, its compensation, n_k), and
+// the shared pseudo-inverse scratch.
 __host__ __device__ inline SolveLds solve_lds(int J, int R) {
   SolveLds L;
   size_t o = 0;
   L.oVtV = o;
   o += (size_t)R * R * 8;
-  L.oWv = o;
-  o += (size_t)4 * R * 8;
-  L.oComb = o;
-  o += (size_t)4 * (R * R + 1) * 8;
-  o = align_up(o, 16);
   L.oVt = o;
   o = align_up(o + (size_t)R * J * 4, 16);
+  L.oC = o;
+  o += (size_t)4 * R * 8;
+  L.oInfo = o;
+  o += (size_t)4 * (R + 4) * 8;
   L.oScr = o;
   o += (size_t)(2 * R * R + R + 3 * 64) * 8 + 64 * 4;
   L.bytes = align_up(o, 16);
   return L;
 }
 
-// c_r = sum_j Y_k[r][j] V[j][r] of one slice by one wave: lane l takes the
-// columns j = l + 64 jj, four ranks at a time, FP64 sums; lane r returns c_r.
-__device__ inline double slice_c(const float *__restrict__ Yk, const float *sVt, int J, int R) {
+// c_r = sum_j Y_k[r][j] V[j][r] of one slice by one wave, FP64 sums of the
+// float products.  Eight ranks at a time: lane l takes rank r0 + l / 8 and the
+// columns j = l mod 8 + 8 t; the eight lanes of a rank add their partials
+// with three exchanges, and the sums go to sc[r] (LDS, this wave's).
+__device__ inline void slice_c(const float *__restrict__ Yk, const float *sVt, int J, int R, double *sc) {
   const int lane = threadIdx.x & 63;
-  double c = 0.0;
-  for (int r0 = 0; r0 < R; r0 += 4) {
-    float y[4][4];
+  const int q = lane >> 3, c8 = lane & 7;
+  for (int r0 = 0; r0 < R; r0 += 8) {
+    const int r = r0 + q;
+    double p = 0.0;
+    if (r < R) {
+      const float *yr = Yk + r * J;
+      const float *vr = sVt + r * J;
+      int j = c8;
+      for (; j + 56 < J; j += 64) {
+        float y[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int u = 0; u < 8; ++u) y[u] = yr[j + 8 * u];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int r = r0 + i, j = lane + 64 * jj;
-        y[i][jj] = (r < R && j < J) ? Yk[r * J + j] : 0.f;
+        for (int u = 0; u < 8; ++u) p = fma((double)y[u], (double)vr[j + 8 * u], p);
       }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double p = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int r = r0 + i, j = lane + 64 * jj;
-        if (r < R && j < J) p = fma((double)y[i][jj], (double)sVt[r * J + j], p);
-      }
-      p = wave_sum(p);
-      if (lane == r0 + i) c = p;
+      for (; j < J; j += 8) p = fma((double)yr[j], (double)vr[j], p);
     }
+    p += __shfl_xor(p, 1, 64);
+    p += __shfl_xor(p, 2, 64);
+    p += __shfl_xor(p, 4, 64);
+    if (c8 == 0 && r < R) sc[r] = p;
   }
-  return c;
+  wave_sync();
 }
 
 // mode 0 (update pass) or 1 (evaluation of the committed state: w_k is the
 // committed W, no solve; in lagged mode c_k = diag(Y_k V) is stored as the
 // recursion's starting value).  Workgroup = one solve chunk, 4 waves, one
-// slice per wave per round.
+// slice per wave per round; after each round the whole workgroup adds the
+// round's G terms, slice by slice in wave order.
 template <int RM>
 __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const PassArgs a = map ? *map[blockIdx.x].args : *args;
-  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
   __shared__ int sFail[4];
-  constexpr int NQ = (RM * RM + 63) / 64;
+  CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
+  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
   const StepHeader *h = a.hdr;
   const int J = a.J, R = a.R, RR = R * R;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -461,28 +529,30 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
   const VBundleView vb = vb_view(a.vb + (int64_t)(upd ? win : gcur) * a.vb_stride, J, R);
   const SolveLds L = solve_lds(J, R);
   double *sVtV = (double *)(smem + L.oVtV);
-  double *sWv = (double *)(smem + L.oWv);
   float *sVt = (float *)(smem + L.oVt);
+  double *sC = (double *)(smem + L.oC) + wv * R;           // this wave's c_k
+  double *sInfo = (double *)(smem + L.oInfo);               // [4][R + 4]
   double *sM = (double *)(smem + L.oScr);
   double *sZ = sM + RR;
   double *sx = sZ + RR;
   double *sTmp = sx + R;
   double *sRot = sTmp + 64;
   int *sPair = (int *)(sRot + 128);
-  double *sComb = (double *)(smem + L.oComb);
   const int chunk2 = blk;
   const int k0 = chunk2 * h->chunk2;
   const int k1 = min(K, k0 + h->chunk2);
-  // the row stage has finished: its work counter is free for the next launch
+  // the row stage has finished: its counters are free for the next launch
   if (upd && chunk2 == 0 && tid < 3) a.queue[tid] = 0;
   const bool need_c = upd ? !a.lagged : (a.lagged != 0);
   for (int e = tid; e < RR; e += 256) sVtV[e] = vb.VtV[e];
-  for (int e = tid; e < 4 * (RR + 1); e += 256) sComb[e] = 0.0;
   if (need_c)
     for (int e = tid; e < R * J; e += 256) sVt[e] = vb.Vt32[e];
   __syncthreads();
 
-  double *gslot = sComb + wv * (RR + 1);   // this wave's G and sum n
+  constexpr int NG = (RM * RM + 255) / 256;   // G entries per thread
+  double gacc[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) gacc[i] = 0.0;
   double nacc = 0.0;
   const bool do_g = !a.lagged || !upd;
 
@@ -490,7 +560,7 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
     const int k = base + wv;
     const bool valid = k < k1;
     bool ok = true;
-    double w = 0.0, c = 0.0, sig = 0.0;
+    double w = 0.0, sig = 0.0, c = 0.0;
     int b = 0, tl = 0;
     bool touched = false;
     const float *Dp = nullptr, *Dcp = nullptr;
@@ -502,12 +572,14 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
       sig = touched ? 1.0 : exp2((double)(step - tl) * a.log2_lambda);
       Dp = a.D + ((int64_t)bs * a.K_cap + k) * RR;
       Dcp = a.Dc ? a.Dc + ((int64_t)bs * a.K_cap + k) * RR : nullptr;
-      if (lane == 0) nacc = fma(sig, a.n[(int64_t)bs * a.K_cap + k], nacc);
       const float *Yk = a.Y + ((int64_t)b * a.K_cap + k) * a.ys;
       if (upd) {
         if (touched) c = lane < R ? a.cbuf[(int64_t)k * R + lane] : 0.0;
         else if (a.lagged) c = lane < R ? a.cst[((int64_t)b * a.K_cap + k) * R + lane] : 0.0;
-        else c = slice_c(Yk, sVt, J, R);
+        else {
+          slice_c(Yk, sVt, J, R, sC);
+          c = lane < R ? sC[lane] : 0.0;
+        }
         // Lemma 2: (V^T V * D_k) w = c, Gauss-Jordan in registers (lane r holds row r)
         double m[RM];
 #pragma unroll
@@ -521,8 +593,8 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
         w = (ok && lane < R) ? rhs[0] / dpiv : 0.0;
       } else {
         if (a.lagged) {
-          c = slice_c(Yk, sVt, J, R);
-          if (lane < R) a.cst[((int64_t)b * a.K_cap + k) * R + lane] = c;
+          slice_c(Yk, sVt, J, R, sC);
+          if (lane < R) a.cst[((int64_t)b * a.K_cap + k) * R + lane] = sC[lane];
         }
         w = lane < R ? a.W[((int64_t)gcur * a.K_cap + k) * R + lane] : 0.0;
       }
@@ -543,6 +615,8 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
       }
       __syncthreads();
     }
+    // this wave's slice for the round's G terms: w_k, sigma_k, D_k, n_k
+    double *info = sInfo + wv * (R + 4);
     if (valid) {
       if (upd) {
         if (lane < R) a.W[((int64_t)wout * a.K_cap + k) * R + lane] = w;
@@ -551,30 +625,47 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
           a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = touched ? (int32_t)step : tl;
         }
       }
+      if (lane < R) info[lane] = w;
+      if (lane == 0) {
+        info[R] = sig;
+        info[R + 1] = __longlong_as_double((long long)(intptr_t)Dp);
+        info[R + 2] = __longlong_as_double((long long)(intptr_t)Dcp);
+        info[R + 3] = fma(sig, a.n[(int64_t)(touched ? 1 - b : b) * a.K_cap + k], 0.0);
+      }
+    } else if (lane == 0) {
+      info[R] = 0.0;
+      info[R + 1] = __longlong_as_double(0LL);
+    }
+    __syncthreads();
+    // G += sigma_k diag(w_k) D_k diag(w_k) and sum n, slice by slice in wave order
+    for (int v = 0; v < 4; ++v) {
+      const double *iv = sInfo + v * (R + 4);
+      const float *Dv = (const float *)(intptr_t)__double_as_longlong(iv[R + 1]);
+      if (!Dv) continue;
+      const float *Dcv = (const float *)(intptr_t)__double_as_longlong(iv[R + 2]);
+      const double sv = iv[R];
       if (do_g) {
-        // G += sigma_k diag(w_k) D_k diag(w_k)
-        double *ww = sWv + wv * R;
-        if (lane < R) ww[lane] = w;
-        wave_sync();
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-          const int q = lane + 64 * i;
+        for (int i = 0; i < NG; ++i) {
+          const int q = tid + 256 * i;
           if (q < RR) {
-            const int r = q / R, s = q - r * R;
-            const double d = (double)Dp[q] + (Dcp ? (double)Dcp[q] : 0.0);
-            gslot[q] = fma(sig * ww[r] * ww[s], d, gslot[q]);
+            const int r = q / R, s2 = q - r * R;
+            const double d = (double)Dv[q] + (Dcv ? (double)Dcv[q] : 0.0);
+            gacc[i] = fma(sv * iv[r] * iv[s2], d, gacc[i]);
           }
         }
-        wave_sync();
       }
+      if (tid == 0) nacc += iv[R + 3];
     }
+    __syncthreads();
   }
-  // the waves' partials added in wave order
-  if (lane == 0) gslot[RR] = nacc;
-  __syncthreads();
   double *p2 = a.part2 + (int64_t)chunk2 * (RR + 1);
-  for (int e = tid; e <= RR; e += 256)
-    p2[e] = ((sComb[e] + sComb[(RR + 1) + e]) + sComb[2 * (RR + 1) + e]) + sComb[3 * (RR + 1) + e];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int q = tid + 256 * i;
+    if (q < RR) p2[q] = gacc[i];
+  }
+  if (tid == 0) p2[RR] = nacc;
 }
 
 // ---------------------------------------------------------------------------
@@ -598,7 +689,7 @@ __host__ __device__ inline int fsum_tps(int ys) {
 template <int EPT>
 __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
   const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
   const int tps = fsum_tps(a.ys);
   __shared__ int sflag;
@@ -618,16 +709,17 @@ __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, 
   double *sw = (double *)smem;   // [kFsumBatch][R]: sigma_k w_k
   const int spi = kFsumThreads / tps, sg = tid / tps, tq = tid - sg * tps;
   const int nq = a.ys >> 2;
-  // the row of each of this thread's floats (the 4 of a float4 can straddle
-  // two rows, or more when J < 4)
-  int rr[EPT][4];
+  // the rows of this thread's floats: float4 e starts in row r0[e]; its
+  // floats from index brk[e] on lie in the next row (J >= 4; with J < 4 the
+  // row of every float is computed where it is used)
+  int r0[EPT], brk[EPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int el = 4 * (tq + tps * e) + c;
-      rr[e][c] = (el < RJ) ? el / J : -1;
-    }
+  for (int e = 0; e < EPT; ++e) {
+    const int el = 4 * (tq + tps * e);
+    r0[e] = el / J;
+    brk[e] = (r0[e] + 1) * J - el;
+  }
+  const bool narrow = J < 4;
   double acc[EPT][4];
 #pragma unroll
   for (int e = 0; e < EPT; ++e)
@@ -647,6 +739,7 @@ __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, 
     __syncthreads();
     // two slices per thread group in flight where the registers allow it
     constexpr int NS = EPT <= 2 ? 2 : 1;
+#pragma unroll 1
     for (int i = sg; i < nb; i += NS * spi) {
       const int i2 = i + spi;
       const bool two = NS == 2 && i2 < nb;
@@ -664,12 +757,29 @@ __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, 
       for (int e = 0; e < EPT; ++e) {
         const float a1[4] = {v1[e].x, v1[e].y, v1[e].z, v1[e].w};
         const float a2[4] = {v2[e].x, v2[e].y, v2[e].z, v2[e].w};
+        const int el = 4 * (tq + tps * e);
+        if (el >= RJ) continue;
+        if (!narrow) {
+          // the float4's two possible rows: r0 (and r0 + 1 from brk on)
+          const int ra = r0[e], rb = min(ra + 1, R - 1);
+          const double wa1 = w1[ra], wb1 = w1[rb];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int r = rr[e][c];
-          if (r >= 0) {
-            acc[e][c] = fma(w1[r], (double)a1[c], acc[e][c]);
-            if (two) acc[e][c] = fma(w2[r], (double)a2[c], acc[e][c]);
+          for (int c = 0; c < 4; ++c)
+            if (el + c < RJ) acc[e][c] = fma(c >= brk[e] ? wb1 : wa1, (double)a1[c], acc[e][c]);
+          if (two) {
+            const double wa2 = w2[ra], wb2 = w2[rb];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              if (el + c < RJ) acc[e][c] = fma(c >= brk[e] ? wb2 : wa2, (double)a2[c], acc[e][c]);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (el + c < RJ) {
+              const int r = (el + c) / J;
+              acc[e][c] = fma(w1[r], (double)a1[c], acc[e][c]);
+              if (two) acc[e][c] = fma(w2[r], (double)a2[c], acc[e][c]);
+            }
           }
         }
       }
@@ -710,6 +820,29 @@ __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, 
 }
 
 // ---------------------------------------------------------------------------
+// Second reduction level before the final phase: the group partials summed in
+// group order into group 0, one thread per entry, so the single-workgroup
+// final phase reads one partial.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce_groups(const PassArgs *args, const BlockMap *map) {
+  CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
+  const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  const int plen = partial_len(a.J, a.R);
+  const int e = blk * 256 + threadIdx.x;
+  if (e >= plen) return;
+  const int ng = a.hdr->n_rgroups;
+  a.gpart[e] = ordered_sum(a.gpart, plen, e, 0, ng);
+}
+
+int reduce_groups_blocks(int J, int R) { return (partial_len(J, R) + 255) / 256; }
+
+int launch_reduce_groups(const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s) {
+  if (n_blocks <= 0) return 0;
+  hipLaunchKernelGGL(k_reduce_groups, dim3(n_blocks), dim3(256), 0, s, args, map);
+  return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // F stage, lagged mode: the new rows' terms of eq. [obtain_FandF] and
 // [obtain_FandG], sum over touched slices of (U_k S_k)^T X_k and
 // S_k U_k^T U_k S_k with the pass's new S_k.  Workgroup c takes the items
@@ -718,7 +851,7 @@ __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, 
 template <int RW, int JW, bool MX>
 __global__ __launch_bounds__(256) void k_fsum_rows(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const PassArgs a = map ? *map[blockIdx.x].args : *args;
+  CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
   const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
   __shared__ int sflag;
   const StepHeader *h = a.hdr;

@@ -218,7 +218,8 @@ __device__ __forceinline__ double stage_rows(const float *__restrict__ src, int 
 // second ticket and returns true: it then runs the final phase.  Every ticket is
 // reset by the workgroup that drew the last number, so all are zero again when
 // the launch ends.
-__device__ bool arrive(const PassArgs &a, const StepHeader *h, int chunk, int *sflag) {
+template <typename A>
+__device__ bool arrive(const A &a, const StepHeader *h, int chunk, int *sflag) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int plen = partial_len(a.J, a.R);
   const int cpr = h->chunks_per_rgroup;
