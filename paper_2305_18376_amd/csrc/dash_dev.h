@@ -260,7 +260,7 @@ int launch_finish_dev(const PassArgs &a, const PassArgs *args, const BlockMap *m
 // The group partials summed into group 0 (one thread per partial entry).
 int reduce_groups_blocks(int J, int R);
 int launch_reduce_groups(const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s);
-size_t split_rows_lds(int J, int R);
+size_t split_rows_lds(int J, int R, int mixed);
 size_t split_solve_lds(int J, int R);
 size_t split_fsum_lds(int J, int R, int lagged);
 size_t finish_dev_lds(int J, int R);

@@ -77,6 +77,115 @@ __host__ __device__ inline RowsLds rows_lds(int J, int R) {
   return L;
 }
 
+// Row-stage layout of the mixed-precision path: the new rows staged once as
+// BF16 in two layouts -- Xr row-major (stride XS) for U^T = P^T X^T and Xc
+// column-major (stride XC) for dY = U^T X -- with P^T (Pt, stride XS) and U^T
+// (Ut, stride XC) in BF16 as well, so that every MFMA operand (eight
+// consecutive k per lane) is one 16-byte LDS read.  Columns are padded to
+// Jp = 32 * ceil(J / 32) (the k steps of P^T X^T), ranks to 16 * ceil(R / 16).
+// The Xr + Xc region also takes the dY hand-off (R x J float) and the c_k
+// partials after the fold; dD gets a region of its own.
+struct RowsLdsBf {
+  int Jp, XS, XC, MB, R16, J16;
+  size_t oPt, oX, oXc, oUt, oDD, oW, oWinv, bytes;
+};
+
+__host__ __device__ inline RowsLdsBf rows_lds_bf(int J, int R) {
+  RowsLdsBf L;
+  L.Jp = (J + 31) / 32 * 32;
+  L.XS = L.Jp + 8;
+  L.MB = (J <= 128) ? 64 : 32;
+  L.XC = L.MB + 8;
+  L.R16 = (R + 15) / 16 * 16;
+  L.J16 = (J + 15) / 16 * 16;
+  size_t o = 0;
+  L.oPt = o;
+  o = align_up(o + (size_t)L.R16 * L.XS * 2, 16);
+  L.oX = o;
+  L.oXc = align_up(o + (size_t)L.MB * L.XS * 2, 16);
+  size_t xend = L.oXc + (size_t)L.J16 * L.XC * 2;
+  xend = std::max(xend, L.oX + (size_t)R * J * 4);
+  xend = std::max(xend, L.oX + (size_t)4 * 8 * 64 * 8);
+  o = align_up(xend, 16);
+  L.oUt = o;
+  o = align_up(o + (size_t)L.R16 * L.XC * 2, 16);
+  L.oDD = o;
+  o = align_up(o + (size_t)R * R * 4, 16);
+  L.oW = o;
+  o += (size_t)R * 8;
+  L.oWinv = o;
+  o += (size_t)R * 4;
+  L.bytes = align_up(o, 16);
+  return L;
+}
+
+// Stage m rows of J floats (HBM, row-major) into Xr and Xc as BF16, with rows
+// m .. mp - 1 and columns J .. Jp - 1 (Xr) / J .. J16 - 1 (Xc) zero; returns
+// this thread's sum of squares of the float values (FP64).
+__device__ inline double stage_rows_bf(const float *__restrict__ src, int m, int mp, int J, const RowsLdsBf &L,
+                                       __bf16 *Xr, __bf16 *Xc, int tid) {
+  double sq = 0.0;
+  const __bf16 z = (__bf16)0.f;
+  // padding
+  for (int e = tid; e < mp * (L.Jp - J); e += 256) {
+    const int row = e / (L.Jp - J);
+    Xr[row * L.XS + J + (e - row * (L.Jp - J))] = z;
+  }
+  for (int e = tid; e < (mp - m) * J; e += 256) {
+    const int row = m + e / J, col = e % J;
+    Xr[row * L.XS + col] = z;
+    Xc[col * L.XC + row] = z;
+  }
+  for (int e = tid; e < (L.J16 - J) * mp; e += 256) {
+    const int col = J + e / mp, row = e % mp;
+    Xc[col * L.XC + row] = z;
+  }
+  const int n = m * J;
+  if ((J & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    const int n4 = n >> 2;
+#pragma unroll 1
+    for (int q0 = tid; q0 < n4; q0 += 4 * 256) {
+      float4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = q0 + 256 * i;
+        v[i] = (q < n4) ? reinterpret_cast<const float4 *>(src)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = q0 + 256 * i;
+        if (q < n4) {
+          const int e = 4 * q, row = e / J, col = e - row * J;
+          const __bf16 b0 = (__bf16)v[i].x, b1 = (__bf16)v[i].y, b2 = (__bf16)v[i].z, b3 = (__bf16)v[i].w;
+          __bf16 *d = Xr + row * L.XS + col;
+          d[0] = b0;
+          d[1] = b1;
+          d[2] = b2;
+          d[3] = b3;
+          Xc[col * L.XC + row] = b0;
+          Xc[(col + 1) * L.XC + row] = b1;
+          Xc[(col + 2) * L.XC + row] = b2;
+          Xc[(col + 3) * L.XC + row] = b3;
+          sq = fma((double)v[i].x, (double)v[i].x, sq);
+          sq = fma((double)v[i].y, (double)v[i].y, sq);
+          sq = fma((double)v[i].z, (double)v[i].z, sq);
+          sq = fma((double)v[i].w, (double)v[i].w, sq);
+        }
+      }
+    }
+  } else {
+    for (int e = tid; e < n; e += 256) {
+      const float x = src[e];
+      const int row = e / J, col = e - row * J;
+      const __bf16 b = (__bf16)x;
+      Xr[row * L.XS + col] = b;
+      Xc[col * L.XC + row] = b;
+      sq = fma((double)x, (double)x, sq);
+    }
+  }
+  return sq;
+}
+
 // RW ranks x JW columns per thread in the [rank][column] layout: thread
 // (wave w, lane l) owns r = w + 4 rr (rr < RW) and j = l + 64 jj (jj < JW).
 // SLOW = false: the slices whose Lemma 1 system passes the acceptance rule;
@@ -100,20 +209,36 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
   const int gcur = a.ctl->gcur;
   const int win = (a.pass == 0) ? gcur : 1 - gcur;
   const VBundleView vb = vb_view(a.vb + (int64_t)win * a.vb_stride, J, R);
+  // the mixed path's fast kernel stages BF16 operands; the float32 path and
+  // the deferred-slice kernel keep float rows and Lemma 1's scratch
+  constexpr bool BF = MX && !SLOW;
   const RowsLds L = rows_lds(J, R);
+  const RowsLdsBf LB = rows_lds_bf(J, R);
   float *sP = (float *)(smem + L.oP);
-  float *sX = (float *)(smem + L.oX);
+  float *sX = BF ? (float *)(smem + LB.oX) : (float *)(smem + L.oX);
   double *sScr = (double *)(smem + L.oX);   // Lemma 1 pseudo-inverse scratch (before the rows)
   float *sU = (float *)(smem + L.oU);
   float *sZf = (float *)(smem + L.oZf);
-  double *sW = (double *)(smem + L.oW);
-  float *sWinv = (float *)(smem + L.oWinv);
-  const int XS = L.XS, MB = L.MB;
+  double *sW = BF ? (double *)(smem + LB.oW) : (double *)(smem + L.oW);
+  float *sWinv = BF ? (float *)(smem + LB.oWinv) : (float *)(smem + L.oWinv);
+  __bf16 *bPt = (__bf16 *)(smem + LB.oPt);
+  __bf16 *bXr = (__bf16 *)(smem + LB.oX);
+  __bf16 *bXc = (__bf16 *)(smem + LB.oXc);
+  __bf16 *bUt = (__bf16 *)(smem + LB.oUt);
+  const int XS = L.XS, MB = BF ? LB.MB : L.MB;
   const bool write_u = a.last_pass || a.lagged;
   if (a.stamp_start && blk == 0 && tid == 0 && a.pass == 0 && h->report)
     ((Report *)h->report)->t_start = __builtin_amdgcn_s_memrealtime();
 
-  for (int e = tid; e < J * R; e += 256) sP[e] = vb.P32[e];
+  if constexpr (BF) {
+    // P^T in BF16, ranks padded to a multiple of 16 and columns to Jp (zero)
+    for (int e = tid; e < LB.R16 * LB.Jp; e += 256) {
+      const int r = e / LB.Jp, j = e - r * LB.Jp;
+      bPt[r * LB.XS + j] = (__bf16)((r < R && j < J) ? vb.P32[j * R + r] : 0.f);
+    }
+  } else {
+    for (int e = tid; e < J * R; e += 256) sP[e] = vb.P32[e];
+  }
   // the entries of V^T this thread multiplies for c_k
   float vt[RW][JW];
 #pragma unroll
@@ -255,6 +380,58 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
         const int m = min(MB, gr.nrows - r0);
         const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
+        if constexpr (BF) {
+          __syncthreads();
+          dn += stage_rows_bf(gr.src + (int64_t)r0 * J, m, mp, J, LB, bXr, bXc, tid);
+          __syncthreads();
+          // U^T = P^T X^T per (row tile, rank tile) on BF16 MFMA: wave w takes
+          // jobs w and w + 4; u = (x P) / w into U^T (BF16) and U_new
+          const int jobs = (mp >> 4) * NTu;
+#pragma unroll
+          for (int jb = 0; jb < 2; ++jb) {
+            const int job = wv + 4 * jb;
+            if (job < jobs) {
+              const int rt = job / NTu, nt = job - rt * NTu;
+              const __bf16 *pa = bPt + (16 * nt + (lane & 15)) * LB.XS + 8 * (lane >> 4);
+              const __bf16 *pb = bXr + (16 * rt + (lane & 15)) * LB.XS + 8 * (lane >> 4);
+              f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+              for (int ks = 0; ks < LB.Jp; ks += 32)
+                acc = mfma_bf16(*(const bf16x8 *)(pa + ks), *(const bf16x8 *)(pb + ks), acc);
+              const int row = 16 * rt + (lane & 15);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int r = 16 * nt + (lane >> 4) * 4 + q;
+                const float u = (r < R && row < m) ? acc[q] * sWinv[min(r, R - 1)] : 0.f;
+                bUt[r * LB.XC + row] = (__bf16)u;
+                if (write_u && r < R && row < m) a.U_out[(gr.out_row + r0 + row) * R + r] = u;
+              }
+            }
+          }
+          __syncthreads();
+          // dY += U^T X, dD += U^T U: every operand eight consecutive rows
+          const int MT = NTu, NT = (J + 15) >> 4;
+          const int li = lane & 15, lk = 8 * (lane >> 4);
+          for (int ks = 0; ks < mp; ks += 32) {
+            bf16x8 au[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+              au[mt] = (mt < MT) ? *(const bf16x8 *)(bUt + (16 * mt + li) * LB.XC + ks + lk) : bf16x8{};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int nt = wv + 4 * c;
+              if (nt < NT) {
+                const bf16x8 bv = *(const bf16x8 *)(bXc + (16 * nt + li) * LB.XC + ks + lk);
+                accY[2 * c] = mfma_bf16(au[0], bv, accY[2 * c]);
+                if (MT > 1) accY[2 * c + 1] = mfma_bf16(au[1], bv, accY[2 * c + 1]);
+              }
+            }
+            if (wv < MT * MT) {
+              const int mt = wv / MT, st = wv - mt * MT;
+              accD = mfma_bf16(mt == 0 ? au[0] : au[1], st == 0 ? au[0] : au[1], accD);
+            }
+          }
+          continue;
+        }
         __syncthreads();
         dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
         for (int e = tid; e < (mp - m) * J; e += 256) {
@@ -324,7 +501,7 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     // hand the tiles to the [rank][column] layout through LDS
     __syncthreads();
     float *sDY = sX;   // R x J
-    float *sDD = sU;   // R x R
+    float *sDD = BF ? (float *)(smem + LB.oDD) : sU;   // R x R
     {
       const int li = lane & 15;
       const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
@@ -988,7 +1165,12 @@ int split_fsum_class(int J, int R, int lagged, int mixed) {
   return lagged ? 1000 + split_rows_class(J, R, mixed) : ept_bucket(y_stride(J, R));
 }
 
-size_t split_rows_lds(int J, int R) { return rows_lds(J, R).bytes; }
+// the fast row kernel's LDS: BF16-staged blocks in the mixed path
+static size_t rows_fast_lds(int J, int R, bool mixed) {
+  return mixed ? rows_lds_bf(J, R).bytes : rows_lds(J, R).bytes;
+}
+
+size_t split_rows_lds(int J, int R, int mixed) { return rows_fast_lds(J, R, mixed != 0); }
 size_t split_solve_lds(int J, int R) { return solve_lds(J, R).bytes; }
 size_t split_fsum_lds(int J, int R, int lagged) {
   if (lagged) return rows_lds(J, R).bytes;
@@ -1004,7 +1186,7 @@ static int launch_rows_t(const PassArgs *args, const BlockMap *map, int n_blocks
 
 template <int RW, int JW, bool MX>
 static int rows_occupancy_t(int J, int R) {
-  const size_t bytes = rows_lds(J, R).bytes;
+  const size_t bytes = rows_fast_lds(J, R, MX);
   if (allow_lds_s(k_rows<RW, JW, MX, false>, bytes)) return 1;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows<RW, JW, MX, false>, 256, bytes) != hipSuccess ||
@@ -1038,7 +1220,7 @@ static int launch_fsum_rows_t(const PassArgs *args, const BlockMap *map, int n_b
 int launch_split_rows(const PassArgs &a, const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s,
                       size_t lds) {
   if (n_blocks <= 0) return 0;
-  const size_t bytes = lds ? lds : rows_lds(a.J, a.R).bytes;
+  const size_t bytes = lds ? lds : rows_fast_lds(a.J, a.R, a.mixed != 0);
   if (a.mixed) {
     DASH_RW_JW_SWITCH(launch_rows_t, true, args, map, n_blocks, bytes, s)
   } else {
