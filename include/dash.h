@@ -72,7 +72,8 @@ typedef struct dash_config {
   int64_t max_groups_per_update; /* capacity in row groups staged for one update         */
   int64_t max_init_rows;     /* capacity of dash_init's initial tensor (rows)            */
   int32_t device;            /* HIP device ordinal                                       */
-  void *stream;              /* hipStream_t to enqueue on; NULL: the library makes one   */
+  void *stream;              /* hipStream_t to enqueue on; NULL: the library makes a
+                                blocking one (ordered after the null stream's work)     */
 } dash_config;
 
 typedef struct dash_ctx dash_ctx;
@@ -306,52 +307,105 @@ dash_status dash_get_slice_errors(dash_ctx *ctx, int32_t *slice, float *se, int3
 dash_status dash_footprint(const dash_config *cfg, int64_t *bytes);
 
 /* ---------------------------------------------------------------------------
- * Serving: many independent streams (one context each, each on a HIP stream
- * of its own) on one device.  Every stream is an irregular tensor of its own
- * with its own J, R and lambda (Problem 1 per stream); streams share nothing,
- * so a stream's results are bit for bit those it would have alone.
+ * Serving: many independent streams on one device.  Every stream is an
+ * irregular tensor of its own with its own J, R, lambda and precision
+ * (Problem 1 per stream), decomposed by a context of its own.  Clients submit
+ * rows at any time; a tick cuts one update per stream from the rows it has
+ * and runs the updates of all streams together, each stage of the update as
+ * one launch per kernel class over every stream.  A stream's workgroup counts
+ * and reduction order depend on the stream alone, so its results are bit for
+ * bit the same alone and in any mix.  Served streams always run the split
+ * sweep.  All server calls are thread-safe.
  * ------------------------------------------------------------------------- */
 typedef struct dash_server dash_server;
 
 typedef struct dash_server_report {
-  int32_t stream;      /* stream id                                              */
-  int32_t committed;   /* as dash_update_report.committed                       */
-  int64_t step;        /* the stream's update index                              */
-  int64_t rows;        /* rows the update consumed                               */
-  double fit;          /* the stream's fit after the update                      */
-  double latency_us;   /* host time from the tick that cut the update to the
-                          poll that saw it committed                             */
+  int32_t stream;        /* stream id                                            */
+  int32_t committed;     /* as dash_update_report.committed                     */
+  int64_t step;          /* the stream's update index                            */
+  int64_t rows;          /* rows the update consumed                             */
+  double fit;            /* the stream's fit after the update                    */
+  double latency_us;     /* host time from the submit of the update's first
+                            request to the moment the server saw it committed */
+  int64_t last_request;  /* the last request the update consumed: the device
+                            buffers of this stream's requests up to it are free */
+  double device_us;      /* device time of the update (its tick's span)          */
 } dash_server_report;
 
+typedef struct dash_server_stats {
+  int64_t ticks;         /* ticks launched                                        */
+  int64_t launches;      /* kernel launches of those ticks                       */
+  int64_t updates;       /* updates reported                                     */
+  int64_t rows;          /* rows of those updates                                */
+  int64_t budget, used;  /* device bytes: budget, admitted footprints            */
+  int32_t queued;        /* streams waiting for admission                        */
+  int32_t open;          /* admitted streams                                     */
+} dash_server_stats;
+
 /* A server on `device` whose streams may together allocate at most
- * budget_bytes of device memory.  Errors: DASH_E_INVALID_ARG,
- * DASH_E_OUT_OF_MEMORY. */
+ * budget_bytes of device memory.  Its HIP stream is a blocking one: ordered
+ * after work the caller put on the null stream.  Errors: DASH_E_INVALID_ARG,
+ * DASH_E_OUT_OF_MEMORY, DASH_E_DEVICE. */
 dash_status dash_server_create(int32_t device, int64_t budget_bytes, dash_server **out);
-/* Close every stream (waiting for their work) and free the server. */
+/* Stop the loop, wait for every update in flight, close every stream, free. */
 dash_status dash_server_destroy(dash_server *srv);
-/* Admit a stream: if its footprint (dash_footprint) fits the unused budget,
- * create its context (cfg->device and cfg->stream are replaced by the
- * server's) and return its id; otherwise DASH_E_CAPACITY and nothing changes
- * (retry once streams have closed).  Other errors as dash_create. */
-dash_status dash_server_open(dash_server *srv, const dash_config *cfg, int32_t *stream);
-/* Close a stream: wait for its work, free its context, return its budget. */
+/* Open a stream for cfg (device and stream fields are replaced by the
+ * server's).  If its footprint (dash_footprint) fits the unused budget and no
+ * stream is waiting, its context is created now (state 2, open).  Otherwise,
+ * with queue = 1 it waits in a FIFO admission queue (state 1) and is admitted
+ * when closes free enough budget; with queue = 0 DASH_E_CAPACITY is returned
+ * and nothing changes.  *stream receives its id either way.  A stream whose
+ * footprint exceeds the whole budget is refused.  Errors: as dash_create,
+ * DASH_E_CAPACITY. */
+dash_status dash_server_open(dash_server *srv, const dash_config *cfg, int32_t queue, int32_t *stream);
+/* *state: 0 closed or unknown, 1 waiting for admission, 2 open. */
+dash_status dash_server_state(dash_server *srv, int32_t stream, int32_t *state);
+/* Close a stream: its updates in flight finish and are reported, requests not
+ * yet in an update are dropped, its context is freed and its budget returned;
+ * waiting streams are admitted.  Errors: DASH_E_INVALID_ARG. */
 dash_status dash_server_close(dash_server *srv, int32_t stream);
-/* The context of a stream (dash_init*, dash_ingest_*, dash_get_* are called on
- * it directly; dash_update* / dash_wait / dash_poll are left to the server),
- * or NULL for an unknown or closed id. */
+/* The context of an open stream, or NULL.  The caller initialises it with
+ * dash_init* and reads it with dash_get_* (only while none of its requests is
+ * waiting or in flight, e.g. after dash_server_drain); dash_ingest_*,
+ * dash_update* and dash_poll/dash_wait are the server's. */
 dash_ctx *dash_server_context(dash_server *srv, int32_t stream);
-/* One scheduling tick: every open stream with staged rows gets one update
- * enqueued (all of them run concurrently); rows staged after the tick go to
- * the next one.  *launched (may be NULL) receives the count.  Returns the first
- * error of a stream (its message is in dash_last_error of its context); the
- * other streams are still served. */
+/* Submit rows to an open, initialised stream: n_groups row groups as
+ * dash_ingest_rows (host slice_id and row_ptr, device rows) and n_new new
+ * slices as dash_ingest_slices (host new_ptr, device new_rows); the groups may
+ * name the new slices, whose ids start at *first_new_id (may be NULL).  The
+ * host arrays are copied; the device buffers stay the caller's and must not
+ * change until an update of this stream reports last_request >= *request.
+ * producer: the HIP stream the rows were written on (the update waits for
+ * it), or NULL for the null stream.  Errors: DASH_E_INVALID_ARG,
+ * DASH_E_BAD_STATE (not open or not initialised), DASH_E_CAPACITY (more rows,
+ * groups or slices than the stream's configuration allows). */
+dash_status dash_server_submit(dash_server *srv, int32_t stream, int32_t n_groups, const int32_t *slice_id,
+                               const int64_t *row_ptr, const float *rows, int32_t n_new, const int64_t *new_ptr,
+                               const float *new_rows, void *producer, int64_t *request, int32_t *first_new_id);
+/* One tick on the calling thread: every open stream with submitted rows (and
+ * fewer than four updates in flight) gets one update of the requests that fit
+ * its per-update capacity.  *launched (may be NULL) receives the count. */
 dash_status dash_server_tick(dash_server *srv, int32_t *launched);
-/* Collect finished updates (wait = 0: those done now; wait = 1: everything in
- * flight) into out[0 .. *n), at most cap.  A stream whose update was rolled
- * back reports it with committed = 0 and loses the updates enqueued after it;
- * the first such status is returned. */
+/* Finished updates into out[0 .. *n), at most cap, in completion order.
+ * wait = 1 (no loop running): first wait for everything in flight.  A stream
+ * whose update was rolled back reports it and the updates after it with
+ * committed = 0; the first such status is returned. */
 dash_status dash_server_poll(dash_server *srv, int32_t wait, dash_server_report *out, int32_t cap,
                              int32_t *n);
+/* Run ticks and completion polling on a host thread of the server's own: a
+ * tick starts when rows are waiting, fewer than two ticks are in flight and
+ * tick_us microseconds have passed since the last one (0: at once).  Errors:
+ * DASH_E_BAD_STATE when already running. */
+dash_status dash_server_start(dash_server *srv, int32_t tick_us);
+/* Stop the loop thread (updates in flight continue; poll with wait = 1). */
+dash_status dash_server_stop(dash_server *srv);
+/* Wait until every submitted request is in a committed, collected update
+ * (reports stay for dash_server_poll).  timeout_ms < 0: no limit; on timeout
+ * DASH_E_BAD_STATE. */
+dash_status dash_server_drain(dash_server *srv, int32_t timeout_ms);
+dash_status dash_server_get_stats(dash_server *srv, dash_server_stats *out);
+/* Text of the server's last launch error ("" if none). */
+const char *dash_server_last_error(dash_server *srv);
 
 #ifdef __cplusplus
 }

@@ -282,6 +282,19 @@ struct FetchArgs {
   unsigned grid;
 };
 FetchArgs fetch_args(const char *src_mapped, char *dst, size_t bytes, void *report);
+// One copy of a batched fetch: src (device view of pinned host memory) to
+// dst, bytes a multiple of 16; report (or NULL) gets its start time.
+struct FetchJob {
+  const char *src;
+  char *dst;
+  int64_t bytes;
+  void *report;
+};
+// Copy every job of jobs[0 .. n_jobs) in one launch; jobs is itself read
+// through its device view (pinned host memory).  max_bytes: the largest job.
+int launch_fetch_list(const FetchJob *jobs_mapped, int n_jobs, int64_t max_bytes, hipStream_t s);
+// LDS of the row stage's deferred-slice kernel.
+size_t split_rows_slow_lds(int J, int R);
 // Dynamic LDS of a sweep launch that also runs the final phase, or 0 when the
 // two do not fit one workgroup.
 size_t fused_pass_lds(int variant, int J, int R);

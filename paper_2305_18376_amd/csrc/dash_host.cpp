@@ -20,143 +20,11 @@
 #include <string>
 #include <vector>
 
-#include "dash.h"
-#include "dash_dev.h"
+#include "dash_ctx.h"
 
 using namespace dash;
 
-namespace {
-
-constexpr int kStages = 4;             // pinned descriptor blocks in rotation
-constexpr int kMaxChunks2 = 8192;      // bound on solve-stage chunks of the split sweep
-
-struct PendingGroup {
-  int32_t slice;
-  const float *src;
-  int64_t nrows;
-  int64_t out_row;
-};
-
-struct InFlight {
-  int64_t step;
-  int32_t K_prev, K_after;
-  int64_t rows;
-  int slot;
-  int cand;        // autotuning candidate the update ran with, or -1
-  double bytes;    // its algorithmic bytes (the autotuner's cost unit)
-  int n_items;     // slices that received rows
-  bool scored;     // anomaly scores were computed
-};
-
-// How an update is launched: sweep variant, slices per wave (or workgroup)
-// relative to the default, and whether the final phase rides in the sweep.
-struct Schedule {
-  int variant;
-  int spread;   // 1: the default chunking; 2: twice the slices per chunk
-  int fuse;
-};
-
-}  // namespace
-
-struct dash_ctx {
-  dash_config cfg{};
-  int J = 0, R = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-  int64_t K_cap = 0, M_cap = 0, G_cap = 0, N_init_cap = 0;
-  // device state
-  float *Y = nullptr;
-  float *Yc = nullptr;   // compensation words of Y and D (mixed precision only)
-  float *Dc = nullptr;
-  float *D = nullptr;
-  double *n = nullptr;
-  uint8_t *cur = nullptr;
-  int32_t *tlast = nullptr;
-  double *W = nullptr;
-  char *vb = nullptr;
-  int64_t vb_stride = 0;
-  Ctl *ctl = nullptr;
-  float *U_out = nullptr;
-  double *partials = nullptr;
-  double *gpart = nullptr;
-  int32_t *counters = nullptr;
-  // split sweep
-  double *cbuf = nullptr;    // [K_cap][R] c_k of touched slices
-  double *part2 = nullptr;   // [kMaxChunks2][R*R+1]
-  int32_t *tag = nullptr;    // [K_cap]
-  int32_t *queue = nullptr;  // row-stage counters [4]
-  int32_t *slow_list = nullptr;   // [K_cap] deferred row-stage items
-  double *cst = nullptr;     // lagged: [2][K_cap][R]
-  double *FG = nullptr;      // lagged: [2][R*J + R*R]
-  int32_t seq = 0;           // enqueue sequence (never reused)
-  int rows_blocks = 0;       // row-stage workgroups per launch
-  size_t off_items = 0;      // descriptor offset of the items of the update being built
-  int n_items = 0, n_chunks2 = 0, chunk2 = 0;
-  // anomaly scores (dash_anomaly)
-  int anom_window = 0;
-  AnomalyArgs anom{};
-  std::deque<double> te_hist;   // te of committed scored updates (the last anom_window)
-  int anom_n_last = -1;         // slices scored by the last committed scored update
-  int64_t *d_rowptr = nullptr;
-  char *dstep[kStages] = {nullptr, nullptr, nullptr, nullptr};   // device copies of the stages
-  char *hstage_dev[kStages] = {nullptr, nullptr, nullptr, nullptr};   // device view of the pinned stages
-  bool desc_fetch = true;   // true: copy each descriptor to device memory first; false: kernels read it in place
-  size_t off_args = 0, off_gptr = 0, off_groups = 0, step_bytes = 0;   // descriptor layout
-  int variant = kPassWave;
-  Schedule sched{kPassWave, 1, 1};         // current schedule
-  // autotuning (dash_autotune): candidates tried in turn over the next updates,
-  // each scored by device time per algorithmic byte; the best is kept
-  std::vector<Schedule> tune_cands;
-  std::vector<double> tune_us, tune_bytes;
-  std::vector<int> tune_n;
-  int tune_per = 0, tune_next = 0;
-  bool tuned = false;
-  int fused_lds = 0;   // > 0: the sweep launch runs the final phase too (its dynamic LDS)
-  int n_cu = 0;   // compute units of the device
-  // pinned
-  char *hstage[kStages] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t stage_ev[kStages] = {nullptr, nullptr, nullptr, nullptr};
-  bool stage_used[kStages] = {false, false, false, false};
-  int stage_next = 0;
-  Report *hreport = nullptr;
-  Report *dreport = nullptr;
-  // host-side view of the state
-  bool initialized = false;
-  int32_t K = 0;          // committed slices
-  int64_t step = 0;       // committed updates
-  int64_t m_last = 0;     // rows of the last committed update
-  int32_t K_enq = 0;      // slices after the last enqueued update
-  int64_t step_enq = 0;
-  int32_t K_pending = 0;  // including staged new slices
-  std::vector<PendingGroup> pending;
-  int64_t rows_pending = 0;
-  std::deque<InFlight> inflight;
-  // graph mode: an update's launches (descriptor fetch, n_iter sweeps, final
-  // phases) replayed from an instantiated graph whose kernel-node parameters
-  // (grid sizes, descriptor pointers) are rewritten for every update.  One
-  // graph per descriptor stage: a stage is reused only after the update that
-  // last used it has completed, so no graph is rewritten while in flight.
-  bool graph_on = false;
-  hipGraph_t graph[kStages] = {};
-  hipGraphExec_t gexec[kStages] = {};
-  std::vector<hipGraphNode_t> gnodes[kStages];      // kernel nodes in launch order
-  std::vector<hipKernelNodeParams> gparams[kStages];   // their captured parameters
-  Schedule gsched{-1, 0, 0};                // the schedule the graphs were captured with
-  bool spans_on = false;                   // collect every reaped update's device span
-  std::vector<float> spans;                // spans (ms) of the reaped updates
-  int chunk_override = 0;
-  std::vector<int> order;  // scratch
-  // profiling: event pairs around launches, folded into stats on read
-  bool profiling = false;   // events around this update's launches
-  int prof_every = 0;       // > 0: profile the updates whose index is a multiple of it
-  std::vector<hipEvent_t> ev;
-  std::vector<int> ev_kind;  // kind per recorded pair
-  int ev_used = 0;           // pairs recorded since the last fold
-  dash_profile_stats prof{};
-};
-
-namespace {
+namespace dash {
 
 dash_status fail(dash_ctx *c, dash_status s, const char *fmt, ...) {
   if (c) {
@@ -688,7 +556,7 @@ dash_status read_ctl(dash_ctx *c, Ctl *out) {
   return DASH_OK;
 }
 
-}  // namespace
+}  // namespace dash
 
 extern "C" {
 
@@ -753,7 +621,11 @@ const char *dash_status_string(dash_status s) {
 
 const char *dash_last_error(const dash_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
-dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
+}  // extern "C"
+
+namespace dash {
+
+dash_status create_context(const dash_config *cfg, hipStream_t stream, bool served, dash_ctx **out) {
   if (!cfg || !out) return DASH_E_INVALID_ARG;
   *out = nullptr;
   if (cfg->J < 1 || cfg->J > kMaxJ || cfg->R < 1 || cfg->R > kMaxR) return DASH_E_INVALID_ARG;
@@ -774,15 +646,19 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->M_cap = cfg->max_rows_per_update;
   c->G_cap = cfg->max_groups_per_update + c->K_cap;  // new slices are groups too
   c->N_init_cap = cfg->max_init_rows;
+  c->served = served;
   c->variant = pass_variant(cfg->J, cfg->R, cfg->precision, cfg->stats_mode == DASH_STATS_LAGGED);
   if (const char *e = std::getenv("DASH_VARIANT"))
     if (std::atoi(e) == kPassSplit) c->variant = kPassSplit;
-  c->fused_lds = (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
+  if (served) c->variant = kPassSplit;   // the batched launches of a server tick run the split sweep
+  c->fused_lds = served ? 0 : (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
   if (const char *e = std::getenv("DASH_FUSE"))
     if (std::atoi(e) == 0) c->fused_lds = 0;
   c->sched = Schedule{c->variant, 1, c->fused_lds > 0 ? 1 : 0};
-  if (const char *e = std::getenv("DASH_DESC_FETCH")) c->desc_fetch = std::atoi(e) != 0;
-  if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
+  if (!served) {
+    if (const char *e = std::getenv("DASH_DESC_FETCH")) c->desc_fetch = std::atoi(e) != 0;
+    if (const char *e = std::getenv("DASH_CHUNK")) c->chunk_override = std::atoi(e);
+  }
   auto bail = [&](dash_status s) {
     dash_destroy(c);
     return s;
@@ -790,13 +666,18 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   if (hipSetDevice(cfg->device) != hipSuccess) return bail(DASH_E_DEVICE);
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess)
     return bail(DASH_E_DEVICE);
+  // a served stream plans its chunks for a fixed share of the device, so that
+  // its reductions have the same order whatever else the server runs
+  if (served) c->n_cu = std::min(c->n_cu, kServeCUs);
   // persistent row-stage workgroups: as many as can be resident
   c->rows_blocks = std::max(1, c->n_cu) *
                    std::max(1, split_rows_blocks_per_cu(cfg->J, cfg->R, cfg->precision == DASH_PREC_MIXED));
-  if (cfg->stream) {
-    c->stream = (hipStream_t)cfg->stream;
+  if (stream) {
+    c->stream = stream;
   } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(DASH_E_DEVICE);
+    // a blocking stream: ordered after the work of the null stream, on which
+    // callers that name no stream produce the rows they ingest
+    if (hipStreamCreate(&c->stream) != hipSuccess) return bail(DASH_E_DEVICE);
     c->own_stream = true;
   }
   const int64_t J = c->J, R = c->R, Kc = c->K_cap;
@@ -868,6 +749,15 @@ dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
   c->pending.reserve(1024);
   *out = c;
   return DASH_OK;
+}
+
+}  // namespace dash
+
+extern "C" {
+
+dash_status dash_create(const dash_config *cfg, dash_ctx **out) {
+  if (!cfg || !out) return DASH_E_INVALID_ARG;
+  return create_context(cfg, (hipStream_t)cfg->stream, false, out);
 }
 
 dash_status dash_destroy(dash_ctx *c) {
@@ -1057,6 +947,8 @@ dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const floa
 dash_status dash_ingest_rows(dash_ctx *c, int32_t n, const int32_t *slice_id, const int64_t *row_ptr,
                              const float *rows) {
   if (!c) return DASH_E_INVALID_ARG;
+  if (c->served && !c->server_ingest)
+    return fail(c, DASH_E_BAD_STATE, "a served stream takes rows through dash_server_submit");
   if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
   if (n < 0) return fail(c, DASH_E_INVALID_ARG, "n < 0");
   if (n == 0) return DASH_OK;
@@ -1086,6 +978,8 @@ dash_status dash_ingest_rows(dash_ctx *c, int32_t n, const int32_t *slice_id, co
 dash_status dash_ingest_slices(dash_ctx *c, int32_t L, const int64_t *row_ptr, const float *rows,
                                int32_t *first_id) {
   if (!c) return DASH_E_INVALID_ARG;
+  if (c->served && !c->server_ingest)
+    return fail(c, DASH_E_BAD_STATE, "a served stream takes rows through dash_server_submit");
   if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
   if (L < 0) return fail(c, DASH_E_INVALID_ARG, "L < 0");
   if (first_id) *first_id = c->K_pending;
@@ -1108,14 +1002,16 @@ dash_status dash_ingest_slices(dash_ctx *c, int32_t L, const int64_t *row_ptr, c
   return DASH_OK;
 }
 
-dash_status dash_update_async(dash_ctx *c) {
-  if (!c) return DASH_E_INVALID_ARG;
-  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
-  if (c->rows_pending == 0) return DASH_OK;  // empty update: no-op, no forgetting
-  if ((int)c->inflight.size() >= kReportRing - 1) {
-    dash_status s = dash_wait(c, nullptr);
-    if (s != DASH_OK) return s;
-  }
+}  // extern "C"
+
+namespace dash {
+
+bool stage_free(dash_ctx *c) {
+  const int s = c->stage_next;
+  return !c->stage_used[s] || hipEventQuery(c->stage_ev[s]) == hipSuccess;
+}
+
+dash_status build_update(dash_ctx *c, BuiltUpdate *bu) {
   const int K = c->K_pending, Kp = c->K_enq;
   int cand = -1;
   if (!c->tune_cands.empty() && !c->tuned) {
@@ -1173,7 +1069,6 @@ dash_status dash_update_async(dash_ctx *c) {
     std::stable_sort(items, items + n_items, [](const Item &x, const Item &y) { return x.rows > y.rows; });
   }
   const int64_t step = c->step_enq + 1;
-  c->profiling = c->prof_every > 0 && step % c->prof_every == 0;
   const int slot = (int)(step % kReportRing);
   std::memset(h, 0, sizeof *h);
   h->K = K;
@@ -1192,12 +1087,59 @@ dash_status dash_update_async(dash_ctx *c) {
   h->seq = ++c->seq;
   c->hreport[slot].done = 0;
   c->hreport[slot].t_start = c->hreport[slot].t_end = 0;
-  const size_t bytes = c->off_items + sizeof(Item) * n_items;
   const char *dblk = c->desc_fetch ? c->dstep[s] : c->hstage_dev[s];
   if (split) write_pass_args(c, blk, dblk, 0);
+  bu->stage = s;
+  bu->bytes = c->off_items + sizeof(Item) * n_items;
+  bu->dblk = dblk;
+  bu->nch = nch;
+  bu->n_chunks2 = h->n_chunks2;
+  bu->n_items = n_items;
+  bu->step = step;
+  bu->slot = slot;
+  bu->cand = cand;
+  bu->scored = c->anom_window > 0;
+  bu->report = h->report;
+  return DASH_OK;
+}
 
+void account_update(dash_ctx *c, const BuiltUpdate &b) {
+  const Group *grp = (const Group *)(c->hstage[b.stage] + c->off_groups);
+  const int ng = (int)c->pending.size();
+  int touched = 0;
+  for (int g = 0; g < ng; ++g)
+    if (g == 0 || grp[g].slice != grp[g - 1].slice) ++touched;
+  const int K = c->K_pending;
+  const double J = c->J, R = c->R, M = (double)c->rows_pending, Kt = (double)touched;
+  const double bytes = c->cfg.n_iter * (M * J * 4 + M * R * 4 + K * (R * J * 4 + R * R * 4 + 8 + R * 8) +
+                                        Kt * (R * J * 4 + R * R * 4 + 8) + K * R * 8);
+  c->inflight.push_back({b.step, c->K_enq, K, c->rows_pending, b.slot, b.cand, bytes, b.n_items, b.scored});
+  c->K_enq = K;
+  c->step_enq = b.step;
+  c->pending.clear();
+  c->rows_pending = 0;
+}
+
+}  // namespace dash
+
+extern "C" {
+
+dash_status dash_update_async(dash_ctx *c) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
+  if (c->served) return fail(c, DASH_E_BAD_STATE, "a served stream is updated by its server's ticks");
+  if (c->rows_pending == 0) return DASH_OK;  // empty update: no-op, no forgetting
+  if ((int)c->inflight.size() >= kReportRing - 1) {
+    dash_status s = dash_wait(c, nullptr);
+    if (s != DASH_OK) return s;
+  }
+  BuiltUpdate b;
+  if (dash_status st = build_update(c, &b)) return st;
+  const int s = b.stage, nch = b.nch, n_items = b.n_items;
+  const bool split = c->sched.variant == kPassSplit;
+  c->profiling = c->prof_every > 0 && b.step % c->prof_every == 0;
   const bool tuning = !c->tune_cands.empty() && !c->tuned;
-  const bool scored = c->anom_window > 0;
+  const bool scored = b.scored;
   if (c->graph_on && !c->profiling && c->desc_fetch && !tuning && !scored) {
     if (c->gsched.variant != c->sched.variant || c->gsched.spread != c->sched.spread ||
         c->gsched.fuse != c->sched.fuse) {
@@ -1206,9 +1148,9 @@ dash_status dash_update_async(dash_ctx *c) {
       graph_reset(c);
       c->gsched = c->sched;
     }
-    if (dash_status st = graph_update(c, s, bytes, nch, h->report, n_items, h->n_chunks2)) return st;
+    if (dash_status st = graph_update(c, s, b.bytes, nch, b.report, n_items, b.n_chunks2)) return st;
   } else {
-    HIP_OR_FAIL(c, upload_stage(c, s, bytes, true, h->report));
+    HIP_OR_FAIL(c, upload_stage(c, s, b.bytes, true, b.report));
     PassArgs a = base_args(c, s);
     a.mode = 0;
     for (int p = 0; p < c->cfg.n_iter; ++p) {
@@ -1216,7 +1158,7 @@ dash_status dash_update_async(dash_ctx *c) {
       a.last_pass = (p == c->cfg.n_iter - 1) ? 1 : 0;
       if (split) {
         a.fuse = 0;
-        if (dash_status st = enqueue_split_pass(c, a, args_dev(c, dblk, p), n_items, h->n_chunks2, nch)) return st;
+        if (dash_status st = enqueue_split_pass(c, a, args_dev(c, b.dblk, p), n_items, b.n_chunks2, nch)) return st;
         continue;
       }
       HIP_OR_FAIL(c, prof_begin(c, kProfPass));
@@ -1238,19 +1180,7 @@ dash_status dash_update_async(dash_ctx *c) {
   HIP_OR_FAIL(c, stage_done(c, s));
   if (c->profiling) c->prof.updates++;
   c->profiling = false;
-  {
-    int touched = 0;
-    for (int g = 0; g < ng; ++g)
-      if (g == 0 || grp[g].slice != grp[g - 1].slice) ++touched;
-    const double J = c->J, R = c->R, M = (double)c->rows_pending, Kt = (double)touched;
-    const double bytes = c->cfg.n_iter * (M * J * 4 + M * R * 4 + K * (R * J * 4 + R * R * 4 + 8 + R * 8) +
-                                          Kt * (R * J * 4 + R * R * 4 + 8) + K * R * 8);
-    c->inflight.push_back({step, Kp, K, c->rows_pending, slot, cand, bytes, n_items, scored});
-  }
-  c->K_enq = K;
-  c->step_enq = step;
-  c->pending.clear();
-  c->rows_pending = 0;
+  account_update(c, b);
   return DASH_OK;
 }
 
@@ -1740,138 +1670,5 @@ dash_status dash_load(dash_ctx *c, const char *path) {
   return DASH_OK;
 }
 
-
-// ---------------------------------------------------------------------------
-// Serving: many streams (contexts) on one device
-// ---------------------------------------------------------------------------
-struct dash_server {
-  int device = 0;
-  int64_t budget = 0, used = 0;
-  struct Stream {
-    dash_ctx *ctx = nullptr;
-    int64_t footprint = 0;
-    std::deque<double> cuts;   // host time (us) at which each in-flight update was cut
-  };
-  std::vector<Stream> streams;
-};
-
-static double now_us() {
-  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-dash_status dash_server_create(int32_t device, int64_t budget_bytes, dash_server **out) {
-  if (!out || budget_bytes < 0) return DASH_E_INVALID_ARG;
-  dash_server *srv = new (std::nothrow) dash_server();
-  if (!srv) return DASH_E_OUT_OF_MEMORY;
-  srv->device = device;
-  srv->budget = budget_bytes;
-  *out = srv;
-  return DASH_OK;
-}
-
-dash_status dash_server_destroy(dash_server *srv) {
-  if (!srv) return DASH_OK;
-  for (auto &st : srv->streams)
-    if (st.ctx) dash_destroy(st.ctx);
-  delete srv;
-  return DASH_OK;
-}
-
-dash_status dash_server_open(dash_server *srv, const dash_config *cfg, int32_t *stream) {
-  if (!srv || !cfg || !stream) return DASH_E_INVALID_ARG;
-  int64_t fp = 0;
-  if (dash_status s = dash_footprint(cfg, &fp)) return s;
-  if (srv->used + fp > srv->budget) return DASH_E_CAPACITY;   // admission: caller may retry later
-  dash_config c2 = *cfg;
-  c2.device = srv->device;
-  c2.stream = nullptr;   // every stream gets a HIP stream of its own
-  dash_ctx *ctx = nullptr;
-  if (dash_status s = dash_create(&c2, &ctx)) return s;
-  int32_t id = -1;
-  for (size_t i = 0; i < srv->streams.size(); ++i)
-    if (!srv->streams[i].ctx) {
-      id = (int32_t)i;
-      break;
-    }
-  if (id < 0) {
-    srv->streams.emplace_back();
-    id = (int32_t)srv->streams.size() - 1;
-  }
-  srv->streams[id].ctx = ctx;
-  srv->streams[id].footprint = fp;
-  srv->streams[id].cuts.clear();
-  srv->used += fp;
-  *stream = id;
-  return DASH_OK;
-}
-
-dash_status dash_server_close(dash_server *srv, int32_t stream) {
-  if (!srv || stream < 0 || stream >= (int32_t)srv->streams.size() || !srv->streams[stream].ctx)
-    return DASH_E_INVALID_ARG;
-  auto &st = srv->streams[stream];
-  dash_destroy(st.ctx);
-  srv->used -= st.footprint;
-  st = dash_server::Stream{};
-  return DASH_OK;
-}
-
-dash_ctx *dash_server_context(dash_server *srv, int32_t stream) {
-  if (!srv || stream < 0 || stream >= (int32_t)srv->streams.size()) return nullptr;
-  return srv->streams[stream].ctx;
-}
-
-dash_status dash_server_tick(dash_server *srv, int32_t *launched) {
-  if (!srv) return DASH_E_INVALID_ARG;
-  int32_t n = 0;
-  dash_status first = DASH_OK;
-  for (auto &st : srv->streams) {
-    dash_ctx *c = st.ctx;
-    if (!c || !c->initialized || c->rows_pending == 0) continue;
-    const double t = now_us();
-    const dash_status s = dash_update_async(c);
-    if (s != DASH_OK) {
-      if (first == DASH_OK) first = s;
-      continue;
-    }
-    st.cuts.push_back(t);
-    ++n;
-  }
-  if (launched) *launched = n;
-  return first;
-}
-
-dash_status dash_server_poll(dash_server *srv, int32_t wait, dash_server_report *out, int32_t cap,
-                             int32_t *n) {
-  if (!srv || !n || cap < 0 || (cap > 0 && !out)) return DASH_E_INVALID_ARG;
-  *n = 0;
-  dash_status first = DASH_OK;
-  for (size_t id = 0; id < srv->streams.size() && *n < cap; ++id) {
-    auto &st = srv->streams[id];
-    if (!st.ctx || st.cuts.empty()) continue;
-    if (wait && hipStreamSynchronize(st.ctx->stream) != hipSuccess) {
-      if (first == DASH_OK) first = DASH_E_DEVICE;
-      continue;
-    }
-    dash_update_report reps[kReportRing];
-    int32_t got = 0;
-    const dash_status s = dash_poll(st.ctx, reps, std::min<int32_t>(kReportRing, cap - *n), &got);
-    const double t = now_us();
-    for (int32_t i = 0; i < got && !st.cuts.empty(); ++i) {
-      dash_server_report &o = out[(*n)++];
-      o.stream = (int32_t)id;
-      o.committed = reps[i].committed;
-      o.step = reps[i].step;
-      o.rows = reps[i].rows;
-      o.fit = reps[i].fit;
-      o.latency_us = t - st.cuts.front();
-      st.cuts.pop_front();
-    }
-    if (s != DASH_OK) {   // rolled back: every update of the stream that was in flight is gone
-      st.cuts.clear();
-      if (first == DASH_OK) first = s;
-    }
-  }
-  return first;
-}
 
 }  // extern "C"

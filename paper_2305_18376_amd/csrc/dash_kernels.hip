@@ -865,6 +865,20 @@ __global__ void k_fetch(const uint4 *src, uint4 *dst, int64_t n16, const unsigne
   if (i < tail) dst_tail[i] = src_tail[i];
 }
 
+// Batched descriptor fetch: workgroup row y copies job y with a grid-stride
+// loop of 16-byte words.
+__global__ void k_fetch_list(const FetchJob *jobs, int n_jobs) {
+  const int y = blockIdx.y;
+  if (y >= n_jobs) return;
+  const FetchJob j = jobs[y];
+  const int64_t n16 = j.bytes / 16;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i0 == 0 && j.report) ((Report *)j.report)->t_start = __builtin_amdgcn_s_memrealtime();
+  const uint4 *src = (const uint4 *)j.src;
+  uint4 *dst = (uint4 *)j.dst;
+  for (int64_t i = i0; i < n16; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 __global__ void k_v_from_f32(int JR, const float *V, double *V64) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e < JR) V64[e] = (double)V[e];
@@ -1078,6 +1092,14 @@ int launch_fetch(const char *src, char *dst, size_t bytes, void *report, hipStre
   const FetchArgs f = fetch_args(src, dst, bytes, report);
   hipLaunchKernelGGL(k_fetch, dim3(f.grid), dim3(256), 0, s, (const uint4 *)f.src, (uint4 *)f.dst, f.n16,
                      (const unsigned char *)f.src_tail, (unsigned char *)f.dst_tail, f.tail, (Report *)f.report);
+  return (int)hipGetLastError();
+}
+
+int launch_fetch_list(const FetchJob *jobs, int n_jobs, int64_t max_bytes, hipStream_t s) {
+  if (n_jobs <= 0) return 0;
+  const int64_t w = std::max<int64_t>(max_bytes / 16, 1);
+  const unsigned gx = (unsigned)std::min<int64_t>((w + 255) / 256, 64);
+  hipLaunchKernelGGL(k_fetch_list, dim3(gx, (unsigned)n_jobs), dim3(256), 0, s, jobs, n_jobs);
   return (int)hipGetLastError();
 }
 

@@ -1171,6 +1171,7 @@ static size_t rows_fast_lds(int J, int R, bool mixed) {
 }
 
 size_t split_rows_lds(int J, int R, int mixed) { return rows_fast_lds(J, R, mixed != 0); }
+size_t split_rows_slow_lds(int J, int R) { return rows_lds(J, R).bytes; }
 size_t split_solve_lds(int J, int R) { return solve_lds(J, R).bytes; }
 size_t split_fsum_lds(int J, int R, int lagged) {
   if (lagged) return rows_lds(J, R).bytes;

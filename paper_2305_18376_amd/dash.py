@@ -73,7 +73,16 @@ class Schedule(C.Structure):
 
 class ServerReport(C.Structure):
     _fields_ = [("stream", C.c_int32), ("committed", C.c_int32), ("step", C.c_int64), ("rows", C.c_int64),
-                ("fit", C.c_double), ("latency_us", C.c_double)]
+                ("fit", C.c_double), ("latency_us", C.c_double), ("last_request", C.c_int64),
+                ("device_us", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("ticks", C.c_int64), ("launches", C.c_int64), ("updates", C.c_int64), ("rows", C.c_int64),
+                ("budget", C.c_int64), ("used", C.c_int64), ("queued", C.c_int32), ("open", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -112,11 +121,19 @@ _SIGS = {
     "dash_spans_read": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_server_create": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(_P)]),
     "dash_server_destroy": (C.c_int, [_P]),
-    "dash_server_open": (C.c_int, [_P, C.POINTER(DashConfig), C.POINTER(C.c_int32)]),
+    "dash_server_open": (C.c_int, [_P, C.POINTER(DashConfig), C.c_int32, C.POINTER(C.c_int32)]),
+    "dash_server_state": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "dash_server_close": (C.c_int, [_P, C.c_int32]),
     "dash_server_context": (_P, [_P, C.c_int32]),
+    "dash_server_submit": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P,
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "dash_server_tick": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "dash_server_poll": (C.c_int, [_P, C.c_int32, C.POINTER(ServerReport), C.c_int32, C.POINTER(C.c_int32)]),
+    "dash_server_start": (C.c_int, [_P, C.c_int32]),
+    "dash_server_stop": (C.c_int, [_P]),
+    "dash_server_drain": (C.c_int, [_P, C.c_int32]),
+    "dash_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
+    "dash_server_last_error": (C.c_char_p, [_P]),
 }
 
 _lib = None
@@ -191,12 +208,7 @@ class Dash:
 
     def __init__(self, J, R, lam=0.7, n_iter=1, max_slices=65536, max_rows=1 << 20,
                  max_groups=65536, max_init_rows=4 << 20, init_max_iter=10, init_tol=1e-10,
-                 device=0, stream=None, precision=PREC_FP32, stats_mode=STATS_EXACT, _handle=None):
-        if _handle is not None:   # a context owned by a DashServer
-            self._h, self._owned = _handle, False
-            self.J, self.R, self.device = J, R, device
-            self._borrowed = []
-            return
+                 device=0, stream=None, precision=PREC_FP32, stats_mode=STATS_EXACT):
         self._owned = True
         cfg = make_config(J, R, lam, n_iter, max_slices, max_rows, max_groups, max_init_rows, init_max_iter,
                           init_tol, device, precision, stats_mode)
@@ -378,7 +390,12 @@ class Dash:
 
 
 class DashServer:
-    """Many streams on one device (the serving layer of the library)."""
+    """Many streams on one device (the serving layer of the library).
+
+    Rows go in through submit(); the device buffers of a request are kept
+    referenced here until an update of its stream reports them consumed."""
+
+    QUEUED, OPEN = 1, 2
 
     def __init__(self, budget_bytes, device=0):
         h = _P()
@@ -387,35 +404,83 @@ class DashServer:
             raise DashError(st, "dash_server_create")
         self._h = h
         self.device = device
-        self._streams = {}
+        self._views = {}
+        self._held = {}      # stream -> [(request id, tensors)]
 
-    def open(self, J, R, **kw):
-        """Admit a stream; returns (id, Dash view of its context) or raises DashError
-        with status E_CAPACITY when its footprint does not fit the unused budget."""
+    def _check(self, st, what):
+        if st != OK:
+            msg = lib().dash_server_last_error(self._h)
+            raise DashError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def open(self, J, R, queue=False, **kw):
+        """Open a stream; returns its id.  Raises DashError (E_CAPACITY) when its
+        footprint does not fit and queue is False; with queue=True it may wait
+        for admission (state() == QUEUED)."""
         cfg = make_config(J, R, device=self.device, **kw)
         sid = C.c_int32()
-        st = lib().dash_server_open(self._h, C.byref(cfg), C.byref(sid))
-        if st != OK:
-            raise DashError(st, "dash_server_open")
-        g = Dash(J, R, device=self.device, _handle=lib().dash_server_context(self._h, sid.value))
-        self._streams[sid.value] = g
-        return sid.value, g
+        self._check(lib().dash_server_open(self._h, C.byref(cfg), 1 if queue else 0, C.byref(sid)),
+                    "dash_server_open")
+        self._held[sid.value] = []
+        self._views.pop(sid.value, None)
+        return sid.value
+
+    def state(self, sid):
+        v = C.c_int32()
+        self._check(lib().dash_server_state(self._h, sid, C.byref(v)), "dash_server_state")
+        return v.value
+
+    def context(self, sid):
+        """A Dash view of an open stream's context (init, get_* only)."""
+        if sid not in self._views:
+            h = lib().dash_server_context(self._h, sid)
+            if not h:
+                raise DashError(E_BAD_STATE, f"stream {sid} is not open")
+            d = Dash.__new__(Dash)
+            d._h, d._owned, d._borrowed = h, False, []
+            dims = Dims()
+            lib().dash_get_dims(h, C.byref(dims))
+            d.J, d.R, d.device = dims.J, dims.R, self.device
+            self._views[sid] = d
+        return self._views[sid]
 
     def close_stream(self, sid):
-        g = self._streams.pop(sid)
-        g._h = None
-        st = lib().dash_server_close(self._h, sid)
-        if st != OK:
-            raise DashError(st, "dash_server_close")
+        v = self._views.pop(sid, None)
+        if v is not None:
+            v._h = None
+        self._check(lib().dash_server_close(self._h, sid), "dash_server_close")
+        self._held.pop(sid, None)
+
+    def submit(self, sid, slice_id=None, row_ptr=None, rows=None, new_ptr=None, new_rows=None, producer=None):
+        """Submit row groups (slice_id, row_ptr host arrays; rows a device tensor)
+        and new slices (new_ptr host array; new_rows a device tensor).  producer:
+        the HIP stream the tensors were written on (default: torch's current
+        stream).  Returns (request id, first new slice id)."""
+        ng = 0 if slice_id is None else len(slice_id)
+        nn = 0 if new_ptr is None else len(new_ptr) - 1
+        sid_a = _host(slice_id, np.int32) if ng else None
+        ptr_a = _host(row_ptr, np.int64) if ng else None
+        nptr_a = _host(new_ptr, np.int64) if nn else None
+        if producer is None:
+            import torch
+            producer = torch.cuda.current_stream(self.device).cuda_stream
+        req = C.c_int64()
+        first = C.c_int32()
+        st = lib().dash_server_submit(self._h, sid, ng, _ptr(sid_a), _ptr(ptr_a), _ptr(rows) if ng else None, nn,
+                                      _ptr(nptr_a), _ptr(new_rows) if nn else None, producer or None,
+                                      C.byref(req), C.byref(first))
+        self._check(st, "dash_server_submit")
+        self._held.setdefault(sid, []).append((req.value, (rows, new_rows)))
+        return req.value, first.value
+
+    def _release(self, reps):
+        for r in reps:
+            held = self._held.get(r["stream"])
+            if held:
+                self._held[r["stream"]] = [(q, t) for q, t in held if q > r["last_request"]]
 
     def tick(self):
         n = C.c_int32()
-        st = lib().dash_server_tick(self._h, C.byref(n))
-        if st != OK:
-            raise DashError(st, "dash_server_tick")
-        for g in self._streams.values():
-            g._inflight_borrowed = getattr(g, "_inflight_borrowed", []) + g._borrowed
-            g._borrowed = []
+        self._check(lib().dash_server_tick(self._h, C.byref(n)), "dash_server_tick")
         return n.value
 
     def poll(self, wait=False, cap=4096):
@@ -423,20 +488,32 @@ class DashServer:
         n = C.c_int32()
         st = lib().dash_server_poll(self._h, 1 if wait else 0, out, cap, C.byref(n))
         reps = [out[i].as_dict() for i in range(n.value)]
-        if wait:
-            for g in self._streams.values():
-                g._inflight_borrowed = []
-        if st != OK:
-            raise DashError(st, "dash_server_poll")
+        self._release(reps)
+        self._check(st, "dash_server_poll")
         return reps
+
+    def start(self, tick_us=0):
+        self._check(lib().dash_server_start(self._h, int(tick_us)), "dash_server_start")
+
+    def stop(self):
+        self._check(lib().dash_server_stop(self._h), "dash_server_stop")
+
+    def drain(self, timeout_ms=-1):
+        self._check(lib().dash_server_drain(self._h, int(timeout_ms)), "dash_server_drain")
+
+    def stats(self):
+        s = ServerStats()
+        self._check(lib().dash_server_get_stats(self._h, C.byref(s)), "dash_server_get_stats")
+        return s.as_dict()
 
     def close(self):
         if getattr(self, "_h", None):
-            for g in self._streams.values():
-                g._h = None
+            for v in self._views.values():
+                v._h = None
             lib().dash_server_destroy(self._h)
             self._h = None
-            self._streams = {}
+            self._views = {}
+            self._held = {}
 
     def __del__(self):
         try:

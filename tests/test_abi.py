@@ -88,7 +88,13 @@ def test_footprint_and_admission_without_a_device():
     srv = C.c_void_p()
     assert D.lib().dash_server_create(0, a.value - 1, C.byref(srv)) == D.OK
     sid = C.c_int32(-1)
-    assert D.lib().dash_server_open(srv, C.byref(small), C.byref(sid)) == D.E_CAPACITY
+    assert D.lib().dash_server_open(srv, C.byref(small), 0, C.byref(sid)) == D.E_CAPACITY
     assert sid.value == -1
+    # larger than the whole budget: refused even when it may wait
+    assert D.lib().dash_server_open(srv, C.byref(small), 1, C.byref(sid)) == D.E_CAPACITY
+    assert sid.value == -1
+    st = D.ServerStats()
+    assert D.lib().dash_server_get_stats(srv, C.byref(st)) == D.OK
+    assert st.open == 0 and st.queued == 0 and st.budget == a.value - 1
     assert D.lib().dash_server_context(srv, 0) is None
     assert D.lib().dash_server_destroy(srv) == D.OK
