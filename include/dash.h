@@ -26,6 +26,7 @@
 #ifndef DASH_H
 #define DASH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -143,6 +144,22 @@ dash_status dash_destroy(dash_ctx *ctx);
  * DASH_E_INVALID_ARG, DASH_E_NUMERIC (context stays uninitialised). */
 dash_status dash_init(dash_ctx *ctx, int32_t K, const int64_t *row_ptr, const float *X,
                       const float *V0, dash_init_report *report);
+
+/* dash_init for callers that cannot allocate device memory (code under HIP
+ * graph capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid hipMalloc): the same initialisation, with the same results, but its
+ * workspace is a fixed array the library holds on each device it runs on
+ * (dash_init_noalloc_limit() bytes, kept until the process ends) instead of a
+ * per-call allocation; no hipMalloc, hipFree or other allocating call.  The
+ * workspace needs (2 J^2 + J + 4 R^2 + K R^2 + ~(K/1024 + 1)(max(2R^2, JR)+2)
+ * doubles, plus a Gram matrix's partials when V0 is NULL); larger problems get
+ * DASH_E_CAPACITY with nothing done.  The call is synchronous and every call
+ * on a device shares that device's array: calls that overlap on one device
+ * (from several threads) race.  Other errors as dash_init. */
+dash_status dash_init_noalloc(dash_ctx *ctx, int32_t K, const int64_t *row_ptr, const float *X,
+                              const float *V0, dash_init_report *report);
+/* Bytes of dash_init_noalloc's per-device workspace. */
+size_t dash_init_noalloc_limit(void);
 
 /* Helper terms from caller-given factors of the initial tensor
  * (eq. [updateC_init]-[updateG_init]): Y_k = U_k^T X_k, D_k = U_k^T U_k,

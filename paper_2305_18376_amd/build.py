@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdash.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("dash_host.cpp", "dash_server.cpp", "dash_kernels.hip", "dash_split.hip", "dash_init.hip",
-            "dash_anomaly.hip")]
+            "dash_anomaly.hip", "dash_noalloc.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

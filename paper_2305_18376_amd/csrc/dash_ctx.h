@@ -183,5 +183,12 @@ int64_t context_footprint(const dash_config *cfg);
 // served stream runs with (split sweep, chunking independent of the device
 // and of other streams).
 dash_status create_context(const dash_config *cfg, hipStream_t stream, bool served, dash_ctx **out);
+// dash_init in parts: argument checks, the size of its device workspace (in
+// doubles), and the initialisation itself on a given workspace (synchronous:
+// the workspace is free again when it returns).
+dash_status init_check(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X);
+size_t init_workspace_doubles(const dash_ctx *c, int32_t K, bool has_v0);
+dash_status init_with_workspace(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
+                                dash_init_report *report, double *ws);
 
 }  // namespace dash

@@ -353,9 +353,12 @@ dash_status reset_device_state(dash_ctx *c, int32_t K, int32_t tl) {
     HIP_OR_FAIL(c, hipMemsetAsync(c->Yc, 0, sizeof(float) * 2 * c->K_cap * y_stride(c->J, c->R), c->stream));
     HIP_OR_FAIL(c, hipMemsetAsync(c->Dc, 0, sizeof(float) * 2 * c->K_cap * c->R * c->R, c->stream));
   }
-  std::vector<int32_t> t(std::max<int32_t>(K, 1), tl);
-  if (K > 0)
-    HIP_OR_FAIL(c, hipMemcpy(c->tlast, t.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+  if (tl == 0) {
+    HIP_OR_FAIL(c, hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * std::max<int32_t>(K, 1), c->stream));
+  } else {
+    std::vector<int32_t> t(std::max<int32_t>(K, 1), tl);
+    if (K > 0) HIP_OR_FAIL(c, hipMemcpy(c->tlast, t.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+  }
   Ctl ctl{};
   ctl.gcur = 0;
   ctl.ok = 1;
@@ -846,8 +849,11 @@ dash_status dash_init_from_factors(dash_ctx *c, int32_t K, const int64_t *row_pt
   return DASH_OK;
 }
 
-dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
-                      dash_init_report *report) {
+}  // extern "C"
+
+namespace dash {
+
+dash_status init_check(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X) {
   if (!c) return DASH_E_INVALID_ARG;
   if (c->initialized) return fail(c, DASH_E_BAD_STATE, "context already initialised");
   if (K < 1) return fail(c, DASH_E_INVALID_ARG, "K must be >= 1");
@@ -855,27 +861,32 @@ dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const floa
   if (!X) return fail(c, DASH_E_INVALID_ARG, "X is NULL");
   if (dash_status s = validate_ptr(c, row_ptr, K, true)) return s;
   if (row_ptr[0] != 0) return fail(c, DASH_E_INVALID_ARG, "row_ptr[0] must be 0");
-  const int64_t N = row_ptr[K];
-  if (N > c->N_init_cap)
-    return fail(c, DASH_E_CAPACITY, "%lld initial rows exceed max_init_rows", (long long)N);
-  if (dash_status s = reset_device_state(c, K, 0)) return s;
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_rowptr, row_ptr, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice,
-                                c->stream));
+  if (row_ptr[K] > c->N_init_cap)
+    return fail(c, DASH_E_CAPACITY, "%lld initial rows exceed max_init_rows", (long long)row_ptr[K]);
+  return DASH_OK;
+}
+
+size_t init_workspace_doubles(const dash_ctx *c, int32_t K, bool has_v0) {
   const int J = c->J, R = c->R, RR = R * R;
-  // the initialisation's scratch lives for this call only
   const int chunk = std::max(1, (K + 1023) / 1024);
   const int n_chunks = (K + chunk - 1) / chunk;
   const int plen = std::max(2 * RR, J * R) + 2;
   const int n_gc = init_gram_chunks(J);
-  const size_t ws_doubles = (size_t)2 * J * J + J + (size_t)(V0 ? 0 : n_gc) * J * J + 4 * (size_t)RR +
-                            (size_t)n_chunks * plen + 2 + (size_t)K * RR;
-  double *ws = nullptr;
-  if (hipMalloc((void **)&ws, ws_doubles * sizeof(double)) != hipSuccess)
-    return fail(c, DASH_E_OUT_OF_MEMORY, "initialisation scratch (%zu doubles)", ws_doubles);
-  struct Freer {
-    double *p;
-    ~Freer() { (void)hipFree(p); }
-  } freer{ws};
+  return (size_t)2 * J * J + J + (size_t)(has_v0 ? 0 : n_gc) * J * J + 4 * (size_t)RR + (size_t)n_chunks * plen +
+         2 + (size_t)K * RR;
+}
+
+dash_status init_with_workspace(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
+                                dash_init_report *report, double *ws) {
+  const int64_t N = row_ptr[K];
+  if (dash_status s = reset_device_state(c, K, 0)) return s;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_rowptr, row_ptr, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice,
+                                c->stream));
+  const int J = c->J, R = c->R, RR = R * R;
+  const int chunk = std::max(1, (K + 1023) / 1024);
+  const int n_chunks = (K + chunk - 1) / chunk;
+  const int plen = std::max(2 * RR, J * R) + 2;
+  const int n_gc = init_gram_chunks(J);
   double *Gm = ws, *Z = Gm + (size_t)J * J, *evals = Z + (size_t)J * J;
   double *gpart = evals + J;
   double *small = gpart + (size_t)(V0 ? 0 : n_gc) * J * J;
@@ -942,6 +953,29 @@ dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const floa
     report->fit = sum_n > 0.0 ? 1.0 - std::sqrt(std::max(0.0, loss)) / std::sqrt(sum_n) : 1.0;
   }
   return DASH_OK;
+}
+
+}  // namespace dash
+
+extern "C" {
+
+dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
+                      dash_init_report *report) {
+  if (dash_status s = init_check(c, K, row_ptr, X)) return s;
+  // the initialisation's scratch lives for this call only
+  const size_t ws_doubles = init_workspace_doubles(c, K, V0 != nullptr);
+  double *ws = nullptr;
+  if (hipMalloc((void **)&ws, ws_doubles * sizeof(double)) != hipSuccess)
+    return fail(c, DASH_E_OUT_OF_MEMORY, "initialisation scratch (%zu doubles)", ws_doubles);
+  const dash_status s = init_with_workspace(c, K, row_ptr, X, V0, report, ws);
+  if (s == DASH_OK) {
+    (void)hipFree(ws);
+  } else {
+    // kernels may still read it: free once the stream is idle
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(ws);
+  }
+  return s;
 }
 
 dash_status dash_ingest_rows(dash_ctx *c, int32_t n, const int32_t *slice_id, const int64_t *row_ptr,

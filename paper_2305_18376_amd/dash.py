@@ -95,6 +95,8 @@ _SIGS = {
     "dash_destroy": (C.c_int, [_P]),
     "dash_init": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.POINTER(InitReport)]),
     "dash_init_from_factors": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P]),
+    "dash_init_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.POINTER(InitReport)]),
+    "dash_init_noalloc_limit": (C.c_size_t, []),
     "dash_ingest_rows": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
     "dash_ingest_slices": (C.c_int, [_P, C.c_int32, _P, _P, C.POINTER(C.c_int32)]),
     "dash_update": (C.c_int, [_P, C.POINTER(UpdateReport)]),
