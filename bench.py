@@ -1,15 +1,23 @@
 """Benchmark of the streaming PARAFAC2 update on one MI355X.
 
-Workload (mid-size dual-way stream): K0 = 2000 slices, I_k log-normal (median
-800, clipped to [100, 4000]), J = 88, R = 10, planted low-rank rows + 5 % noise;
-every update appends U{1..20} rows to every slice and brings 20 new slices of
-U{1..20} rows; lambda = 0.95, one ALS pass per update (Algorithm 1).
+Default (--workload serve): the serving workload in mixed precision -- 64
+independent streams (J ~ U{32,64,128,256}, R ~ U{8,16,32}, K0 ~ U{500..5000},
+lambda = 0.95), rows arriving as Poisson processes of 2000 rows/s per stream
+to Zipf(1.2)-popular slices plus 2 new slices/s of U{1..60} rows, cut into
+25 ms requests, served by one DashServer (200 GB admission budget) whose loop
+thread batches every stream's pending requests into one tick.  A "step" is
+one tick.  Three phases on the same streams: an open-loop replay at the
+arrival times (p50/p99 latency from a request's submit to its update's
+commit), a closed-loop run with four requests in flight per stream (the
+headline rows/s: every row of the phase over its wall time, inputs resident
+in HBM), and a 2 GB-budget run in which streams wait for admission.  The
+sampled streams' per-update fits are checked against the FP64 oracle fed the
+same cuts, which is also timed on the host (the CPU baseline).
 
-A "step" is one update (Lemma 1 rows -> Lemma 2 sweep -> Lemma 3 solve ->
-commit) over one batch that is already resident in HBM.  Warm-up updates run
-blocking and their fits are checked against the FP64 oracle, which is also
-timed on the host as the CPU baseline; the timed updates run back to back
-(asynchronously) and are bracketed by stream synchronisation.
+--workload mid | batch_r10 | batch_r20 | precision: one stream (one context),
+a "step" is one update over a batch resident in HBM; warm-up updates run
+blocking and are checked against the oracle, the timed updates run back to
+back.
 
 Prints ONE JSON line.
 """
@@ -54,12 +62,17 @@ def algorithmic_bytes(M, K, K_t, J, R, words=1):
             + K * R * 8)
 
 
+KERNEL_SOURCES = ("dash_dev.h", "dash_math.h", "dash_tiles.h", "dash_kernels.hip", "dash_split.hip")
+
+
 def _source_digest():
-    """SHA-256 of the kernel source the library is built from."""
+    """SHA-256 over the device sources of the update kernels."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2305_18376_amd", "csrc", "dash_kernels.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_18376_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def counter_traffic(kernel, workload):
@@ -86,12 +99,18 @@ def counter_traffic(kernel, workload):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed updates (mid: 90, others: 20)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed updates (mid: 90, batch/precision: 20); serve: ignored (the phases are timed)")
     ap.add_argument("--warmup", type=int, default=None, help="warm-up updates (mid: 10, others: 3)")
-    ap.add_argument("--workload", default="mid", choices=["mid", "batch_r10", "batch_r20", "precision"],
-                    help="mid is the headline workload; the others are the batching and precision ones "
-                         "(their initial slices are shorter: the per-update cost does not depend on them)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed"])
+    ap.add_argument("--workload", default="serve", choices=["serve", "mid", "batch_r10", "batch_r20", "precision"],
+                    help="serve (default) is the serving workload; the others run one stream (the batching and "
+                         "precision ones with shorter initial slices: the per-update cost does not depend on them)")
+    ap.add_argument("--precision", default=None, choices=["fp32", "mixed"],
+                    help="default: mixed for serve, fp32 otherwise")
+    ap.add_argument("--open-seconds", type=float, default=8.0, help="serve: open-loop replay length")
+    ap.add_argument("--closed-seconds", type=float, default=4.0,
+                    help="serve: stream time replayed closed-loop after the open-loop phase")
+    ap.add_argument("--streams", type=int, default=64, help="serve: number of streams")
     ap.add_argument("--autotune", type=int, default=0,
                     help="N > 0: the warm-up updates try every launch schedule N times and keep the fastest")
     ap.add_argument("--graph", type=int, default=0,
@@ -102,10 +121,6 @@ def main():
     ap.add_argument("--oracle-seconds", type=float, default=25.0,
                     help="bound on the FP64 oracle replay (CPU baseline and fit check)")
     ap.add_argument("--no-oracle", action="store_true")
-    ap.add_argument("--serve", action="store_true",
-                    help="serving measurement instead: 64 streams of mixed shapes on one device, "
-                         "one update per stream per tick; prints its own JSON line")
-    ap.add_argument("--ticks", type=int, default=200, help="ticks of the serving measurement")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one plain device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
@@ -115,8 +130,12 @@ def main():
               "(the update would shard by slice with one all-reduce of F, G per pass).", file=sys.stderr)
         sys.exit(2)
 
-    if args.serve:
+    if args.workload == "serve":
+        if args.precision is None:
+            args.precision = "mixed"
         return serve_main(args)
+    if args.precision is None:
+        args.precision = "fp32"
 
     import torch
     from paper_2305_18376_amd.dash import Dash
@@ -286,110 +305,319 @@ def oracle_leg(wl, ptr, X, U, batches, gpu_fits, gpu_final_fit, budget_s):
     return fit_check, cpu
 
 
-def serve_streams(n_streams, ticks, seed=5000):
-    """Seeded multi-stream workload: per stream J ~ U{32,64,128,256}, R ~ U{8,16,32},
-    lambda ~ U[0.8, 0.99], K0 ~ U{100..300} slices of log-normal length (median 30);
-    every tick Poisson(50) new rows spread over the slices by Zipf(1.2) popularity
-    of a random ranking, and a new slice of U{1..60} rows with probability 0.05."""
-    streams = []
-    for sidx in range(n_streams):
-        rng = np.random.default_rng([seed, sidx])
-        J = int(rng.choice([32, 64, 128, 256]))
-        R = int(rng.choice([8, 16, 32]))
-        lam = float(rng.uniform(0.8, 0.99))
-        K0 = int(rng.integers(100, 301))
-        K_max = K0 + ticks
-        V = rng.standard_normal((J, R))
-        W = rng.uniform(0.5, 1.5, size=(K_max, R))
+SERVE_WORKLOAD = ("serving: {n} streams, J~U{{32,64,128,256}}, R~U{{8,16,32}}, K0~U{{500..5000}} slices "
+                  "(initial slices log-normal median 24, clip [R+1,200], shorter than the median-500 law: the "
+                  "update cost depends on the slice count, not on the rows that built them), lambda=0.95, "
+                  "Poisson 2000 rows/s/stream to Zipf(1.2)-popular slices + Poisson 2 new slices/s of U{{1..60}} "
+                  "rows, 25 ms requests, admission budget 200 GB; open loop {to:g} s at the arrival times, closed "
+                  "loop over the next {tc:g} s of stream time with 4 requests in flight per stream")
 
-        def rows(ids):
-            U = rng.standard_normal((len(ids), R))
-            X = (U * W[ids]) @ V.T + 0.05 * rng.standard_normal((len(ids), J))
-            return X.astype(np.float32), U
 
-        lens = np.clip(np.round(np.exp(np.log(30) + rng.standard_normal(K0))), R + 1, 400).astype(np.int64)
-        ptr0 = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
-        X0, U0 = rows(np.repeat(np.arange(K0), lens))
-        rank = rng.permutation(K_max)
-        batches = []
-        K = K0
-        for t in range(ticks):
-            n = int(rng.poisson(50))
-            pop = (np.arange(1, K + 1) ** -1.2)[np.argsort(rank[:K])]
-            ids = np.sort(rng.choice(K, size=n, p=pop / pop.sum())) if n else np.zeros(0, np.int64)
-            uniq, cnt = np.unique(ids, return_counts=True)
-            X, _ = rows(ids)
-            new = None
-            if rng.random() < 0.05:
-                m = int(rng.integers(1, 61))
-                new = rows(np.full(m, K))[0]
-                K += 1
-            batches.append((uniq.astype(np.int32), np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64), X, new))
-        streams.append(dict(J=J, R=R, lam=lam, K0=K0, K_max=K_max, V=V, W=W[:K0], ptr0=ptr0, X0=X0, U0=U0,
-                            batches=batches))
-    return streams
+def _merge_cut(st, reqs):
+    """The rows of several requests of one stream as one update (ingest order)."""
+    groups, news = [], []
+    for q in reqs:
+        for l in range(len(q.new_ptr) - 1):
+            news.append(st.new_rows[q.n0 + q.new_ptr[l]:q.n0 + q.new_ptr[l + 1]])
+        for g in range(len(q.row_ids)):
+            groups.append((int(q.row_ids[g]), st.rows[q.r0 + q.row_ptr[g]:q.r0 + q.row_ptr[g + 1]]))
+    return groups, news
+
+
+def serve_oracle_leg(streams, cuts, gpu_fits, sample, budget_s):
+    """The FP64 oracle replays sampled streams with the server's cuts: its fit
+    after every update is compared with the update's reported fit; the replay
+    (one BLAS thread, then all threads) is the CPU baseline."""
+    import platform
+    from threadpoolctl import threadpool_limits
+    from oracle.dash_oracle import DashOracle
+    res = {"streams": [], "max_abs_dfit": 0.0, "updates_compared": 0}
+    cpu = {}
+    for label, limit, share in (("1 thread", 1, 0.6), ("all threads", None, 0.4)):
+        rows_tot, secs_tot = 0, 0.0
+        for i in sample:
+            st = streams[i]
+            with threadpool_limits(limits=limit):
+                o = DashOracle(st.J, st.R, st.lam)
+                p = st.init_ptr
+                o.init_from_factors([st.init_X[p[k]:p[k + 1]] for k in range(st.K0)],
+                                    [st.init_U[p[k]:p[k + 1]] for k in range(st.K0)], st.W[: st.K0], st.V)
+                secs, n = 0.0, 0
+                for c, f in zip(cuts[i], gpu_fits[i]):
+                    groups, news = _merge_cut(st, c)
+                    t = time.perf_counter()
+                    r = o.update(groups, news)
+                    secs += time.perf_counter() - t
+                    rows_tot += sum(x.shape[0] for _, x in groups) + sum(x.shape[0] for x in news)
+                    n += 1
+                    if limit == 1:
+                        d = abs(r.fit - f)
+                        res["max_abs_dfit"] = max(res["max_abs_dfit"], d)
+                        res["updates_compared"] += 1
+                    if secs >= budget_s * share / len(sample):
+                        break
+            secs_tot += secs
+            if limit == 1:
+                res["streams"].append({"stream": i, "J": st.J, "R": st.R, "K0": st.K0, "updates": n})
+        cores = limit if limit else (os.cpu_count() or 1)
+        cpu[label] = {"value": rows_tot / secs_tot if secs_tot > 0 else None, "threads": cores,
+                      "rows": rows_tot, "seconds": secs_tot}
+    res["within_1e-3"] = bool(res["updates_compared"] > 0 and res["max_abs_dfit"] <= 1e-3)
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    best = cpu["all threads"]
+    cpu_line = {"value": best["value"], "unit": "rows/s", "cores": best["threads"], "kind": "oracle",
+                "cpu_model": model, "nproc": os.cpu_count(), "single_thread": cpu["1 thread"]["value"],
+                "sample": f"the FP64 numpy oracle replaying the first updates of streams {list(sample)} with the "
+                          f"server's cuts: {cpu['1 thread']['rows']} rows in {cpu['1 thread']['seconds']:.1f} s on 1 "
+                          f"BLAS thread, {best['rows']} rows in {best['seconds']:.1f} s on {best['threads']}"}
+    return res, cpu_line
+
+
+def _json_default(o):
+    if isinstance(o, np.generic):
+        return o.item()
+    raise TypeError(type(o).__name__)
 
 
 def serve_main(args):
-    """Closed-loop serving measurement: every tick stages one batch per stream,
-    enqueues one update per stream (all concurrent, one HIP stream each) and
-    polls until all of them are committed.  Latency = host time from the tick
-    that cut an update to the poll that saw it committed."""
     import torch
     from paper_2305_18376_amd.dash import DashServer, PREC_FP32, PREC_MIXED
-    n_streams, T = 64, args.ticks
+    from paper_2305_18376_amd.synth import serving_streams
     prec = PREC_MIXED if args.precision == "mixed" else PREC_FP32
+    T_open, T_closed, n_streams = args.open_seconds, args.closed_seconds, args.streams
     t0 = time.time()
-    streams = serve_streams(n_streams, T)
+    streams = serving_streams(n_streams, seconds=T_open + T_closed)
     t_gen = time.time() - t0
     dev = torch.device("cuda", 0)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    M_CAP, G_CAP = 16384, 8192
+    kw_of = lambda st: dict(lam=st.lam, precision=prec, max_slices=st.K_max + 8, max_rows=M_CAP, max_groups=G_CAP)
     srv = DashServer(200 << 30)
-    views = []
-    for d in streams:
-        sid, g = srv.open(d["J"], d["R"], lam=d["lam"], max_slices=d["K_max"] + 8, max_rows=4096,
-                          max_groups=4096, precision=prec)
-        g.init_from_factors(d["ptr0"], to(d["X0"]), to(d["U0"]), to(d["W"]), to(d["V"]))
-        dbat = [(ids, ptr, to(X) if X.shape[0] else None, None if new is None else to(new))
-                for ids, ptr, X, new in d["batches"]]
-        views.append((sid, g, dbat))
+    sids, drows, dnew = [], [], []
+    for st in streams:
+        sid = srv.open(st.J, st.R, **kw_of(st))
+        srv.context(sid).init_from_factors(st.init_ptr, to(st.init_X), to(st.init_U), to(st.W[: st.K0]),
+                                           to(st.V))
+        sids.append(sid)
+        drows.append(to(st.rows))
+        dnew.append(to(st.new_rows))
     torch.cuda.synchronize()
+    idx_of_sid = {sid: i for i, sid in enumerate(sids)}
+    req_of = {}          # (sid, request id) -> request index
+    sent = [[] for _ in streams]   # request ids in submit order
+    reports = []
 
-    def run(sel, ticks, warm):
-        lat, rows_done, t_run = [], 0, 0.0
-        for t in range(ticks):
-            for i in sel:
-                _, g, dbat = views[i]
-                ids, ptr, X, new = dbat[t]
-                if new is not None:
-                    g.ingest_slices(np.array([0, new.shape[0]], np.int64), new)
-                if X is not None:
-                    g.ingest_rows(ids, ptr, X)
-            h0 = time.perf_counter()
-            srv.tick()
-            reps = srv.poll(wait=True)
-            dt = time.perf_counter() - h0
-            if t >= warm:
-                t_run += dt
-                lat += [r["latency_us"] for r in reps]
-                rows_done += sum(r["rows"] for r in reps)
-            assert all(r["committed"] for r in reps)
-        return np.array(lat), rows_done, t_run
+    def submit(i, qi):
+        st, q = streams[i], streams[i].requests[qi]
+        kw = {}
+        if q.n1 > q.n0:
+            kw = dict(new_ptr=q.new_ptr, new_rows=dnew[i][q.n0:q.n1])
+        if q.r1 > q.r0:
+            rid, _ = srv.submit(sids[i], q.row_ids, q.row_ptr, drows[i][q.r0:q.r1], **kw)
+        else:
+            rid, _ = srv.submit(sids[i], **kw)
+        req_of[(sids[i], rid)] = qi
+        sent[i].append(rid)
+        return rid
 
-    warm = 10
-    lat, rows_done, t_run = run(range(n_streams), T, warm)
-    out = {"metric": "serving: ingested rows/sec with p50/p99 cut-to-commit update latency",
-           "value": rows_done / t_run, "unit": "rows/s", "n_gpus": 1, "streams": n_streams,
-           "ticks": T - warm, "warmup": warm, "higher_is_better": True,
-           "latency_ms": {"p50": float(np.percentile(lat, 50)) / 1e3, "p99": float(np.percentile(lat, 99)) / 1e3},
-           "ms_per_tick": 1e3 * t_run / (T - warm),
-           "dtype": "f32" if args.precision == "fp32" else "bf16-mfma/f32", "data": "synthetic",
-           "config": {"workload": "64 streams, J~U{32,64,128,256}, R~U{8,16,32}, K0~U{100..300}, "
-                                  "Poisson(50) rows/tick over Zipf(1.2) slices, new slice p=0.05/tick",
-                      "budget_gb": 200, "closed_loop": True},
-           "gen_s": t_gen}
+    def collect():
+        got = srv.poll()
+        reports.extend(got)
+        return got
+
+    # warm-up: the first 0.2 s of every stream, then drain
+    srv.start(0)
+    warm = sorted((q.t, i, qi) for i, st in enumerate(streams) for qi, q in enumerate(st.requests) if q.t < 0.2)
+    for _, i, qi in warm:
+        submit(i, qi)
+    srv.drain(120000)
+    collect()
+    n_warm_reports = len(reports)
+
+    # open loop: each request submitted at its arrival time
+    sched = sorted((q.t, i, qi) for i, st in enumerate(streams) for qi, q in enumerate(st.requests)
+                   if 0.2 <= q.t < T_open)
+    lag = []
+    h0 = time.perf_counter()
+    t_base = sched[0][0] if sched else 0.0
+    last_poll = h0
+    for t, i, qi in sched:
+        target = h0 + (t - t_base)
+        now = time.perf_counter()
+        if target > now:
+            time.sleep(target - now)
+        lag.append(time.perf_counter() - target)
+        submit(i, qi)
+        if time.perf_counter() - last_poll > 0.005:
+            collect()
+            last_poll = time.perf_counter()
+    srv.drain(120000)
+    h1 = time.perf_counter()
+    collect()
+    open_reps = reports[n_warm_reports:]
+    open_lat = np.array([r["latency_us"] for r in open_reps]) / 1e3
+    open_rows = sum(r["rows"] for r in open_reps)
+    st_open = srv.stats()
+
+    # closed loop: four requests in flight per stream, profiled every 10th tick
+    todo = [[qi for qi, q in enumerate(st.requests) if q.t >= T_open] for st in streams]
+    nxt = [0] * n_streams
+    inflight = [0] * n_streams
+    done_upto = [0] * n_streams      # index into sent[i] of the first request not yet consumed
+    n_before = len(reports)
+    srv.profile(10)
+    h2 = time.perf_counter()
+    for i in range(n_streams):
+        while inflight[i] < 4 and nxt[i] < len(todo[i]):
+            submit(i, todo[i][nxt[i]])
+            nxt[i] += 1
+            inflight[i] += 1
+    remaining = sum(len(t) for t in todo)
+    consumed = 0
+    while consumed < remaining:
+        got = collect()
+        if not got:
+            time.sleep(50e-6)
+            continue
+        for r in got:
+            i = idx_of_sid[r["stream"]]
+            while done_upto[i] < len(sent[i]) and sent[i][done_upto[i]] <= r["last_request"]:
+                if req_of[(sids[i], sent[i][done_upto[i]])] >= (todo[i][0] if todo[i] else 1 << 60):
+                    inflight[i] -= 1
+                    consumed += 1
+                done_upto[i] += 1
+            while inflight[i] < 4 and nxt[i] < len(todo[i]):
+                submit(i, todo[i][nxt[i]])
+                nxt[i] += 1
+                inflight[i] += 1
+    h3 = time.perf_counter()
+    closed_reps = reports[n_before:]
+    closed_rows = sum(r["rows"] for r in closed_reps)
+    st_closed = srv.stats()
+    kstats, kticks = srv.profile_read()
+    srv.profile(0)
+    srv.stop()
+    all_committed = all(r["committed"] == 1 for r in reports)
+
+    # the sampled streams' cuts and fits, for the oracle
+    sample = sorted(range(n_streams), key=lambda i: streams[i].K0 * streams[i].J * streams[i].R)[:2]
+    cuts, fits = {}, {}
+    for i in sample:
+        mine = sorted((r for r in reports if r["stream"] == sids[i]), key=lambda r: r["step"])
+        c, k, prev = [], 0, 0
+        for r in mine:
+            grp = []
+            while k < len(sent[i]) and sent[i][k] <= r["last_request"]:
+                grp.append(streams[i].requests[req_of[(sids[i], sent[i][k])]])
+                k += 1
+            c.append(grp)
+        cuts[i], fits[i] = c, [r["fit"] for r in mine]
+
+    # dominant kernel of the closed loop
+    kern = max(kstats, key=lambda e: e["ms"]) if kstats else None
+    roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+    if kern and kern["ms"] > 0:
+        ach = kern["bytes"] / (kern["ms"] / 1e3) / 1e9
+        roof.update(achieved=ach, frac=ach / HBM_PEAK_GBS, kernel=kern["name"],
+                    avg_launch_us=1e3 * kern["ms"] / kern["launches"],
+                    algorithmic_bytes_per_launch=kern["bytes"] / kern["launches"],
+                    timing=f"HIP events on the server's stream around every launch of every 10th tick "
+                           f"({kticks} ticks timed)")
+        roof["traffic"] = counter_traffic(kern["name"].split("<")[0], "serve_mixed" if prec else "serve")
+    ticks_closed = st_closed["ticks"] - st_open["ticks"]
+    out = {
+        "metric": METRIC,
+        "value": closed_rows / (h3 - h2),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": ticks_closed,
+        "warmup": st_open["ticks"],
+        "ms_per_step": 1e3 * (h3 - h2) / max(ticks_closed, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mfma/f32" if prec == PREC_MIXED else "f32",
+        "data": "synthetic",
+        "config": {"workload": SERVE_WORKLOAD.format(n=n_streams, to=T_open, tc=T_closed),
+                   "streams": n_streams, "rows_closed_loop": closed_rows,
+                   "updates_closed_loop": len(closed_reps)},
+        "latency_ms": {"p50": float(np.percentile(open_lat, 50)), "p99": float(np.percentile(open_lat, 99)),
+                       "note": "open loop at the arrival times: submit of an update's first request to its "
+                               "commit seen by the server's loop thread"},
+        "open_loop": {"rows_per_s": open_rows / (h1 - h0), "offered_rows_per_s": 2000.0 * n_streams,
+                      "updates": len(open_reps), "ticks": st_open["ticks"],
+                      "submit_lag_ms_p99": 1e3 * float(np.percentile(lag, 99)) if lag else None},
+        "closed_loop": {"latency_ms_p50": float(np.percentile([r["latency_us"] for r in closed_reps], 50)) / 1e3,
+                        "latency_ms_p99": float(np.percentile([r["latency_us"] for r in closed_reps], 99)) / 1e3,
+                        "launches_per_tick": (st_closed["launches"] - st_open["launches"]) / max(ticks_closed, 1)},
+        "kernels_closed_loop": [{"name": e["name"], "avg_us": 1e3 * e["ms"] / e["launches"],
+                                 "gbps": e["bytes"] / (e["ms"] / 1e3) / 1e9 if e["ms"] > 0 else None}
+                                for e in sorted(kstats, key=lambda e: -e["ms"])],
+        "roofline": roof,
+        "all_committed": all_committed,
+        "gen_s": t_gen,
+    }
     srv.close()
-    print(json.dumps(out), flush=True)
+    del drows, dnew
+    torch.cuda.synchronize()
+    out["queueing"] = serve_queueing(streams[: n_streams], prec, kw_of, to)
+    if not args.no_oracle:
+        out["fit_check"], out["cpu_baseline"] = serve_oracle_leg(streams, cuts, fits, sample, args.oracle_seconds)
+    print(json.dumps(out, default=_json_default), flush=True)
+
+
+def serve_queueing(streams, prec, kw_of, to, budget=2 << 30, windows=10):
+    """Every stream asks for admission under a 2 GB budget; admitted streams
+    are initialised, serve their first requests and close, which admits the
+    ones waiting."""
+    from paper_2305_18376_amd.dash import DashServer
+    srv = DashServer(budget)
+    t0 = time.perf_counter()
+    sids = [srv.open(st.J, st.R, queue=True, **kw_of(st)) for st in streams]
+    admitted0 = sum(1 for s in sids if srv.state(s) == srv.OPEN)
+    srv.start(0)
+    served, peak_used, updates = set(), 0, 0
+    while len(served) < len(streams):
+        opened = [i for i, s in enumerate(sids) if i not in served and srv.state(s) == srv.OPEN]
+        if not opened:
+            break
+        keep = []
+        for i in opened:
+            st = streams[i]
+            srv.context(sids[i]).init_from_factors(st.init_ptr, to(st.init_X), to(st.init_U),
+                                                   to(st.W[: st.K0]), to(st.V))
+            rows = to(st.rows)
+            newr = to(st.new_rows) if st.new_rows.shape[0] else None
+            keep.append((rows, newr))
+            for q in st.requests[:windows]:
+                kw = {}
+                if q.n1 > q.n0:
+                    kw = dict(new_ptr=q.new_ptr, new_rows=newr[q.n0:q.n1])
+                if q.r1 > q.r0:
+                    srv.submit(sids[i], q.row_ids, q.row_ptr, rows[q.r0:q.r1], **kw)
+                else:
+                    srv.submit(sids[i], **kw)
+        srv.drain(120000)
+        updates += len(srv.poll())
+        peak_used = max(peak_used, srv.stats()["used"])
+        for i in opened:
+            srv.close_stream(sids[i])
+            served.add(i)
+        del keep
+    srv.stop()
+    wall = time.perf_counter() - t0
+    srv.close()
+    return {"budget_gb": budget / 2 ** 30, "streams": len(streams), "admitted_at_open": admitted0,
+            "queued_at_open": len(streams) - admitted0, "served": len(served), "updates": updates,
+            "peak_used_gb": peak_used / 2 ** 30, "wall_s": wall}
 
 
 if __name__ == "__main__":

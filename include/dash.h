@@ -421,6 +421,22 @@ dash_status dash_server_stop(dash_server *srv);
  * DASH_E_BAD_STATE. */
 dash_status dash_server_drain(dash_server *srv, int32_t timeout_ms);
 dash_status dash_server_get_stats(dash_server *srv, dash_server_stats *out);
+/* Device time of the server's kernels, per kernel instantiation. */
+typedef struct dash_kernel_stat {
+  char name[48];        /* e.g. "k_solve<16>" (stage kernel and template arguments) */
+  int64_t launches;     /* timed launches                                          */
+  double ms;            /* their summed device time (HIP events around each launch,
+                           on the server's stream)                                 */
+  double bytes;         /* their summed algorithmic bytes                          */
+} dash_kernel_stat;
+/* Time every launch of every `every`-th tick from now on (0: stop); clears the
+ * statistics.  Events sit between the timed launches, so the timed ticks run
+ * slightly slower than the others. */
+dash_status dash_server_profile(dash_server *srv, int32_t every);
+/* The statistics so far (waits for the timed ticks): at most cap entries into
+ * out, *n the count, *ticks (may be NULL) the ticks timed. */
+dash_status dash_server_profile_read(dash_server *srv, dash_kernel_stat *out, int32_t cap, int32_t *n,
+                                     int64_t *ticks);
 /* Text of the server's last launch error ("" if none). */
 const char *dash_server_last_error(dash_server *srv);
 

@@ -166,6 +166,8 @@ struct BuiltUpdate {
   int cand = -1;           // autotuning candidate
   bool scored = false;
   void *report = nullptr;  // device address of the report
+  int K = 0;               // slices after the update
+  int64_t rows = 0;        // rows it consumes
 };
 
 dash_status fail(dash_ctx *c, dash_status s, const char *fmt, ...);

@@ -295,6 +295,10 @@ struct FetchJob {
 int launch_fetch_list(const FetchJob *jobs_mapped, int n_jobs, int64_t max_bytes, hipStream_t s);
 // LDS of the row stage's deferred-slice kernel.
 size_t split_rows_slow_lds(int J, int R);
+// Name of the kernel instantiation a split-sweep stage launches for arguments
+// a (stage: 0 rows, 1 deferred slices, 2 solve, 3 F, 4 group reduction, 5
+// final phase), e.g. "k_solve<16>"; written into buf (n bytes).
+void split_kernel_name(int stage, const PassArgs &a, char *buf, size_t n);
 // Dynamic LDS of a sweep launch that also runs the final phase, or 0 when the
 // two do not fit one workgroup.
 size_t fused_pass_lds(int variant, int J, int R);

@@ -1134,6 +1134,8 @@ dash_status build_update(dash_ctx *c, BuiltUpdate *bu) {
   bu->cand = cand;
   bu->scored = c->anom_window > 0;
   bu->report = h->report;
+  bu->K = K;
+  bu->rows = c->rows_pending;
   return DASH_OK;
 }
 

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -100,7 +101,31 @@ struct Launch {
   size_t map_off;     // byte offset of its block map in the table
   int n_blocks;
   size_t lds;         // the largest member's dynamic LDS
+  double bytes;       // algorithmic bytes of its members' work
 };
+
+// A timed launch waiting for its events to be read.
+struct ProfRec {
+  hipEvent_t a, b;
+  int entry;          // index into the per-kernel statistics
+  double bytes;
+};
+
+// Algorithmic bytes one stage must move for one stream's update (the model
+// of the design notes): w = 2 words per Y_k / D_k entry in the mixed path
+// (value and compensation), 1 in float32.
+double stage_bytes(int stage, const dash_ctx *c, const BuiltUpdate &b) {
+  const double J = c->J, R = c->R, M = (double)b.rows, K = b.K, Kt = b.n_items;
+  const double w = c->cfg.precision == DASH_PREC_MIXED ? 2.0 : 1.0;
+  switch (stage) {
+    case 0: return M * J * 4 + M * R * 4 + Kt * (2 * w * (R * J + R * R) * 4 + 16 + R * 8);
+    case 1: return 0.0;   // deferred slices: counted with the row stage
+    case 2: return (K - Kt) * R * J * 4 + K * w * R * R * 4 + K * (2 * R * 8 + 8) + Kt * R * 8;
+    case 3: return K * R * J * 4 + K * R * 8;
+    case 4: return ((double)b.nch / kChunksPerRGroup + 1) * (R * J + R * R) * 8;
+    default: return 2 * (R * J + R * R) * 8;
+  }
+}
 
 }  // namespace
 
@@ -125,6 +150,12 @@ struct dash_server {
   int64_t next_request = 1;
   dash_server_stats stats{};
   std::string err;
+  // profiling: HIP events around every launch of every prof_every-th tick
+  int prof_every = 0;
+  int64_t prof_ticks = 0;
+  std::vector<ProfRec> prof_pending;
+  std::vector<dash_kernel_stat> prof_stats;
+  std::vector<hipEvent_t> tev_pool;   // timing events
 };
 
 namespace {
@@ -275,6 +306,42 @@ dash_status stage_requests(dash_server *srv, Stream &st, Cut *cut, int *n_req) {
   return DASH_OK;
 }
 
+hipEvent_t take_timing_event(dash_server *srv) {
+  if (!srv->tev_pool.empty()) {
+    hipEvent_t e = srv->tev_pool.back();
+    srv->tev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Read the timed launches' events into the statistics (the stream is idle).
+dash_status prof_fold(dash_server *srv) {
+  for (const ProfRec &p : srv->prof_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) return DASH_E_DEVICE;
+    dash_kernel_stat &st = srv->prof_stats[p.entry];
+    st.launches += 1;
+    st.ms += ms;
+    st.bytes += p.bytes;
+    srv->tev_pool.push_back(p.a);
+    srv->tev_pool.push_back(p.b);
+  }
+  srv->prof_pending.clear();
+  return DASH_OK;
+}
+
+int prof_entry(dash_server *srv, const char *name) {
+  for (size_t i = 0; i < srv->prof_stats.size(); ++i)
+    if (std::strncmp(srv->prof_stats[i].name, name, sizeof srv->prof_stats[i].name) == 0) return (int)i;
+  dash_kernel_stat st{};
+  std::snprintf(st.name, sizeof st.name, "%s", name);
+  srv->prof_stats.push_back(st);
+  return (int)srv->prof_stats.size() - 1;
+}
+
 void append_map(std::vector<BlockMap> &maps, const PassArgs *ad, int n) {
   for (int l = 0; l < n; ++l) maps.push_back(BlockMap{ad, l, n});
 }
@@ -344,6 +411,7 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
         L.map_off = maps.size();
         L.n_blocks = 0;
         L.lds = 0;
+        L.bytes = 0.0;
         for (int i : cl.second) {
           const dash_ctx *c = sel[i].c;
           const BuiltUpdate &b = sel[i].b;
@@ -362,6 +430,7 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
           }
           append_map(maps, ad, n);
           L.n_blocks += n;
+          L.bytes += stage_bytes(stage, c, b);
           L.lds = std::max(L.lds, lds);
         }
         PassArgs a = base_args_at(sel[cl.second[0]].c, sel[cl.second[0]].b.dblk);
@@ -402,8 +471,22 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
     if (hipEventRecord(x.c->stage_ev[x.b.stage], s) != hipSuccess) return DASH_E_DEVICE;
     x.c->stage_used[x.b.stage] = true;
   }
+  const bool timed = srv->prof_every > 0 && srv->stats.ticks % srv->prof_every == 0;
+  if (timed && srv->prof_pending.size() > 4096) {
+    if (hipStreamSynchronize(s) != hipSuccess) return DASH_E_DEVICE;
+    if (dash_status st = prof_fold(srv)) return st;
+  }
   for (const Launch &L : launches) {
     const BlockMap *m = dmaps + L.map_off;
+    ProfRec pr{nullptr, nullptr, 0, L.bytes};
+    if (timed) {
+      char name[48];
+      split_kernel_name(L.stage, L.rep, name, sizeof name);
+      pr.entry = prof_entry(srv, name);
+      pr.a = take_timing_event(srv);
+      pr.b = take_timing_event(srv);
+      if (!pr.a || !pr.b || hipEventRecord(pr.a, s) != hipSuccess) return DASH_E_DEVICE;
+    }
     int e = 0;
     switch (L.stage) {
       case 0: e = launch_split_rows(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
@@ -414,7 +497,12 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
       default: e = launch_finish_dev(L.rep, nullptr, m, L.n_blocks, 0, s, L.lds); break;
     }
     if (e) return dev_fail(e);
+    if (timed) {
+      if (hipEventRecord(pr.b, s) != hipSuccess) return DASH_E_DEVICE;
+      srv->prof_pending.push_back(pr);
+    }
   }
+  if (timed) srv->prof_ticks += 1;
   for (const Sel &x : sel) {
     if (!x.b.scored) continue;
     // anomaly scores of a stream that has them on (Definitions 1-2)
@@ -505,6 +593,11 @@ dash_status dash_server_destroy(dash_server *srv) {
     if (t.ev) (void)hipEventDestroy(t.ev);
   for (auto e : srv->ticks_in_flight) srv->ev_pool.push_back(e);
   for (auto e : srv->ev_pool) (void)hipEventDestroy(e);
+  for (const ProfRec &p : srv->prof_pending) {
+    srv->tev_pool.push_back(p.a);
+    srv->tev_pool.push_back(p.b);
+  }
+  for (auto e : srv->tev_pool) (void)hipEventDestroy(e);
   if (srv->stream) (void)hipStreamDestroy(srv->stream);
   delete srv;
   return DASH_OK;
@@ -727,6 +820,29 @@ dash_status dash_server_get_stats(dash_server *srv, dash_server_stats *out) {
   int32_t open = 0;
   for (const Stream &st : srv->streams) open += st.state == kStateOpen ? 1 : 0;
   out->open = open;
+  return DASH_OK;
+}
+
+dash_status dash_server_profile(dash_server *srv, int32_t every) {
+  if (!srv || every < 0) return DASH_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->stream && hipStreamSynchronize(srv->stream) != hipSuccess) return DASH_E_DEVICE;
+  if (dash_status s = prof_fold(srv)) return s;
+  srv->prof_every = every;
+  srv->prof_stats.clear();
+  srv->prof_ticks = 0;
+  return DASH_OK;
+}
+
+dash_status dash_server_profile_read(dash_server *srv, dash_kernel_stat *out, int32_t cap, int32_t *n,
+                                     int64_t *ticks) {
+  if (!srv || !n || cap < 0 || (cap > 0 && !out)) return DASH_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->stream && hipStreamSynchronize(srv->stream) != hipSuccess) return DASH_E_DEVICE;
+  if (dash_status s = prof_fold(srv)) return s;
+  *n = (int32_t)std::min<size_t>(srv->prof_stats.size(), (size_t)cap);
+  for (int32_t i = 0; i < *n; ++i) out[i] = srv->prof_stats[i];
+  if (ticks) *ticks = srv->prof_ticks;
   return DASH_OK;
 }
 

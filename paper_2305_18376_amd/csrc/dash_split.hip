@@ -28,6 +28,8 @@
 // (w_k does not depend on the common factor lambda^dt) and enter F and G with
 // sigma_k = lambda^dt.  See dash_dev.h for the layouts.
 #include <hip/hip_runtime.h>
+
+#include <cstdio>
 #include <math.h>
 
 #include <algorithm>
@@ -1172,6 +1174,23 @@ static size_t rows_fast_lds(int J, int R, bool mixed) {
 
 size_t split_rows_lds(int J, int R, int mixed) { return rows_fast_lds(J, R, mixed != 0); }
 size_t split_rows_slow_lds(int J, int R) { return rows_lds(J, R).bytes; }
+
+void split_kernel_name(int stage, const PassArgs &a, char *buf, size_t n) {
+  const int mx = a.mixed ? 1 : 0;
+  switch (stage) {
+    case 0: snprintf(buf, n, "k_rows<%d, %d, %s, false>", rw_bucket(a.R), jw_bucket(a.J), mx ? "true" : "false"); break;
+    case 1: snprintf(buf, n, "k_rows<8, 4, %s, true>", mx ? "true" : "false"); break;
+    case 2: snprintf(buf, n, "k_solve<%d>", rm_bucket(a.R)); break;
+    case 3:
+      if (a.lagged && a.mode == 0)
+        snprintf(buf, n, "k_fsum_rows<%d, %d, %s>", rw_bucket(a.R), jw_bucket(a.J), mx ? "true" : "false");
+      else
+        snprintf(buf, n, "k_fsum<%d>", ept_bucket(a.ys));
+      break;
+    case 4: snprintf(buf, n, "k_reduce_groups"); break;
+    default: snprintf(buf, n, "k_finish_dev<%d>", finish_class(a.R)); break;
+  }
+}
 size_t split_solve_lds(int J, int R) { return solve_lds(J, R).bytes; }
 size_t split_fsum_lds(int J, int R, int lagged) {
   if (lagged) return rows_lds(J, R).bytes;

@@ -80,6 +80,13 @@ class ServerReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double)]
+
+    def as_dict(self):
+        return {"name": self.name.decode(), "launches": self.launches, "ms": self.ms, "bytes": self.bytes}
+
+
 class ServerStats(C.Structure):
     _fields_ = [("ticks", C.c_int64), ("launches", C.c_int64), ("updates", C.c_int64), ("rows", C.c_int64),
                 ("budget", C.c_int64), ("used", C.c_int64), ("queued", C.c_int32), ("open", C.c_int32)]
@@ -136,6 +143,9 @@ _SIGS = {
     "dash_server_drain": (C.c_int, [_P, C.c_int32]),
     "dash_server_get_stats": (C.c_int, [_P, C.POINTER(ServerStats)]),
     "dash_server_last_error": (C.c_char_p, [_P]),
+    "dash_server_profile": (C.c_int, [_P, C.c_int32]),
+    "dash_server_profile_read": (C.c_int, [_P, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int64)]),
 }
 
 _lib = None
@@ -502,6 +512,17 @@ class DashServer:
 
     def drain(self, timeout_ms=-1):
         self._check(lib().dash_server_drain(self._h, int(timeout_ms)), "dash_server_drain")
+
+    def profile(self, every=10):
+        self._check(lib().dash_server_profile(self._h, int(every)), "dash_server_profile")
+
+    def profile_read(self, cap=64):
+        out = (KernelStat * cap)()
+        n = C.c_int32()
+        t = C.c_int64()
+        self._check(lib().dash_server_profile_read(self._h, out, cap, C.byref(n), C.byref(t)),
+                    "dash_server_profile_read")
+        return [out[i].as_dict() for i in range(n.value)], t.value
 
     def stats(self):
         s = ServerStats()

@@ -298,3 +298,124 @@ def make_workload(name: str, **kw) -> Workload:
     }[name]
     base.update(kw)
     return _iid(name, **base)
+
+
+# --------------------------------------------------------------------------
+# Serving workload: many independent streams with Poisson arrivals
+# --------------------------------------------------------------------------
+@dataclass
+class Request:
+    """The rows one stream received in one cut window (ingest order): groups
+    of existing slices, rows[r0:r1] of the stream's row array, and new slices,
+    new_rows[n0:n1] of its new-slice array."""
+    t: float                     # window end (seconds of the stream's clock)
+    row_ids: np.ndarray          # int32 [n]
+    row_ptr: np.ndarray          # int64 [n+1], relative to r0
+    r0: int
+    r1: int
+    new_ptr: np.ndarray          # int64 [L+1], relative to n0
+    n0: int
+    n1: int
+
+    @property
+    def M(self) -> int:
+        return (self.r1 - self.r0) + (self.n1 - self.n0)
+
+
+@dataclass
+class ServedStream:
+    J: int
+    R: int
+    lam: float
+    K0: int
+    V: np.ndarray = field(repr=False)           # J x R
+    W: np.ndarray = field(repr=False)           # K_max x R
+    init_ptr: np.ndarray = field(repr=False)    # int64 [K0+1]
+    init_X: np.ndarray = field(repr=False)      # float32
+    init_U: np.ndarray = field(repr=False)      # float64
+    rows: np.ndarray = field(repr=False)        # float32 [N, J], every request's rows
+    new_rows: np.ndarray = field(repr=False)    # float32 [N_new, J]
+    requests: list = field(repr=False, default_factory=list)
+
+    @property
+    def K_max(self) -> int:
+        return int(self.W.shape[0])
+
+
+def serving_streams(n_streams=64, seconds=10.0, seed=5000, window=0.025, rate=2000.0, new_rate=2.0,
+                    init_median=24, init_hi=200):
+    """The serving workload's streams, stream s seeded with seed + s.
+
+    Per stream: J ~ U{32,64,128,256}, R ~ U{8,16,32}, K0 ~ U{500..5000},
+    lambda = 0.95; planted rows x = (u * w_k) V^T + 5 % noise (u ~ N(0,1)^R,
+    w_k ~ U[0.5,1.5]^R, V ~ N(0,1)).  Rows arrive as a Poisson process of
+    `rate` rows per second, each to an existing slice drawn by Zipf(1.2)
+    popularity over a random ranking of the slices; new slices arrive as a
+    Poisson process of `new_rate` per second with U{1..60} rows.  A request is
+    one `window` of a stream's clock (the windows of different streams are
+    offset by a random phase).  Initial slices have log-normal lengths of
+    median `init_median` (sigma 1, clipped to [R+1, init_hi]): the cost of an
+    update depends on the number of slices, not on the rows that built them."""
+    out = []
+    for s in range(n_streams):
+        rng = _rng(seed + s, 0)
+        J = int(rng.choice([32, 64, 128, 256]))
+        R = int(rng.choice([8, 16, 32]))
+        K0 = int(rng.integers(500, 5001))
+        n_new_max = int(rng.poisson(new_rate * seconds)) + 1
+        K_max = K0 + n_new_max
+        V = rng.standard_normal((J, R))
+        W = rng.uniform(0.5, 1.5, size=(K_max, R))
+        lens = _lognormal_lengths(rng, K0, init_median, R + 1, init_hi)
+
+        def draw(ids, g):
+            u = g.standard_normal((len(ids), R))
+            w = W[ids]
+            x = (u * w) @ V.T
+            x += 0.05 * np.sqrt((w * w).sum(axis=1))[:, None] * g.standard_normal(x.shape)
+            return x.astype(np.float32), u
+
+        init_ptr = _ptr(lens)
+        init_X, init_U = draw(np.repeat(np.arange(K0), lens), _rng(seed + s, 1))
+        g = _rng(seed + s, 2)
+        rank = g.permutation(K_max)
+        # arrival times over the whole run
+        n_rows = int(g.poisson(rate * seconds))
+        t_rows = np.sort(g.uniform(0.0, seconds, size=n_rows))
+        n_new = min(int(g.poisson(new_rate * seconds)), n_new_max)
+        t_new = np.sort(g.uniform(0.0, seconds, size=n_new))
+        new_len = g.integers(1, 61, size=n_new)
+        phase = g.uniform(0.0, window)
+        edges = np.arange(phase, seconds + window, window)
+        ids_all = np.empty(n_rows, dtype=np.int64)
+        reqs = []
+        K = K0
+        pop_K, cdf = -1, None
+        r_at, n_at, i_new = 0, 0, 0
+        for e in edges:
+            # new slices of this window (they join the ranking at once)
+            L0 = i_new
+            while i_new < n_new and t_new[i_new] < e:
+                i_new += 1
+            r_end = int(np.searchsorted(t_rows, e))
+            m = r_end - r_at
+            if K != pop_K:
+                p = (np.argsort(np.argsort(rank[:K])) + 1.0) ** -1.2
+                cdf = np.cumsum(p / p.sum())
+                pop_K = K
+            ids = np.minimum(np.searchsorted(cdf, g.uniform(size=m)), K - 1)
+            order = np.argsort(ids, kind="stable")
+            ids_all[r_at:r_end] = ids[order]
+            uniq, cnt = np.unique(ids, return_counts=True)
+            nl = new_len[L0:i_new]
+            if m or i_new > L0:
+                reqs.append(Request(float(e), uniq.astype(np.int32), _ptr(cnt), r_at, r_end, _ptr(nl), n_at,
+                                    n_at + int(nl.sum())))
+            r_at = r_end
+            n_at += int(nl.sum())
+            K += i_new - L0
+        rows, _ = draw(ids_all, _rng(seed + s, 3))
+        new_ids = np.repeat(np.arange(K0, K0 + n_new), new_len)
+        new_rows, _ = draw(new_ids, _rng(seed + s, 4))
+        out.append(ServedStream(J, R, 0.95, K0, V, W, init_ptr, init_X, init_U, rows, new_rows, reqs))
+    return out
