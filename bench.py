@@ -8,7 +8,7 @@ to Zipf(1.2)-popular slices plus 2 new slices/s of U{1..60} rows, cut into
 thread batches every stream's pending requests into one tick.  A "step" is
 one tick.  Three phases on the same streams: an open-loop replay at the
 arrival times (p50/p99 latency from a request's submit to its update's
-commit), a closed-loop run with four requests in flight per stream (the
+commit), a closed-loop run with eight requests in flight per stream (the
 headline rows/s: every row of the phase over its wall time, inputs resident
 in HBM), and a 2 GB-budget run in which streams wait for admission.  The
 sampled streams' per-update fits are checked against the FP64 oracle fed the
@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--closed-seconds", type=float, default=4.0,
                     help="serve: stream time replayed closed-loop after the open-loop phase")
     ap.add_argument("--streams", type=int, default=64, help="serve: number of streams")
+    ap.add_argument("--closed-depth", type=int, default=8, help="serve: requests in flight per stream, closed loop")
     ap.add_argument("--autotune", type=int, default=0,
                     help="N > 0: the warm-up updates try every launch schedule N times and keep the fastest")
     ap.add_argument("--graph", type=int, default=0,
@@ -310,7 +311,7 @@ SERVE_WORKLOAD = ("serving: {n} streams, J~U{{32,64,128,256}}, R~U{{8,16,32}}, K
                   "update cost depends on the slice count, not on the rows that built them), lambda=0.95, "
                   "Poisson 2000 rows/s/stream to Zipf(1.2)-popular slices + Poisson 2 new slices/s of U{{1..60}} "
                   "rows, 25 ms requests, admission budget 200 GB; open loop {to:g} s at the arrival times, closed "
-                  "loop over the next {tc:g} s of stream time with 4 requests in flight per stream")
+                  "loop over the next {tc:g} s of stream time with {qd} requests in flight per stream")
 
 
 def _merge_cut(st, reqs):
@@ -415,15 +416,30 @@ def serve_main(args):
     sent = [[] for _ in streams]   # request ids in submit order
     reports = []
 
+    # every request's C arguments, prepared before the timed phases (the row
+    # buffers stay alive in drows / dnew for the whole run)
+    import ctypes as C
+    from paper_2305_18376_amd.dash import lib as _lib
+    L, hsrv = _lib(), srv._h
+    cargs = []
+    for i, st in enumerate(streams):
+        rb, nb, J4 = drows[i].data_ptr(), dnew[i].data_ptr(), 4 * st.J
+        per = []
+        for q in st.requests:
+            ng, nn = len(q.row_ids), len(q.new_ptr) - 1
+            per.append((sids[i], ng, q.row_ids.ctypes.data if ng else None, q.row_ptr.ctypes.data if ng else None,
+                        rb + q.r0 * J4 if ng else None, nn, q.new_ptr.ctypes.data if nn else None,
+                        nb + q.n0 * J4 if nn else None))
+        cargs.append(per)
+    rid_box = C.c_int64()
+    rid_ref = C.byref(rid_box)
+
     def submit(i, qi):
-        st, q = streams[i], streams[i].requests[qi]
-        kw = {}
-        if q.n1 > q.n0:
-            kw = dict(new_ptr=q.new_ptr, new_rows=dnew[i][q.n0:q.n1])
-        if q.r1 > q.r0:
-            rid, _ = srv.submit(sids[i], q.row_ids, q.row_ptr, drows[i][q.r0:q.r1], **kw)
-        else:
-            rid, _ = srv.submit(sids[i], **kw)
+        a = cargs[i][qi]
+        st = L.dash_server_submit(hsrv, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], None, rid_ref, None)
+        if st != 0:
+            raise RuntimeError(f"dash_server_submit: status {st}")
+        rid = rid_box.value
         req_of[(sids[i], rid)] = qi
         sent[i].append(rid)
         return rid
@@ -467,7 +483,7 @@ def serve_main(args):
     open_rows = sum(r["rows"] for r in open_reps)
     st_open = srv.stats()
 
-    # closed loop: four requests in flight per stream, profiled every 10th tick
+    # closed loop: QD requests in flight per stream, profiled every 10th tick
     todo = [[qi for qi, q in enumerate(st.requests) if q.t >= T_open] for st in streams]
     nxt = [0] * n_streams
     inflight = [0] * n_streams
@@ -475,8 +491,9 @@ def serve_main(args):
     n_before = len(reports)
     srv.profile(10)
     h2 = time.perf_counter()
+    QD = args.closed_depth
     for i in range(n_streams):
-        while inflight[i] < 4 and nxt[i] < len(todo[i]):
+        while inflight[i] < QD and nxt[i] < len(todo[i]):
             submit(i, todo[i][nxt[i]])
             nxt[i] += 1
             inflight[i] += 1
@@ -494,7 +511,7 @@ def serve_main(args):
                     inflight[i] -= 1
                     consumed += 1
                 done_upto[i] += 1
-            while inflight[i] < 4 and nxt[i] < len(todo[i]):
+            while inflight[i] < QD and nxt[i] < len(todo[i]):
                 submit(i, todo[i][nxt[i]])
                 nxt[i] += 1
                 inflight[i] += 1
@@ -546,7 +563,7 @@ def serve_main(args):
         "vs_baseline": None,
         "dtype": "bf16-mfma/f32" if prec == PREC_MIXED else "f32",
         "data": "synthetic",
-        "config": {"workload": SERVE_WORKLOAD.format(n=n_streams, to=T_open, tc=T_closed),
+        "config": {"workload": SERVE_WORKLOAD.format(n=n_streams, to=T_open, tc=T_closed, qd=args.closed_depth),
                    "streams": n_streams, "rows_closed_loop": closed_rows,
                    "updates_closed_loop": len(closed_reps)},
         "latency_ms": {"p50": float(np.percentile(open_lat, 50)), "p99": float(np.percentile(open_lat, 99)),

@@ -64,10 +64,18 @@ hipError_t dalloc(T **p, size_t bytes) {
 void split_chunks(const dash_ctx *c, int K, int *c3_out, int *c2_out) {
   const int n = std::max(1, c->n_cu);
   int c3 = std::max(1, (K + 2 * n - 1) / (2 * n));
+  // a served stream shares the device: F chunks of about kServeChunkBytes of
+  // Y each, whatever the slice size
+  if (c->served) c3 = std::max(1, (int)(kServeChunkBytes / (4 * (int64_t)y_stride(c->J, c->R))));
   if (c->chunk_override > 0) c3 = c->chunk_override;
   c3 *= c->sched.spread;
-  int c2 = std::max(1, std::min(c3, (K + 8 * n - 1) / (8 * n)));
-  while ((K + c2 - 1) / c2 > kMaxChunks2) ++c2;
+  // solve chunks: two workgroups per CU (one resident round), a multiple of
+  // the workgroup's four waves; a served stream plans them for the whole
+  // device (short chunks: its latency, not its own throughput, matters)
+  const int ns = c->served ? kServeSolveCUs : n;
+  int c2 = std::max(1, std::min(c3, (K + 2 * ns - 1) / (2 * ns)));
+  c2 = (c2 + 3) / 4 * 4;
+  while ((K + c2 - 1) / c2 > kMaxChunks2) c2 += 4;
   c3 = std::max(c3, c2);
   c3 = (c3 + c2 - 1) / c2 * c2;
   while ((K + c3 - 1) / c3 > kMaxChunks) c3 += c2;

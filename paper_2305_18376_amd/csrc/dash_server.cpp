@@ -393,10 +393,12 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
         switch (stage) {
           case 0: key = split_rows_class(c->J, c->R, mixed); break;
           case 1: key = mixed; break;
-          case 2: key = split_solve_class(c->R); break;
+          // solve and final phase: one launch for every class; the F stage per
+          // class (its instantiations differ in registers and occupancy)
+          case 2: key = 0; break;
           case 3: key = split_fsum_class(c->J, c->R, lagged, mixed); break;
           case 4: key = 0; break;
-          default: key = finish_class(c->R); break;
+          default: key = 0; break;
         }
         auto it = std::find_if(classes.begin(), classes.end(), [&](const auto &e) { return e.first == key; });
         if (it == classes.end()) {
@@ -481,7 +483,10 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
     ProfRec pr{nullptr, nullptr, 0, L.bytes};
     if (timed) {
       char name[48];
-      split_kernel_name(L.stage, L.rep, name, sizeof name);
+      if (L.stage == 2 || L.stage == 5)
+        std::snprintf(name, sizeof name, "%s", L.stage == 2 ? "k_solve_any" : "k_finish_dev_any");
+      else
+        split_kernel_name(L.stage, L.rep, name, sizeof name);
       pr.entry = prof_entry(srv, name);
       pr.a = take_timing_event(srv);
       pr.b = take_timing_event(srv);
@@ -491,10 +496,10 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
     switch (L.stage) {
       case 0: e = launch_split_rows(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 1: e = launch_split_rows_slow(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
-      case 2: e = launch_split_solve(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
+      case 2: e = launch_split_solve_any(m, L.n_blocks, s, L.lds); break;
       case 3: e = launch_split_fsum(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 4: e = launch_reduce_groups(nullptr, m, L.n_blocks, s); break;
-      default: e = launch_finish_dev(L.rep, nullptr, m, L.n_blocks, 0, s, L.lds); break;
+      default: e = launch_finish_dev_any(m, L.n_blocks, s, L.lds); break;
     }
     if (e) return dev_fail(e);
     if (timed) {

@@ -631,12 +631,14 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
 // Solve stage
 // ---------------------------------------------------------------------------
 struct SolveLds {
-  size_t oVtV, oVt, oC, oInfo, oScr, bytes;
+  size_t oVtV, oVt, oW, oScr, bytes;
 };
 
-// V^T V (FP64), V^T (float, R x J), the waves' c_k (4 x R), the waves' slices
-// for the G sums (4 x (R + 4): w_k, sigma_k, D_k, its compensation, n_k), and
-// the shared pseudo-inverse scratch.
+constexpr int kSolveWaves = 4;   // waves of a solve workgroup
+
+// V^T V (FP64), V^T (float, R x J), each wave's w_k (for its G terms), and a
+// scratch shared by the pseudo-inverse of deferred slices and the final
+// combination of the waves' G partials.
 __host__ __device__ inline SolveLds solve_lds(int J, int R) {
   SolveLds L;
   size_t o = 0;
@@ -644,56 +646,203 @@ __host__ __device__ inline SolveLds solve_lds(int J, int R) {
   o += (size_t)R * R * 8;
   L.oVt = o;
   o = align_up(o + (size_t)R * J * 4, 16);
-  L.oC = o;
-  o += (size_t)4 * R * 8;
-  L.oInfo = o;
-  o += (size_t)4 * (R + 4) * 8;
+  L.oW = o;
+  o += (size_t)kSolveWaves * R * 8;
   L.oScr = o;
-  o += (size_t)(2 * R * R + R + 3 * 64) * 8 + 64 * 4;
+  const size_t pinv = (size_t)(2 * R * R + 2 * R + 3 * 64) * 8 + 64 * 4;
+  const size_t comb = (size_t)(R * R + kSolveWaves) * 8;
+  o += pinv > comb ? pinv : comb;
   L.bytes = align_up(o, 16);
   return L;
 }
 
 // c_r = sum_j Y_k[r][j] V[j][r] of one slice by one wave, FP64 sums of the
-// float products.  Eight ranks at a time: lane l takes rank r0 + l / 8 and the
-// columns j = l mod 8 + 8 t; the eight lanes of a rank add their partials
-// with three exchanges, and the sums go to sc[r] (LDS, this wave's).
-__device__ inline void slice_c(const float *__restrict__ Yk, const float *sVt, int J, int R, double *sc) {
+// float products.  Lane l takes ranks r0 + l / 8 (r0 = 0, 8, ...) and, when
+// rows are 16-byte aligned, the float4 columns 4 (l mod 8) + 32 t: a load
+// instruction reads eight whole 128-byte runs, and every load of the slice
+// (R J / 256 float4 per lane, J <= 256) is issued before the first product
+// (for R > 16: those of eight ranks at a time, for the registers), so the
+// slice waits for one or a few memory latencies, not one per batch.  The eight
+// lanes of a rank add their partials with three exchanges.  Returns c_lane
+// (lane < R).
+template <int RM>
+__device__ inline double slice_c(const float *__restrict__ Yk, const float *sVt, int J, int R, double *sc) {
   const int lane = threadIdx.x & 63;
   const int q = lane >> 3, c8 = lane & 7;
-  for (int r0 = 0; r0 < R; r0 += 8) {
-    const int r = r0 + q;
-    double p = 0.0;
-    if (r < R) {
-      const float *yr = Yk + r * J;
-      const float *vr = sVt + r * J;
-      int j = c8;
-      for (; j + 56 < J; j += 64) {
-        float y[8];
+  constexpr int NG = (RM + 7) / 8;      // groups of eight ranks
+  constexpr int GB = RM >= 32 ? 1 : NG;  // groups whose loads are in flight together (registers)
+  if ((J & 3) == 0) {
+    const int J4 = J >> 2;
+#pragma unroll 1
+    for (int g0 = 0; g0 < NG; g0 += GB) {
+    float4 y[GB][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) y[u] = yr[j + 8 * u];
+    for (int gg = 0; gg < GB; ++gg) {
+      const int r = 8 * (g0 + gg) + q;
+      const float4 *yr = reinterpret_cast<const float4 *>(Yk + r * J);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) p = fma((double)y[u], (double)vr[j + 8 * u], p);
+      for (int t = 0; t < 8; ++t) {
+        const int j4 = c8 + 8 * t;
+        y[gg][t] = (r < R && j4 < J4) ? yr[j4] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      for (; j < J; j += 8) p = fma((double)yr[j], (double)vr[j], p);
     }
-    p += __shfl_xor(p, 1, 64);
-    p += __shfl_xor(p, 2, 64);
-    p += __shfl_xor(p, 4, 64);
-    if (c8 == 0 && r < R) sc[r] = p;
+#pragma unroll
+    for (int gg = 0; gg < GB; ++gg) {
+      const int g = gg;
+      const int r = 8 * (g0 + gg) + q;
+      double p = 0.0;
+      if (r < R) {
+        const float4 *vr = reinterpret_cast<const float4 *>(sVt + r * J);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int j4 = c8 + 8 * t;
+          if (j4 < J4) {
+            const float4 v = vr[j4];
+            p = fma((double)y[g][t].x, (double)v.x, p);
+            p = fma((double)y[g][t].y, (double)v.y, p);
+            p = fma((double)y[g][t].z, (double)v.z, p);
+            p = fma((double)y[g][t].w, (double)v.w, p);
+          }
+        }
+      }
+      p += __shfl_xor(p, 1, 64);
+      p += __shfl_xor(p, 2, 64);
+      p += __shfl_xor(p, 4, 64);
+      if (c8 == 0 && r < R) sc[r] = p;
+    }
+    }
+  } else {
+    for (int r0 = 0; r0 < R; r0 += 8) {
+      const int r = r0 + q;
+      double p = 0.0;
+      if (r < R)
+        for (int j = c8; j < J; j += 8) p = fma((double)Yk[r * J + j], (double)sVt[r * J + j], p);
+      p += __shfl_xor(p, 1, 64);
+      p += __shfl_xor(p, 2, 64);
+      p += __shfl_xor(p, 4, 64);
+      if (c8 == 0 && r < R) sc[r] = p;
+    }
   }
   wave_sync();
+  const double c = lane < R ? sc[lane] : 0.0;
+  wave_sync();
+  return c;
+}
+
+// One slice's state as the solve stage sees it.
+struct SolveSlice {
+  int b, tl;
+  bool touched;
+  double sig;
+  const float *Dp, *Dcp, *Yk;
+};
+
+__device__ inline SolveSlice solve_slice(CPassArgs &a, int k, int gcur, int64_t step, int seq, bool upd, int RR) {
+  SolveSlice x;
+  x.b = a.cur[(int64_t)gcur * a.K_cap + k];
+  x.tl = a.tlast[(int64_t)gcur * a.K_cap + k];
+  x.touched = upd && a.tag[k] == seq;
+  const int bs = x.touched ? 1 - x.b : x.b;
+  x.sig = x.touched ? 1.0 : exp2((double)(step - x.tl) * a.log2_lambda);
+  x.Dp = a.D + ((int64_t)bs * a.K_cap + k) * RR;
+  x.Dcp = a.Dc ? a.Dc + ((int64_t)bs * a.K_cap + k) * RR : nullptr;
+  x.Yk = a.Y + ((int64_t)x.b * a.K_cap + k) * a.ys;
+  return x;
+}
+
+// c_k of Lemma 2 for slice k (update pass): the row stage's sums for a
+// touched slice, the lagged recursion's stored value, or diag(Y_k V).
+template <int RM>
+__device__ inline double solve_c(CPassArgs &a, const SolveSlice &x, int k, int J, int R, const float *sVt,
+                                 double *sc) {
+  const int lane = threadIdx.x & 63;
+  if (x.touched) return lane < R ? a.cbuf[(int64_t)k * R + lane] : 0.0;
+  if (a.lagged) return lane < R ? a.cst[((int64_t)x.b * a.K_cap + k) * R + lane] : 0.0;
+  return slice_c<RM>(x.Yk, sVt, J, R, sc);
+}
+
+// The committed bookkeeping of slice k after its w_k is known (update pass).
+__device__ inline void solve_store(CPassArgs &a, const SolveSlice &x, int k, int gcur, int wout, int64_t step,
+                                   double w, int R) {
+  const int lane = threadIdx.x & 63;
+  if (lane < R) a.W[((int64_t)wout * a.K_cap + k) * R + lane] = w;
+  if (lane == 0) {
+    a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(x.touched ? 1 - x.b : x.b);
+    a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = x.touched ? (int32_t)step : x.tl;
+  }
+}
+
+// This wave's G terms of slice k: G += sigma_k diag(w_k) D_k diag(w_k), entry
+// q = lane + 64 i in gacc[i]; sw holds w_k.
+template <int RM>
+__device__ inline void solve_g(double (&gacc)[(RM * RM + 63) / 64], const SolveSlice &x, const double *sw, int R) {
+  const int lane = threadIdx.x & 63, RR = R * R;
+#pragma unroll
+  for (int i = 0; i < (RM * RM + 63) / 64; ++i) {
+    const int q = lane + 64 * i;
+    if (q < RR) {
+      const int r = q / R, s2 = q - r * R;
+      const double d = (double)x.Dp[q] + (x.Dcp ? (double)x.Dcp[q] : 0.0);
+      gacc[i] = fma(x.sig * sw[r] * sw[s2], d, gacc[i]);
+    }
+  }
+}
+
+// The deferred slices of a solve chunk (systems that failed the acceptance
+// rule), in slice order, by one wave: the eigen pseudo-inverse in the shared
+// scratch; their G and n terms go to this wave's partials.  Kept out of line:
+// the rare path should not set the register budget of the common one.
+template <int RM>
+__device__ __forceinline__ void solve_deferred(CPassArgs &a, int32_t *sDef, int nd, int gcur, int wout, int64_t step,
+                                            int seq, bool upd, bool do_g, const double *sVtV, const float *sVt,
+                                            double *sScr, double *sW, double (&gacc)[(RM * RM + 63) / 64],
+                                            double &nacc) {
+  const int lane = threadIdx.x & 63;
+  const int J = a.J, R = a.R, RR = R * R;
+  if (lane == 0)
+    for (int i = 1; i < nd; ++i)   // insertion sort: the list is short
+      for (int j = i; j > 0 && sDef[j - 1] > sDef[j]; --j) {
+        const int t = sDef[j];
+        sDef[j] = sDef[j - 1];
+        sDef[j - 1] = t;
+      }
+  double *sM = sScr, *sZ = sM + RR, *sx = sZ + RR, *sTmp = sx + 2 * R, *sRot = sTmp + 64;
+  int *sPair = (int *)(sRot + 128);
+  for (int i = 0; i < nd; ++i) {
+    int k = lane == 0 ? sDef[i] : 0;   // lane 0 sorted the list: its view is current
+    k = __shfl(k, 0, 64);
+    const SolveSlice x = solve_slice(a, k, gcur, step, seq, upd, RR);
+    const double c = solve_c<RM>(a, x, k, J, R, sVt, sx + R);
+    for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * ((double)x.Dp[q] + (x.Dcp ? (double)x.Dcp[q] : 0.0));
+    if (lane < R) sx[lane] = c;
+    wave_sync();
+    wave_pinv_apply(sM, sx, R, sZ, sTmp, sRot, sPair);
+    const double w = lane < R ? sx[lane] : 0.0;
+    solve_store(a, x, k, gcur, wout, step, w, R);
+    if (lane < R) sW[lane] = w;
+    wave_sync();
+    if (do_g) solve_g<RM>(gacc, x, sW, R);
+    nacc = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nacc);
+    wave_sync();
+  }
 }
 
 // mode 0 (update pass) or 1 (evaluation of the committed state: w_k is the
 // committed W, no solve; in lagged mode c_k = diag(Y_k V) is stored as the
-// recursion's starting value).  Workgroup = one solve chunk, 4 waves, one
-// slice per wave per round; after each round the whole workgroup adds the
-// round's G terms, slice by slice in wave order.
+// recursion's starting value).  Workgroup = one solve chunk of kSolveWaves
+// waves; wave v takes the chunk's slices v, v + kSolveWaves, ... on its own
+// (no workgroup barrier between slices) and keeps its G and n partials in
+// registers.  A system that fails the acceptance rule is deferred: after the
+// waves are done, the deferred slices are solved in slice order by the
+// pseudo-inverse in the shared scratch and their terms go to wave 0's
+// partial (the list lives in the chunk's own range of the row stage's
+// deferred-slice array, free once that stage is done).  The partials are then
+// summed in wave order.
 template <int RM>
-__global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const BlockMap *map) {
+__device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int sFail[4];
+  __shared__ int sNDef;
+  __shared__ double sN[kSolveWaves];
   CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
   const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
   const StepHeader *h = a.hdr;
@@ -709,142 +858,123 @@ __global__ __launch_bounds__(256, 2) void k_solve(const PassArgs *args, const Bl
   const SolveLds L = solve_lds(J, R);
   double *sVtV = (double *)(smem + L.oVtV);
   float *sVt = (float *)(smem + L.oVt);
-  double *sC = (double *)(smem + L.oC) + wv * R;           // this wave's c_k
-  double *sInfo = (double *)(smem + L.oInfo);               // [4][R + 4]
-  double *sM = (double *)(smem + L.oScr);
-  double *sZ = sM + RR;
-  double *sx = sZ + RR;
-  double *sTmp = sx + R;
-  double *sRot = sTmp + 64;
-  int *sPair = (int *)(sRot + 128);
+  double *sW = (double *)(smem + L.oW) + wv * R;   // this wave's w_k
+  double *sScr = (double *)(smem + L.oScr);
   const int chunk2 = blk;
   const int k0 = chunk2 * h->chunk2;
   const int k1 = min(K, k0 + h->chunk2);
+  int32_t *sDef = a.slow_list + k0;   // at most k1 - k0 entries
   // the row stage has finished: its counters are free for the next launch
   if (upd && chunk2 == 0 && tid < 3) a.queue[tid] = 0;
   const bool need_c = upd ? !a.lagged : (a.lagged != 0);
-  for (int e = tid; e < RR; e += 256) sVtV[e] = vb.VtV[e];
+  for (int e = tid; e < RR; e += blockDim.x) sVtV[e] = vb.VtV[e];
   if (need_c)
-    for (int e = tid; e < R * J; e += 256) sVt[e] = vb.Vt32[e];
+    for (int e = tid; e < R * J; e += blockDim.x) sVt[e] = vb.Vt32[e];
+  if (tid == 0) sNDef = 0;
   __syncthreads();
 
-  constexpr int NG = (RM * RM + 255) / 256;   // G entries per thread
+  constexpr int NG = (RM * RM + 63) / 64;
   double gacc[NG];
 #pragma unroll
   for (int i = 0; i < NG; ++i) gacc[i] = 0.0;
   double nacc = 0.0;
   const bool do_g = !a.lagged || !upd;
+  double *sc = sW;   // slice_c's staging (the w slot is free until w is known)
 
-  for (int base = k0; base < k1; base += 4) {
-    const int k = base + wv;
-    const bool valid = k < k1;
-    bool ok = true;
-    double w = 0.0, sig = 0.0, c = 0.0;
-    int b = 0, tl = 0;
-    bool touched = false;
-    const float *Dp = nullptr, *Dcp = nullptr;
-    if (valid) {
-      b = a.cur[(int64_t)gcur * a.K_cap + k];
-      tl = a.tlast[(int64_t)gcur * a.K_cap + k];
-      touched = upd && a.tag[k] == seq;
-      const int bs = touched ? 1 - b : b;
-      sig = touched ? 1.0 : exp2((double)(step - tl) * a.log2_lambda);
-      Dp = a.D + ((int64_t)bs * a.K_cap + k) * RR;
-      Dcp = a.Dc ? a.Dc + ((int64_t)bs * a.K_cap + k) * RR : nullptr;
-      const float *Yk = a.Y + ((int64_t)b * a.K_cap + k) * a.ys;
-      if (upd) {
-        if (touched) c = lane < R ? a.cbuf[(int64_t)k * R + lane] : 0.0;
-        else if (a.lagged) c = lane < R ? a.cst[((int64_t)b * a.K_cap + k) * R + lane] : 0.0;
-        else {
-          slice_c(Yk, sVt, J, R, sC);
-          c = lane < R ? sC[lane] : 0.0;
+  for (int k = k0 + wv; k < k1; k += kSolveWaves) {
+    const SolveSlice x = solve_slice(a, k, gcur, step, seq, upd, RR);
+    double w;
+    if (upd) {
+      const double c = solve_c<RM>(a, x, k, J, R, sVt, sc);
+      // Lemma 2: (V^T V * D_k) w = c, Gauss-Jordan in registers (lane r holds
+      // row r, read as float4 when rows are 16-byte aligned)
+      double m[RM];
+      if ((R & 3) == 0) {
+        const float4 *d4 = reinterpret_cast<const float4 *>(x.Dp + lane * R);
+        const float4 *e4 = x.Dcp ? reinterpret_cast<const float4 *>(x.Dcp + lane * R) : nullptr;
+#pragma unroll
+        for (int c4 = 0; c4 < RM / 4; ++c4) {
+          const bool in = lane < R && 4 * c4 < R;
+          const float4 d = in ? d4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 e = (in && e4) ? e4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const double *vv = sVtV + lane * R + 4 * c4;
+          m[4 * c4 + 0] = in ? vv[0] * ((double)d.x + (double)e.x) : 0.0;
+          m[4 * c4 + 1] = in ? vv[1] * ((double)d.y + (double)e.y) : 0.0;
+          m[4 * c4 + 2] = in ? vv[2] * ((double)d.z + (double)e.z) : 0.0;
+          m[4 * c4 + 3] = in ? vv[3] * ((double)d.w + (double)e.w) : 0.0;
         }
-        // Lemma 2: (V^T V * D_k) w = c, Gauss-Jordan in registers (lane r holds row r)
-        double m[RM];
+      } else {
 #pragma unroll
         for (int cc = 0; cc < RM; ++cc)
-          m[cc] = (lane < R && cc < R)
-                      ? sVtV[lane * R + cc] * ((double)Dp[lane * R + cc] + (Dcp ? (double)Dcp[lane * R + cc] : 0.0))
-                      : 0.0;
-        double rhs[1] = {c};
-        double dpiv;
-        ok = wave_gj_reg<RM, 1>(m, rhs, dpiv, R);
-        w = (ok && lane < R) ? rhs[0] / dpiv : 0.0;
-      } else {
-        if (a.lagged) {
-          slice_c(Yk, sVt, J, R, sC);
-          if (lane < R) a.cst[((int64_t)b * a.K_cap + k) * R + lane] = sC[lane];
-        }
-        w = lane < R ? a.W[((int64_t)gcur * a.K_cap + k) * R + lane] : 0.0;
+          m[cc] = (lane < R && cc < R) ? sVtV[lane * R + cc] * ((double)x.Dp[lane * R + cc] +
+                                                                (x.Dcp ? (double)x.Dcp[lane * R + cc] : 0.0))
+                                       : 0.0;
       }
+      double rhs[1] = {c};
+      double dpiv;
+      const bool ok = wave_gj_reg<RM, 1>(m, rhs, dpiv, R);
+      if (!ok) {
+        if (lane == 0) sDef[atomicAdd(&sNDef, 1)] = k;
+        continue;
+      }
+      w = lane < R ? rhs[0] / dpiv : 0.0;
+      solve_store(a, x, k, gcur, wout, step, w, R);
+    } else {
+      if (a.lagged) {
+        const double c = slice_c<RM>(x.Yk, sVt, J, R, sc);
+        if (lane < R) a.cst[((int64_t)x.b * a.K_cap + k) * R + lane] = c;
+      }
+      w = lane < R ? a.W[((int64_t)gcur * a.K_cap + k) * R + lane] : 0.0;
     }
-    if (lane == 0) sFail[wv] = (valid && !ok) ? 1 : 0;
-    __syncthreads();
-    // systems that failed the acceptance rule: the eigen pseudo-inverse, one
-    // wave at a time in the shared scratch
-    for (int v = 0; v < 4; ++v) {
-      if (!sFail[v]) continue;
-      if (wv == v) {
-        for (int q = lane; q < RR; q += 64)
-          sM[q] = sVtV[q] * ((double)Dp[q] + (Dcp ? (double)Dcp[q] : 0.0));
-        if (lane < R) sx[lane] = c;
-        wave_sync();
-        wave_pinv_apply(sM, sx, R, sZ, sTmp, sRot, sPair);
-        w = lane < R ? sx[lane] : 0.0;
-      }
-      __syncthreads();
-    }
-    // this wave's slice for the round's G terms: w_k, sigma_k, D_k, n_k
-    double *info = sInfo + wv * (R + 4);
-    if (valid) {
-      if (upd) {
-        if (lane < R) a.W[((int64_t)wout * a.K_cap + k) * R + lane] = w;
-        if (lane == 0) {
-          a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(touched ? 1 - b : b);
-          a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = touched ? (int32_t)step : tl;
-        }
-      }
-      if (lane < R) info[lane] = w;
-      if (lane == 0) {
-        info[R] = sig;
-        info[R + 1] = __longlong_as_double((long long)(intptr_t)Dp);
-        info[R + 2] = __longlong_as_double((long long)(intptr_t)Dcp);
-        info[R + 3] = fma(sig, a.n[(int64_t)(touched ? 1 - b : b) * a.K_cap + k], 0.0);
-      }
-    } else if (lane == 0) {
-      info[R] = 0.0;
-      info[R + 1] = __longlong_as_double(0LL);
-    }
-    __syncthreads();
-    // G += sigma_k diag(w_k) D_k diag(w_k) and sum n, slice by slice in wave order
-    for (int v = 0; v < 4; ++v) {
-      const double *iv = sInfo + v * (R + 4);
-      const float *Dv = (const float *)(intptr_t)__double_as_longlong(iv[R + 1]);
-      if (!Dv) continue;
-      const float *Dcv = (const float *)(intptr_t)__double_as_longlong(iv[R + 2]);
-      const double sv = iv[R];
-      if (do_g) {
+    if (lane < R) sW[lane] = w;
+    wave_sync();
+    if (do_g) solve_g<RM>(gacc, x, sW, R);
+    nacc = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nacc);
+    wave_sync();
+  }
+  __syncthreads();
+  // deferred slices, in slice order, by wave 0 with the shared scratch
+  const int nd = sNDef;
+  if (nd > 0 && wv == 0) solve_deferred<RM>(a, sDef, nd, gcur, wout, step, seq, upd, do_g, sVtV, sVt, sScr, sW, gacc,
+                                            nacc);
+  __syncthreads();
+  // the waves' partials in wave order
+  double *sG = sScr;
+  for (int v = 0; v < kSolveWaves; ++v) {
+    if (wv == v) {
 #pragma unroll
-        for (int i = 0; i < NG; ++i) {
-          const int q = tid + 256 * i;
-          if (q < RR) {
-            const int r = q / R, s2 = q - r * R;
-            const double d = (double)Dv[q] + (Dcv ? (double)Dcv[q] : 0.0);
-            gacc[i] = fma(sv * iv[r] * iv[s2], d, gacc[i]);
-          }
-        }
+      for (int i = 0; i < NG; ++i) {
+        const int q = lane + 64 * i;
+        if (q < RR) sG[q] = (v == 0) ? gacc[i] : sG[q] + gacc[i];
       }
-      if (tid == 0) nacc += iv[R + 3];
+      if (lane == 0) sN[v] = nacc;
     }
     __syncthreads();
   }
   double *p2 = a.part2 + (int64_t)chunk2 * (RR + 1);
-#pragma unroll
-  for (int i = 0; i < NG; ++i) {
-    const int q = tid + 256 * i;
-    if (q < RR) p2[q] = gacc[i];
+  for (int q = tid; q < RR; q += blockDim.x) p2[q] = sG[q];
+  if (tid == 0) {
+    double n = 0.0;
+    for (int v = 0; v < kSolveWaves; ++v) n += sN[v];
+    p2[RR] = n;
   }
-  if (tid == 0) p2[RR] = nacc;
+}
+
+template <int RM>
+__global__ __launch_bounds__(64 * kSolveWaves, 2) void k_solve(const PassArgs *args, const BlockMap *map) {
+  solve_body<RM>(args, map);
+}
+
+// Every rank class in one launch (a server tick): each workgroup takes the
+// body of its own context's R.
+__global__ __launch_bounds__(64 * kSolveWaves, 2) void k_solve_any(const PassArgs *args, const BlockMap *map) {
+  const int R = ((CPassArgs *)map[blockIdx.x].args)->R;
+  if (R <= 8)
+    solve_body<8>(args, map);
+  else if (R <= 16)
+    solve_body<16>(args, map);
+  else
+    solve_body<32>(args, map);
 }
 
 // ---------------------------------------------------------------------------
@@ -866,7 +996,7 @@ __host__ __device__ inline int fsum_tps(int ys) {
 }
 
 template <int EPT>
-__global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, const BlockMap *map) {
+__device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
   CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
   const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
@@ -996,6 +1126,27 @@ __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, 
   const int c2a = chunk * per, c2b = min(h->n_chunks2, c2a + per);
   for (int e = tid; e <= RR; e += kFsumThreads) part[RJ + e] = ordered_sum(a.part2, RR + 1, e, c2a, c2b);
   (void)arrive(a, h, chunk, &sflag);
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, const BlockMap *map) {
+  fsum_body<EPT>(args, map);
+}
+
+// float4 positions per thread of a slice's F-stage work (1, 2 or 4).
+__host__ __device__ inline int ept_bucket(int ys) {
+  const int tps = fsum_tps(ys), e = (ys / 4 + tps - 1) / tps;
+  return e <= 1 ? 1 : (e <= 2 ? 2 : 4);
+}
+
+// Every float4-per-thread class in one launch (a server tick).
+__global__ __launch_bounds__(kFsumThreads, 4) void k_fsum_any(const PassArgs *args, const BlockMap *map) {
+  const int ys = ((CPassArgs *)map[blockIdx.x].args)->ys;
+  switch (ept_bucket(ys)) {
+    case 1: fsum_body<1>(args, map); break;
+    case 2: fsum_body<2>(args, map); break;
+    default: fsum_body<4>(args, map); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,10 +1307,6 @@ static int allow_lds_s(F *fn, size_t bytes) {
 static inline int rw_bucket(int R) { return R <= 8 ? 2 : (R <= 16 ? 4 : 8); }
 static inline int jw_bucket(int J) { return J <= 64 ? 1 : (J <= 128 ? 2 : 4); }
 static inline int rm_bucket(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
-static inline int ept_bucket(int ys) {
-  const int tps = fsum_tps(ys), e = (ys / 4 + tps - 1) / tps;
-  return e <= 1 ? 1 : (e <= 2 ? 2 : 4);
-}
 
 int split_rows_class(int J, int R, int mixed) { return (rw_bucket(R) * 8 + jw_bucket(J)) * 2 + (mixed ? 1 : 0); }
 int split_solve_class(int R) { return rm_bucket(R); }
@@ -1278,7 +1425,7 @@ int split_rows_blocks_per_cu(int J, int R, int mixed) {
 template <int RM>
 static int launch_solve_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes, hipStream_t s) {
   if (int e = allow_lds_s(k_solve<RM>, bytes)) return e;
-  hipLaunchKernelGGL((k_solve<RM>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  hipLaunchKernelGGL((k_solve<RM>), dim3(n_blocks), dim3(64 * kSolveWaves), bytes, s, args, map);
   return (int)hipGetLastError();
 }
 
@@ -1315,6 +1462,20 @@ int launch_split_fsum(const PassArgs &a, const PassArgs *args, const BlockMap *m
     case 2: return launch_fsum_t<2>(args, map, n_blocks, bytes, s);
     default: return launch_fsum_t<4>(args, map, n_blocks, bytes, s);
   }
+}
+
+int launch_split_solve_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds) {
+  if (n_blocks <= 0) return 0;
+  if (int e = allow_lds_s(k_solve_any, lds)) return e;
+  hipLaunchKernelGGL(k_solve_any, dim3(n_blocks), dim3(64 * kSolveWaves), lds, s, nullptr, map);
+  return (int)hipGetLastError();
+}
+
+int launch_split_fsum_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds) {
+  if (n_blocks <= 0) return 0;
+  if (int e = allow_lds_s(k_fsum_any, lds)) return e;
+  hipLaunchKernelGGL(k_fsum_any, dim3(n_blocks), dim3(kFsumThreads), lds, s, nullptr, map);
+  return (int)hipGetLastError();
 }
 
 #undef DASH_RW_JW_SWITCH

@@ -208,7 +208,7 @@ def test_loop_thread_serves_requests_submitted_while_ticks_run():
     for i, d in specs.items():
         sids[i] = srv.open(d["J"], d["R"], lam=d["lam"], precision=PREC_MIXED if d["mixed"] else PREC_FP32, **KW)
         init_ctx(srv.context(sids[i]), d)
-    srv.start(0)
+    srv.start(2000)   # at most one tick per 2 ms: a round's requests share ticks
     req_of = {}   # (stream, request id) -> batch index
     reports = []
     for t in range(rounds):
