@@ -82,7 +82,8 @@ struct dash_ctx {
   double *part2 = nullptr;   // [kMaxChunks2][R*R+1]
   int32_t *tag = nullptr;    // [K_cap]
   int32_t *queue = nullptr;  // row-stage counters [4]
-  int32_t *slow_list = nullptr;   // [K_cap] deferred row-stage items
+  int32_t *slow_list = nullptr;   // [K_cap] deferred row-stage items (and solve-stage systems)
+  int32_t *solve_defer = nullptr; // [min(K_cap, kMaxChunks2)] deferred systems per solve chunk
   double *cst = nullptr;     // lagged: [2][K_cap][R]
   double *FG = nullptr;      // lagged: [2][R*J + R*R]
   int32_t seq = 0;           // enqueue sequence (never reused)

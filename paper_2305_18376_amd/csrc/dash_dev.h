@@ -150,6 +150,7 @@ struct PassArgs {
   int32_t *queue;      // row-stage counters (zero between launches): [0] work queue,
                        // [1] deferred slices, [2] their work queue
   int32_t *slow_list;  // [K_cap] items deferred to Lemma 1's pseudo-inverse form
+  int32_t *solve_defer;   // [n_chunks2] slices of a solve chunk deferred to the pseudo-inverse
   int lagged;          // DASH_STATS_LAGGED: Algorithm 1's recursions for c_k, F, G
   double *cst;         // lagged: [2][K_cap][R] stored c_k (buffer by cur)
   double *FG;          // lagged: [2][R*J + R*R] F^T then G (buffer by gcur)
@@ -302,6 +303,9 @@ struct FetchJob {
 int launch_fetch_list(const FetchJob *jobs_mapped, int n_jobs, int64_t max_bytes, hipStream_t s);
 // LDS of the row stage's deferred-slice kernel.
 size_t split_rows_slow_lds(int J, int R);
+// The solve stage's deferred systems (those that failed the acceptance rule):
+// one workgroup per solve chunk, most of which find nothing to do.
+int launch_split_solve_fix(const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s, size_t lds);
 // Name of the kernel instantiation a split-sweep stage launches for arguments
 // a (stage: 0 rows, 1 deferred slices, 2 solve, 3 F, 4 group reduction, 5
 // final phase), e.g. "k_solve<16>"; written into buf (n bytes).

@@ -222,6 +222,7 @@ PassArgs base_args_at(const dash_ctx *c, const char *d) {
   a.tag = c->tag;
   a.queue = c->queue;
   a.slow_list = c->slow_list;
+  a.solve_defer = c->solve_defer;
   a.lagged = c->cfg.stats_mode == DASH_STATS_LAGGED ? 1 : 0;
   a.cst = c->cst;
   a.FG = c->FG;
@@ -289,6 +290,7 @@ dash_status enqueue_split_pass(dash_ctx *c, const PassArgs &a, const PassArgs *a
   }
   HIP_OR_FAIL(c, prof_begin(c, kProfSolve));
   LAUNCH_OR_FAIL(c, launch_split_solve(a, ad, nullptr, n_chunks2, c->stream));
+  LAUNCH_OR_FAIL(c, launch_split_solve_fix(ad, nullptr, n_chunks2, c->stream, split_solve_lds(c->J, c->R)));
   HIP_OR_FAIL(c, prof_end(c));
   HIP_OR_FAIL(c, prof_begin(c, kProfReduce));
   LAUNCH_OR_FAIL(c, launch_split_fsum(a, ad, nullptr, n_chunks, c->stream));
@@ -402,7 +404,7 @@ int64_t context_footprint(const dash_config *cfg) {
   const int64_t lag = cfg->stats_mode == DASH_STATS_LAGGED
                           ? al(8 * 2 * Kc * R) + al(8 * 2 * ((int64_t)cfg->J * R + R * R)) : 0;
   const int64_t split = al(8 * Kc * R) + al(8 * std::min<int64_t>(Kc, kMaxChunks2) * (R * R + 1)) +
-                        al(4 * Kc) + al(16) + al(4 * Kc);
+                        al(4 * Kc) + al(16) + al(4 * Kc) + al(4 * std::min<int64_t>(Kc, kMaxChunks2));
   return carry + lag + split + al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) + al(8 * 2 * Kc) + al(2 * Kc) + al(4 * 2 * Kc) +
          al(8 * 2 * Kc * R) + al(2 * (int64_t)vb_bytes(cfg->J, cfg->R)) + al(sizeof(Ctl)) +
          al(4 * cfg->max_rows_per_update * R) + al(8 * n_chunks_cap * plen) +
@@ -463,7 +465,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
     args[p].last_pass = (p == n_iter - 1) ? 1 : 0;
   }
   FetchArgs fa = fetch_args(c->hstage_dev[s], c->dstep[s], bytes, report);
-  const size_t per_pass = split ? 6 : (base.fuse ? 1 : 2);
+  const size_t per_pass = split ? 7 : (base.fuse ? 1 : 2);
   const size_t expect = 1 + (size_t)n_iter * per_pass;
   if (!c->gexec[s]) {
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -474,6 +476,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
         e = launch_split_rows(args[p], ad, nullptr, std::min(n_items, c->rows_blocks), c->stream);
         if (!e) e = launch_split_rows_slow(args[p], ad, nullptr, kSlowBlocks, c->stream);
         if (!e) e = launch_split_solve(args[p], ad, nullptr, n_chunks2, c->stream);
+        if (!e) e = launch_split_solve_fix(ad, nullptr, n_chunks2, c->stream, split_solve_lds(c->J, c->R));
         if (!e) e = launch_split_fsum(args[p], ad, nullptr, nch, c->stream);
         if (!e) e = launch_reduce_groups(ad, nullptr, reduce_groups_blocks(c->J, c->R), c->stream);
         if (!e) e = launch_finish_dev(args[p], ad, nullptr, 1, 0, c->stream);
@@ -544,6 +547,7 @@ dash_status graph_update(dash_ctx *c, int s, size_t bytes, int nch, void *report
         void *dfin[] = {&ad, &nomap, &mode0};
         HIP_OR_FAIL(c, set(i++, (unsigned)std::min(n_items, c->rows_blocks), dargs));
         HIP_OR_FAIL(c, set(i++, (unsigned)kSlowBlocks, dargs));
+        HIP_OR_FAIL(c, set(i++, (unsigned)n_chunks2, dargs));
         HIP_OR_FAIL(c, set(i++, (unsigned)n_chunks2, dargs));
         HIP_OR_FAIL(c, set(i++, (unsigned)nch, dargs));
         HIP_OR_FAIL(c, set(i++, (unsigned)reduce_groups_blocks(c->J, c->R), dargs));
@@ -713,7 +717,8 @@ dash_status create_context(const dash_config *cfg, hipStream_t stream, bool serv
             dalloc(&c->part2, sizeof(double) * std::min<int64_t>(Kc, kMaxChunks2) * (R * R + 1)) == hipSuccess &&
             dalloc(&c->tag, sizeof(int32_t) * Kc) == hipSuccess &&
             dalloc(&c->queue, sizeof(int32_t) * 4) == hipSuccess &&
-            dalloc(&c->slow_list, sizeof(int32_t) * Kc) == hipSuccess;
+            dalloc(&c->slow_list, sizeof(int32_t) * Kc) == hipSuccess &&
+            dalloc(&c->solve_defer, sizeof(int32_t) * std::min<int64_t>(Kc, kMaxChunks2)) == hipSuccess;
   if (ok && cfg->stats_mode == DASH_STATS_LAGGED)
     ok = dalloc(&c->cst, sizeof(double) * 2 * Kc * R) == hipSuccess &&
          dalloc(&c->FG, sizeof(double) * 2 * (J * R + R * R)) == hipSuccess;
@@ -794,6 +799,7 @@ dash_status dash_destroy(dash_ctx *c) {
   (void)hipFree(c->tag);
   (void)hipFree(c->queue);
   (void)hipFree(c->slow_list);
+  (void)hipFree(c->solve_defer);
   (void)hipFree(c->cst);
   (void)hipFree(c->FG);
   (void)hipFree(c->anom.se);

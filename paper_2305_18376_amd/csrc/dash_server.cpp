@@ -15,9 +15,10 @@
 // Admission is by device footprint against the server's budget; a stream that
 // does not fit may wait in a FIFO queue and is admitted when closes free the
 // budget.  dash_server_start runs the tick/poll loop on a host thread of its
-// own: a tick is launched as soon as rows are waiting and fewer than two ticks
-// are in flight, so requests that arrive while the GPU works join the next
-// tick (continuous batching).
+// own: a tick is launched as soon as rows are waiting and no tick is in
+// flight, or beside the one in flight once a quarter of the open streams have
+// rows waiting, so requests that arrive while the GPU works join the next tick
+// (continuous batching) and ticks stay full under load.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -496,7 +497,10 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
     switch (L.stage) {
       case 0: e = launch_split_rows(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 1: e = launch_split_rows_slow(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
-      case 2: e = launch_split_solve_any(m, L.n_blocks, s, L.lds); break;
+      case 2:
+        e = launch_split_solve_any(m, L.n_blocks, s, L.lds);
+        if (!e) e = launch_split_solve_fix(nullptr, m, L.n_blocks, s, L.lds);
+        break;
       case 3: e = launch_split_fsum(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 4: e = launch_reduce_groups(nullptr, m, L.n_blocks, s); break;
       default: e = launch_finish_dev_any(m, L.n_blocks, s, L.lds); break;
@@ -538,13 +542,29 @@ bool has_requests(const dash_server *srv) {
   return false;
 }
 
+// Open streams, and those with submitted rows that a tick could cut now.
+void ready_count(const dash_server *srv, int *open, int *ready) {
+  *open = *ready = 0;
+  for (const Stream &st : srv->streams) {
+    if (st.state != kStateOpen) continue;
+    ++*open;
+    if (!st.requests.empty() && st.ctx->initialized) ++*ready;
+  }
+}
+
 void loop_main(dash_server *srv) {
   std::unique_lock<std::mutex> lk(srv->mu);
   while (!srv->stop) {
     dash_status s = collect(srv);
     if (s != DASH_OK && srv->loop_err == DASH_OK) srv->loop_err = s;
+    // a tick starts when none is in flight, or beside the one in flight when
+    // a quarter of the open streams are ready (so ticks stay full when the
+    // device is busy, and requests never wait for an idle device)
     const bool due = srv->tick_us <= 0 || now_us() - srv->last_tick >= (double)srv->tick_us;
-    if (due && (int)srv->ticks_in_flight.size() < kTicksInFlight && has_requests(srv)) {
+    int open = 0, ready = 0;
+    ready_count(srv, &open, &ready);
+    const int inflight = (int)srv->ticks_in_flight.size();
+    if (due && ready > 0 && (inflight == 0 || (inflight < kTicksInFlight && 4 * ready >= open))) {
       s = run_tick(srv, nullptr);
       if (s != DASH_OK && srv->loop_err == DASH_OK) srv->loop_err = s;
     }

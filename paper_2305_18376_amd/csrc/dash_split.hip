@@ -632,101 +632,30 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
 // ---------------------------------------------------------------------------
 struct SolveLds {
   size_t oVtV, oVt, oW, oScr, bytes;
+  int vts;   // row stride of V^T in LDS (floats)
 };
 
 constexpr int kSolveWaves = 4;   // waves of a solve workgroup
 
-// V^T V (FP64), V^T (float, R x J), each wave's w_k (for its G terms), and a
-// scratch shared by the pseudo-inverse of deferred slices and the final
-// combination of the waves' G partials.
+// V^T V (FP64, row stride R + 1), V^T (float, row stride J + 4: the rows a
+// lane group reads side by side fall in different banks), a deferred slice's
+// w, and a scratch shared by the pseudo-inverse of deferred slices, their G
+// terms and the final combination of the waves' G partials.
 __host__ __device__ inline SolveLds solve_lds(int J, int R) {
   SolveLds L;
+  L.vts = J + 4;
   size_t o = 0;
   L.oVtV = o;
-  o += (size_t)R * R * 8;
-  L.oVt = o;
-  o = align_up(o + (size_t)R * J * 4, 16);
+  o += (size_t)R * (R + 1) * 8;
+  L.oVt = o = align_up(o, 16);
+  o = align_up(o + (size_t)R * L.vts * 4, 16);
   L.oW = o;
-  o += (size_t)kSolveWaves * R * 8;
+  o += (size_t)R * 8;
   L.oScr = o;
   const size_t pinv = (size_t)(2 * R * R + 2 * R + 3 * 64) * 8 + 64 * 4;
-  const size_t comb = (size_t)(R * R + kSolveWaves) * 8;
-  o += pinv > comb ? pinv : comb;
+  o += pinv + (size_t)2 * (R * R + 1) * 8;   // pseudo-inverse scratch, deferred G, combined G
   L.bytes = align_up(o, 16);
   return L;
-}
-
-// c_r = sum_j Y_k[r][j] V[j][r] of one slice by one wave, FP64 sums of the
-// float products.  Lane l takes ranks r0 + l / 8 (r0 = 0, 8, ...) and, when
-// rows are 16-byte aligned, the float4 columns 4 (l mod 8) + 32 t: a load
-// instruction reads eight whole 128-byte runs, and every load of the slice
-// (R J / 256 float4 per lane, J <= 256) is issued before the first product
-// (for R > 16: those of eight ranks at a time, for the registers), so the
-// slice waits for one or a few memory latencies, not one per batch.  The eight
-// lanes of a rank add their partials with three exchanges.  Returns c_lane
-// (lane < R).
-template <int RM>
-__device__ inline double slice_c(const float *__restrict__ Yk, const float *sVt, int J, int R, double *sc) {
-  const int lane = threadIdx.x & 63;
-  const int q = lane >> 3, c8 = lane & 7;
-  constexpr int NG = (RM + 7) / 8;      // groups of eight ranks
-  constexpr int GB = RM >= 32 ? 1 : NG;  // groups whose loads are in flight together (registers)
-  if ((J & 3) == 0) {
-    const int J4 = J >> 2;
-#pragma unroll 1
-    for (int g0 = 0; g0 < NG; g0 += GB) {
-    float4 y[GB][8];
-#pragma unroll
-    for (int gg = 0; gg < GB; ++gg) {
-      const int r = 8 * (g0 + gg) + q;
-      const float4 *yr = reinterpret_cast<const float4 *>(Yk + r * J);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int j4 = c8 + 8 * t;
-        y[gg][t] = (r < R && j4 < J4) ? yr[j4] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int gg = 0; gg < GB; ++gg) {
-      const int g = gg;
-      const int r = 8 * (g0 + gg) + q;
-      double p = 0.0;
-      if (r < R) {
-        const float4 *vr = reinterpret_cast<const float4 *>(sVt + r * J);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int j4 = c8 + 8 * t;
-          if (j4 < J4) {
-            const float4 v = vr[j4];
-            p = fma((double)y[g][t].x, (double)v.x, p);
-            p = fma((double)y[g][t].y, (double)v.y, p);
-            p = fma((double)y[g][t].z, (double)v.z, p);
-            p = fma((double)y[g][t].w, (double)v.w, p);
-          }
-        }
-      }
-      p += __shfl_xor(p, 1, 64);
-      p += __shfl_xor(p, 2, 64);
-      p += __shfl_xor(p, 4, 64);
-      if (c8 == 0 && r < R) sc[r] = p;
-    }
-    }
-  } else {
-    for (int r0 = 0; r0 < R; r0 += 8) {
-      const int r = r0 + q;
-      double p = 0.0;
-      if (r < R)
-        for (int j = c8; j < J; j += 8) p = fma((double)Yk[r * J + j], (double)sVt[r * J + j], p);
-      p += __shfl_xor(p, 1, 64);
-      p += __shfl_xor(p, 2, 64);
-      p += __shfl_xor(p, 4, 64);
-      if (c8 == 0 && r < R) sc[r] = p;
-    }
-  }
-  wave_sync();
-  const double c = lane < R ? sc[lane] : 0.0;
-  wave_sync();
-  return c;
 }
 
 // One slice's state as the solve stage sees it.
@@ -750,53 +679,108 @@ __device__ inline SolveSlice solve_slice(CPassArgs &a, int k, int gcur, int64_t 
   return x;
 }
 
-// c_k of Lemma 2 for slice k (update pass): the row stage's sums for a
-// touched slice, the lagged recursion's stored value, or diag(Y_k V).
-template <int RM>
-__device__ inline double solve_c(CPassArgs &a, const SolveSlice &x, int k, int J, int R, const float *sVt,
-                                 double *sc) {
-  const int lane = threadIdx.x & 63;
-  if (x.touched) return lane < R ? a.cbuf[(int64_t)k * R + lane] : 0.0;
-  if (a.lagged) return lane < R ? a.cst[((int64_t)x.b * a.K_cap + k) * R + lane] : 0.0;
-  return slice_c<RM>(x.Yk, sVt, J, R, sc);
-}
-
-// The committed bookkeeping of slice k after its w_k is known (update pass).
-__device__ inline void solve_store(CPassArgs &a, const SolveSlice &x, int k, int gcur, int wout, int64_t step,
-                                   double w, int R) {
-  const int lane = threadIdx.x & 63;
-  if (lane < R) a.W[((int64_t)wout * a.K_cap + k) * R + lane] = w;
-  if (lane == 0) {
-    a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(x.touched ? 1 - x.b : x.b);
-    a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = x.touched ? (int32_t)step : x.tl;
-  }
-}
-
-// This wave's G terms of slice k: G += sigma_k diag(w_k) D_k diag(w_k), entry
-// q = lane + 64 i in gacc[i]; sw holds w_k.
-template <int RM>
-__device__ inline void solve_g(double (&gacc)[(RM * RM + 63) / 64], const SolveSlice &x, const double *sw, int R) {
-  const int lane = threadIdx.x & 63, RR = R * R;
+// c_r = sum_j Y_k[r][j] V[j][r] for one row: FP64 sum of the float products in
+// column order; float4 loads, eight in flight, when rows are 16-byte aligned.
+__device__ inline double row_c(const float *__restrict__ yr, const float *vr, int J) {
+  double p = 0.0;
+  if ((J & 3) == 0) {
+    const float4 *y4 = reinterpret_cast<const float4 *>(yr);
+    const float4 *v4 = reinterpret_cast<const float4 *>(vr);
+    const int J4 = J >> 2;
+    for (int t0 = 0; t0 < J4; t0 += 8) {
+      float4 y[8];
 #pragma unroll
-  for (int i = 0; i < (RM * RM + 63) / 64; ++i) {
-    const int q = lane + 64 * i;
-    if (q < RR) {
-      const int r = q / R, s2 = q - r * R;
-      const double d = (double)x.Dp[q] + (x.Dcp ? (double)x.Dcp[q] : 0.0);
-      gacc[i] = fma(x.sig * sw[r] * sw[s2], d, gacc[i]);
+      for (int u = 0; u < 8; ++u) y[u] = (t0 + u < J4) ? y4[t0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (t0 + u < J4) {
+          const float4 v = v4[t0 + u];
+          p = fma((double)y[u].x, (double)v.x, p);
+          p = fma((double)y[u].y, (double)v.y, p);
+          p = fma((double)y[u].z, (double)v.z, p);
+          p = fma((double)y[u].w, (double)v.w, p);
+        }
+      }
     }
+  } else {
+    for (int j = 0; j < J; ++j) p = fma((double)yr[j], (double)vr[j], p);
   }
+  return p;
+}
+
+// c_k of Lemma 2, row r (update pass): the row stage's sums for a touched
+// slice, the lagged recursion's stored value, or diag(Y_k V).
+__device__ inline double solve_c_row(CPassArgs &a, const SolveSlice &x, int k, int J, int R, int r, const float *sVt,
+                                     int vts) {
+  if (r >= R) return 0.0;
+  if (x.touched) return a.cbuf[(int64_t)k * R + r];
+  if (a.lagged) return a.cst[((int64_t)x.b * a.K_cap + k) * R + r];
+  return row_c(x.Yk + r * J, sVt + r * vts, J);
+}
+
+// Row r of D_k (plus its compensation word), as doubles, 0 beyond R.
+template <int RM>
+__device__ __forceinline__ void load_d_row(const SolveSlice &x, int R, int r, double (&d)[RM]) {
+  if ((R & 3) == 0) {
+    const float4 *d4 = reinterpret_cast<const float4 *>(x.Dp + r * R);
+    const float4 *e4 = x.Dcp ? reinterpret_cast<const float4 *>(x.Dcp + r * R) : nullptr;
+#pragma unroll
+    for (int c4 = 0; c4 < RM / 4; ++c4) {
+      const bool in = r < R && 4 * c4 < R;
+      const float4 v = in ? d4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 e = (in && e4) ? e4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      d[4 * c4 + 0] = (double)v.x + (double)e.x;
+      d[4 * c4 + 1] = (double)v.y + (double)e.y;
+      d[4 * c4 + 2] = (double)v.z + (double)e.z;
+      d[4 * c4 + 3] = (double)v.w + (double)e.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+      d[c] = (r < R && c < R) ? (double)x.Dp[r * R + c] + (x.Dcp ? (double)x.Dcp[r * R + c] : 0.0) : 0.0;
+  }
+}
+
+// Gauss-Jordan of one group of RM lanes: lane base + r holds row r of an
+// RM x RM system (rows n .. RM - 1 are padding) and entry r of the right-hand
+// side; pivot rows are exchanged within the group.  The acceptance rule of the
+// oracle's Cholesky: every pivot of a real row above kPivotRel times the
+// largest diagonal entry (ok is uniform over the group; a failing group runs
+// on harmlessly).  On ok, x_r = b / d.
+template <int RM>
+__device__ __forceinline__ bool group_gj(double (&m)[RM], double &b, double &d, int n, int base, int r) {
+  double diag = 0.0;
+#pragma unroll
+  for (int c = 0; c < RM; ++c) diag = (c == r) ? m[c] : diag;
+  double dmax = (r < n) ? diag : 0.0;
+#pragma unroll
+  for (int o = 1; o < RM; o <<= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  bool ok = dmax > 0.0;
+  const double thr = kPivotRel * dmax;
+  const double pad = ok ? dmax : 1.0;
+#pragma unroll
+  for (int c = 0; c < RM; ++c) m[c] = (r >= n) ? ((c == r) ? pad : 0.0) : m[c];
+  d = 1.0;
+#pragma unroll
+  for (int p = 0; p < RM; ++p) {
+    double piv = __shfl(m[p], base + p, 64);
+    ok = ok && (p >= n || piv > thr);
+    piv = (piv > 0.0) ? piv : 1.0;
+    d = (r == p) ? piv : d;
+    const double f = (r != p) ? m[p] / piv : 0.0;
+#pragma unroll
+    for (int c = p + 1; c < RM; ++c) m[c] = fma(-f, __shfl(m[c], base + p, 64), m[c]);
+    b = fma(-f, __shfl(b, base + p, 64), b);
+  }
+  return ok;
 }
 
 // The deferred slices of a solve chunk (systems that failed the acceptance
 // rule), in slice order, by one wave: the eigen pseudo-inverse in the shared
-// scratch; their G and n terms go to this wave's partials.  Kept out of line:
-// the rare path should not set the register budget of the common one.
-template <int RM>
-__device__ __forceinline__ void solve_deferred(CPassArgs &a, int32_t *sDef, int nd, int gcur, int wout, int64_t step,
-                                            int seq, bool upd, bool do_g, const double *sVtV, const float *sVt,
-                                            double *sScr, double *sW, double (&gacc)[(RM * RM + 63) / 64],
-                                            double &nacc) {
+// scratch; their G terms go to sGd (LDS, RR entries) and their n to *nd_sum.
+__device__ inline void solve_deferred(CPassArgs &a, int32_t *sDef, int nd, int gcur, int wout, int64_t step, int seq,
+                                      bool upd, bool do_g, const double *sVtV, const float *sVt, int vts, double *sScr,
+                                      double *sw, double *sGd, double *nd_sum) {
   const int lane = threadIdx.x & 63;
   const int J = a.J, R = a.R, RR = R * R;
   if (lane == 0)
@@ -806,40 +790,60 @@ __device__ __forceinline__ void solve_deferred(CPassArgs &a, int32_t *sDef, int 
         sDef[j] = sDef[j - 1];
         sDef[j - 1] = t;
       }
+  for (int q = lane; q < RR; q += 64) sGd[q] = 0.0;
   double *sM = sScr, *sZ = sM + RR, *sx = sZ + RR, *sTmp = sx + 2 * R, *sRot = sTmp + 64;
   int *sPair = (int *)(sRot + 128);
+  double nsum = 0.0;
   for (int i = 0; i < nd; ++i) {
     int k = lane == 0 ? sDef[i] : 0;   // lane 0 sorted the list: its view is current
     k = __shfl(k, 0, 64);
     const SolveSlice x = solve_slice(a, k, gcur, step, seq, upd, RR);
-    const double c = solve_c<RM>(a, x, k, J, R, sVt, sx + R);
-    for (int q = lane; q < RR; q += 64) sM[q] = sVtV[q] * ((double)x.Dp[q] + (x.Dcp ? (double)x.Dcp[q] : 0.0));
+    const double c = solve_c_row(a, x, k, J, R, lane, sVt, vts);
+    for (int q = lane; q < RR; q += 64) {
+      const int r = q / R, cc = q - r * R;
+      sM[q] = sVtV[r * (R + 1) + cc] * ((double)x.Dp[q] + (x.Dcp ? (double)x.Dcp[q] : 0.0));
+    }
     if (lane < R) sx[lane] = c;
     wave_sync();
     wave_pinv_apply(sM, sx, R, sZ, sTmp, sRot, sPair);
     const double w = lane < R ? sx[lane] : 0.0;
-    solve_store(a, x, k, gcur, wout, step, w, R);
-    if (lane < R) sW[lane] = w;
+    if (lane < R) {
+      a.W[((int64_t)wout * a.K_cap + k) * R + lane] = w;
+      sw[lane] = w;
+    }
+    if (lane == 0) {
+      a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(x.touched ? 1 - x.b : x.b);
+      a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = x.touched ? (int32_t)step : x.tl;
+    }
     wave_sync();
-    if (do_g) solve_g<RM>(gacc, x, sW, R);
-    nacc = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nacc);
+    if (do_g)
+      for (int q = lane; q < RR; q += 64) {
+        const int r = q / R, s2 = q - r * R;
+        const double d = (double)x.Dp[q] + (x.Dcp ? (double)x.Dcp[q] : 0.0);
+        sGd[q] = fma(x.sig * sw[r] * sw[s2], d, sGd[q]);
+      }
+    nsum = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nsum);
     wave_sync();
   }
+  if (lane == 0) *nd_sum = nsum;
 }
 
 // mode 0 (update pass) or 1 (evaluation of the committed state: w_k is the
 // committed W, no solve; in lagged mode c_k = diag(Y_k V) is stored as the
 // recursion's starting value).  Workgroup = one solve chunk of kSolveWaves
-// waves; wave v takes the chunk's slices v, v + kSolveWaves, ... on its own
-// (no workgroup barrier between slices) and keeps its G and n partials in
-// registers.  A system that fails the acceptance rule is deferred: after the
-// waves are done, the deferred slices are solved in slice order by the
-// pseudo-inverse in the shared scratch and their terms go to wave 0's
-// partial (the list lives in the chunk's own range of the row stage's
-// deferred-slice array, free once that stage is done).  The partials are then
-// summed in wave order.
+// waves; a wave splits into 64 / RM lane groups, each taking one slice at a
+// time (lane r of a group owns row r of the slice's R x R system, its c_r, its
+// w_r and row r of its G terms), so 64 / RM slices are in flight per wave and
+// no workgroup barrier separates slices.  Group g of wave v takes the chunk's
+// slices v S + g + 4 S i (S = 64 / RM).  Each lane keeps its G row partial in
+// registers; at the end the groups of a wave are summed by a fixed exchange
+// tree, then the waves in order, then the deferred slices (systems that
+// failed the acceptance rule) are listed in the chunk's range of the row
+// stage's deferred-slice array (free once that stage is done) and solved by
+// the next launch.
 template <int RM>
 __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap *map) {
+  constexpr int S = 64 / RM;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sNDef;
   __shared__ double sN[kSolveWaves];
@@ -848,6 +852,7 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
   const StepHeader *h = a.hdr;
   const int J = a.J, R = a.R, RR = R * R;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane % RM, grp = lane / RM, base = grp * RM;
   const int K = h->K, seq = h->seq;
   const int64_t step = h->step;
   const int gcur = a.ctl->gcur;
@@ -858,8 +863,8 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
   const SolveLds L = solve_lds(J, R);
   double *sVtV = (double *)(smem + L.oVtV);
   float *sVt = (float *)(smem + L.oVt);
-  double *sW = (double *)(smem + L.oW) + wv * R;   // this wave's w_k
   double *sScr = (double *)(smem + L.oScr);
+  double *sG = sScr;   // the waves' combined G
   const int chunk2 = blk;
   const int k0 = chunk2 * h->chunk2;
   const int k1 = min(K, k0 + h->chunk2);
@@ -867,88 +872,80 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
   // the row stage has finished: its counters are free for the next launch
   if (upd && chunk2 == 0 && tid < 3) a.queue[tid] = 0;
   const bool need_c = upd ? !a.lagged : (a.lagged != 0);
-  for (int e = tid; e < RR; e += blockDim.x) sVtV[e] = vb.VtV[e];
+  for (int e = tid; e < RR; e += blockDim.x) sVtV[(e / R) * (R + 1) + e % R] = vb.VtV[e];
   if (need_c)
-    for (int e = tid; e < R * J; e += blockDim.x) sVt[e] = vb.Vt32[e];
+    for (int e = tid; e < R * J; e += blockDim.x) sVt[(e / J) * L.vts + e % J] = vb.Vt32[e];
   if (tid == 0) sNDef = 0;
   __syncthreads();
 
-  constexpr int NG = (RM * RM + 63) / 64;
-  double gacc[NG];
+  double gacc[RM];
 #pragma unroll
-  for (int i = 0; i < NG; ++i) gacc[i] = 0.0;
+  for (int i = 0; i < RM; ++i) gacc[i] = 0.0;
   double nacc = 0.0;
   const bool do_g = !a.lagged || !upd;
-  double *sc = sW;   // slice_c's staging (the w slot is free until w is known)
 
-  for (int k = k0 + wv; k < k1; k += kSolveWaves) {
-    const SolveSlice x = solve_slice(a, k, gcur, step, seq, upd, RR);
-    double w;
-    if (upd) {
-      const double c = solve_c<RM>(a, x, k, J, R, sVt, sc);
-      // Lemma 2: (V^T V * D_k) w = c, Gauss-Jordan in registers (lane r holds
-      // row r, read as float4 when rows are 16-byte aligned)
-      double m[RM];
-      if ((R & 3) == 0) {
-        const float4 *d4 = reinterpret_cast<const float4 *>(x.Dp + lane * R);
-        const float4 *e4 = x.Dcp ? reinterpret_cast<const float4 *>(x.Dcp + lane * R) : nullptr;
+  for (int kb = k0 + wv * S; kb < k1; kb += kSolveWaves * S) {
+    const int k = kb + grp;
+    if (k < k1) {
+      const SolveSlice x = solve_slice(a, k, gcur, step, seq, upd, RR);
+      double w = 0.0;
+      bool use = true;
+      if (upd) {
+        double b = solve_c_row(a, x, k, J, R, r, sVt, L.vts);
+        // Lemma 2: (V^T V * D_k) w = c
+        double m[RM];
+        load_d_row<RM>(x, R, r, m);
 #pragma unroll
-        for (int c4 = 0; c4 < RM / 4; ++c4) {
-          const bool in = lane < R && 4 * c4 < R;
-          const float4 d = in ? d4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const float4 e = (in && e4) ? e4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const double *vv = sVtV + lane * R + 4 * c4;
-          m[4 * c4 + 0] = in ? vv[0] * ((double)d.x + (double)e.x) : 0.0;
-          m[4 * c4 + 1] = in ? vv[1] * ((double)d.y + (double)e.y) : 0.0;
-          m[4 * c4 + 2] = in ? vv[2] * ((double)d.z + (double)e.z) : 0.0;
-          m[4 * c4 + 3] = in ? vv[3] * ((double)d.w + (double)e.w) : 0.0;
+        for (int c = 0; c < RM; ++c) m[c] = (r < R && c < R) ? sVtV[r * (R + 1) + c] * m[c] : 0.0;
+        double dpiv;
+        const bool ok = group_gj<RM>(m, b, dpiv, R, base, r);
+        if (!ok) {
+          if (r == 0) sDef[atomicAdd(&sNDef, 1)] = k;
+          use = false;
+        } else {
+          w = r < R ? b / dpiv : 0.0;
+          if (r < R) a.W[((int64_t)wout * a.K_cap + k) * R + r] = w;
+          if (r == 0) {
+            a.cur[(int64_t)(1 - gcur) * a.K_cap + k] = (uint8_t)(x.touched ? 1 - x.b : x.b);
+            a.tlast[(int64_t)(1 - gcur) * a.K_cap + k] = x.touched ? (int32_t)step : x.tl;
+          }
         }
       } else {
+        if (a.lagged && r < R)
+          a.cst[((int64_t)x.b * a.K_cap + k) * R + r] = row_c(x.Yk + r * J, sVt + r * L.vts, J);
+        w = r < R ? a.W[((int64_t)gcur * a.K_cap + k) * R + r] : 0.0;
+      }
+      if (use) {
+        // row r of G += sigma_k diag(w_k) D_k diag(w_k)
+        if (do_g) {
+          double d[RM];
+          load_d_row<RM>(x, R, r, d);
+          const double sr = x.sig * w;
 #pragma unroll
-        for (int cc = 0; cc < RM; ++cc)
-          m[cc] = (lane < R && cc < R) ? sVtV[lane * R + cc] * ((double)x.Dp[lane * R + cc] +
-                                                                (x.Dcp ? (double)x.Dcp[lane * R + cc] : 0.0))
-                                       : 0.0;
+          for (int i = 0; i < RM; ++i) {
+            const double wi = __shfl(w, base + i, 64);
+            gacc[i] = fma(sr * wi, d[i], gacc[i]);
+          }
+        }
+        if (r == 0) nacc = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nacc);
       }
-      double rhs[1] = {c};
-      double dpiv;
-      const bool ok = wave_gj_reg<RM, 1>(m, rhs, dpiv, R);
-      if (!ok) {
-        if (lane == 0) sDef[atomicAdd(&sNDef, 1)] = k;
-        continue;
-      }
-      w = lane < R ? rhs[0] / dpiv : 0.0;
-      solve_store(a, x, k, gcur, wout, step, w, R);
-    } else {
-      if (a.lagged) {
-        const double c = slice_c<RM>(x.Yk, sVt, J, R, sc);
-        if (lane < R) a.cst[((int64_t)x.b * a.K_cap + k) * R + lane] = c;
-      }
-      w = lane < R ? a.W[((int64_t)gcur * a.K_cap + k) * R + lane] : 0.0;
     }
-    if (lane < R) sW[lane] = w;
-    wave_sync();
-    if (do_g) solve_g<RM>(gacc, x, sW, R);
-    nacc = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nacc);
-    wave_sync();
   }
-  __syncthreads();
-  // deferred slices, in slice order, by wave 0 with the shared scratch
-  const int nd = sNDef;
-  if (nd > 0 && wv == 0) solve_deferred<RM>(a, sDef, nd, gcur, wout, step, seq, upd, do_g, sVtV, sVt, sScr, sW, gacc,
-                                            nacc);
-  __syncthreads();
-  // the waves' partials in wave order
-  double *sG = sScr;
-  for (int v = 0; v < kSolveWaves; ++v) {
-    if (wv == v) {
+  // the groups of this wave: a fixed exchange tree
 #pragma unroll
-      for (int i = 0; i < NG; ++i) {
-        const int q = lane + 64 * i;
-        if (q < RR) sG[q] = (v == 0) ? gacc[i] : sG[q] + gacc[i];
-      }
-      if (lane == 0) sN[v] = nacc;
+  for (int o = RM; o < 64; o <<= 1) {
+#pragma unroll
+    for (int i = 0; i < RM; ++i) gacc[i] += __shfl_xor(gacc[i], o, 64);
+    nacc += __shfl_xor(nacc, o, 64);
+  }
+  // the waves' partials in wave order (lanes 0 .. R - 1 of each hold the rows)
+  for (int v = 0; v < kSolveWaves; ++v) {
+    if (wv == v && lane < R) {
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+        if (i < R) sG[lane * R + i] = (v == 0) ? gacc[i] : sG[lane * R + i] + gacc[i];
     }
+    if (wv == v && lane == 0) sN[v] = nacc;
     __syncthreads();
   }
   double *p2 = a.part2 + (int64_t)chunk2 * (RR + 1);
@@ -957,7 +954,48 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
     double n = 0.0;
     for (int v = 0; v < kSolveWaves; ++v) n += sN[v];
     p2[RR] = n;
+    a.solve_defer[chunk2] = sNDef;   // the next launch solves these
   }
+}
+
+// The deferred systems of each solve chunk (launched after the solve stage,
+// one workgroup per chunk): wave 0 solves them in slice order by the
+// pseudo-inverse and adds their G and n terms to the chunk's partial after the
+// waves' terms.  Chunks without deferred systems leave at once.
+__global__ __launch_bounds__(64 * kSolveWaves) void k_solve_fix(const PassArgs *args, const BlockMap *map) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sNd;
+  CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
+  const int chunk2 = map ? map[blockIdx.x].local : (int)blockIdx.x;
+  const int nd = a.solve_defer[chunk2];
+  if (nd == 0) return;
+  const StepHeader *h = a.hdr;
+  const int J = a.J, R = a.R, RR = R * R;
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const int seq = h->seq;
+  const int64_t step = h->step;
+  const int gcur = a.ctl->gcur;
+  const int win = (a.pass == 0) ? gcur : 1 - gcur;
+  const bool upd = a.mode == 0;
+  const VBundleView vb = vb_view(a.vb + (int64_t)(upd ? win : gcur) * a.vb_stride, J, R);
+  const SolveLds L = solve_lds(J, R);
+  double *sVtV = (double *)(smem + L.oVtV);
+  float *sVt = (float *)(smem + L.oVt);
+  double *sw = (double *)(smem + L.oW);
+  double *sScr = (double *)(smem + L.oScr);
+  double *sGd = sScr + (size_t)(2 * R * R + 2 * R + 3 * 64) + 32;
+  for (int e = tid; e < RR; e += blockDim.x) sVtV[(e / R) * (R + 1) + e % R] = vb.VtV[e];
+  if (upd && !a.lagged)
+    for (int e = tid; e < R * J; e += blockDim.x) sVt[(e / J) * L.vts + e % J] = vb.Vt32[e];
+  __syncthreads();
+  const int k0 = chunk2 * h->chunk2;
+  if (wv == 0)
+    solve_deferred(a, a.slow_list + k0, nd, gcur, 1 - gcur, step, seq, upd, !a.lagged || !upd, sVtV, sVt, L.vts,
+                   sScr, sw, sGd, &sNd);
+  __syncthreads();
+  double *p2 = a.part2 + (int64_t)chunk2 * (RR + 1);
+  for (int q = tid; q < RR; q += blockDim.x) p2[q] += sGd[q];
+  if (tid == 0) p2[RR] += sNd;
 }
 
 template <int RM>
@@ -1321,6 +1359,13 @@ static size_t rows_fast_lds(int J, int R, bool mixed) {
 
 size_t split_rows_lds(int J, int R, int mixed) { return rows_fast_lds(J, R, mixed != 0); }
 size_t split_rows_slow_lds(int J, int R) { return rows_lds(J, R).bytes; }
+
+int launch_split_solve_fix(const PassArgs *args, const BlockMap *map, int n_blocks, hipStream_t s, size_t lds) {
+  if (n_blocks <= 0) return 0;
+  if (int e = allow_lds_s(k_solve_fix, lds)) return e;
+  hipLaunchKernelGGL(k_solve_fix, dim3(n_blocks), dim3(64 * kSolveWaves), lds, s, args, map);
+  return (int)hipGetLastError();
+}
 
 void split_kernel_name(int stage, const PassArgs &a, char *buf, size_t n) {
   const int mx = a.mixed ? 1 : 0;
