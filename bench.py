@@ -65,6 +65,14 @@ def algorithmic_bytes(M, K, K_t, J, R, words=1):
 KERNEL_SOURCES = ("dash_dev.h", "dash_math.h", "dash_tiles.h", "dash_kernels.hip", "dash_split.hip")
 
 
+def rows_stage_bytes(M, K_t, J, R, words=1):
+    """Bytes the split sweep's row stage must move: the new rows read, U_new
+    written, and each touched slice's Y_k / D_k read and the folded ones
+    written (words per entry as above), its n_k read and written and its c_k
+    written."""
+    return M * J * 4 + M * R * 4 + K_t * (2 * words * (R * J + R * R) * 4 + 16 + R * 8)
+
+
 def _source_digest():
     """SHA-256 over the device sources of the update kernels."""
     import hashlib
@@ -112,6 +120,7 @@ def main():
                     help="serve: stream time replayed closed-loop after the open-loop phase")
     ap.add_argument("--streams", type=int, default=64, help="serve: number of streams")
     ap.add_argument("--closed-depth", type=int, default=8, help="serve: requests in flight per stream, closed loop")
+    ap.add_argument("--no-queue", action="store_true", help="serve: skip the 2 GB admission-queue run")
     ap.add_argument("--autotune", type=int, default=0,
                     help="N > 0: the warm-up updates try every launch schedule N times and keep the fastest")
     ap.add_argument("--graph", type=int, default=0,
@@ -219,20 +228,25 @@ def main():
     value = rows / (dev_ms / 1e3)
 
     # algorithmic bytes of the sampled (event-timed) passes; update index s = W_ + i + 1
-    bytes_pass, bytes_all = 0, 0
+    # the dominant kernel: the fused sweep (wave variant: the whole update's
+    # bytes) or the split sweep's row stage (its own bytes); its launches are
+    # the "pass" events of the sampled updates
+    sched = g.schedule()
+    split = sched["variant"] != 0
+    kernel = "k_pass_wave" if not split else "k_rows"
+    words = 2 if args.precision == "mixed" else 1
+    bytes_pass, bytes_all, n_sampled = 0, 0, 0
     for i in range(K_):
         b = batches[W_ + i]
         s = W_ + i + 1
-        nb = algorithmic_bytes(b.M, wl.K_at(s), b.n_groups + b.n_new, wl.J, wl.R,
-                               words=2 if args.precision == "mixed" else 1) * wl.n_iter
+        nb = algorithmic_bytes(b.M, wl.K_at(s), b.n_groups + b.n_new, wl.J, wl.R, words=words) * wl.n_iter
         bytes_all += nb
         if args.sample_every > 0 and s % args.sample_every == 0:
-            bytes_pass += nb
+            bytes_pass += (rows_stage_bytes(b.M, b.n_groups + b.n_new, wl.J, wl.R, words) * wl.n_iter
+                           if split else nb)
+            n_sampled += wl.n_iter
     pass_ms = prof["pass_ms"]
     achieved = bytes_pass / (pass_ms / 1e3) / 1e9 if pass_ms > 0 else None
-
-    sched = g.schedule()
-    kernel = "k_pass_wave" if sched["variant"] == 0 else "k_rows"
     out = {
         "metric": METRIC,
         "value": value,
@@ -258,7 +272,12 @@ def main():
                          f"({prof['updates']} sampled)",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "kernel": kernel, "algorithmic_bytes_per_step": bytes_all / K_},
+                     "kernel": kernel, "algorithmic_bytes_per_step": bytes_all / K_,
+                     "algorithmic_bytes_per_launch": bytes_pass / n_sampled if n_sampled else None,
+                     "avg_launch_us": 1e3 * pass_ms / n_sampled if n_sampled else None,
+                     "timing": f"HIP events around the row stage (and its deferred-slice launch) of every "
+                               f"{args.sample_every}-th update" if split else
+                               f"HIP events around the sweep of every {args.sample_every}-th update"},
         "final_fit": last["fit"],
         "gen_s": t_gen,
     }
@@ -461,6 +480,7 @@ def serve_main(args):
     # open loop: each request submitted at its arrival time
     sched = sorted((q.t, i, qi) for i, st in enumerate(streams) for qi, q in enumerate(st.requests)
                    if 0.2 <= q.t < T_open)
+    st_warm = srv.stats()
     lag = []
     h0 = time.perf_counter()
     t_base = sched[0][0] if sched else 0.0
@@ -479,17 +499,17 @@ def serve_main(args):
     h1 = time.perf_counter()
     collect()
     open_reps = reports[n_warm_reports:]
-    open_lat = np.array([r["latency_us"] for r in open_reps]) / 1e3
+    open_lat = np.array([r["latency_us"] for r in open_reps]) / 1e3 if open_reps else np.zeros(1)
     open_rows = sum(r["rows"] for r in open_reps)
     st_open = srv.stats()
 
-    # closed loop: QD requests in flight per stream, profiled every 10th tick
+    # closed loop: QD requests in flight per stream, profiled every N-th tick
     todo = [[qi for qi, q in enumerate(st.requests) if q.t >= T_open] for st in streams]
     nxt = [0] * n_streams
     inflight = [0] * n_streams
     done_upto = [0] * n_streams      # index into sent[i] of the first request not yet consumed
     n_before = len(reports)
-    srv.profile(10)
+    srv.profile(args.sample_every)
     h2 = time.perf_counter()
     QD = args.closed_depth
     for i in range(n_streams):
@@ -522,6 +542,14 @@ def serve_main(args):
     kstats, kticks = srv.profile_read()
     srv.profile(0)
     srv.stop()
+    if args.copy_mb > 0:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     all_committed = all(r["committed"] == 1 for r in reports)
 
     # the sampled streams' cuts and fits, for the oracle
@@ -546,8 +574,8 @@ def serve_main(args):
         roof.update(achieved=ach, frac=ach / HBM_PEAK_GBS, kernel=kern["name"],
                     avg_launch_us=1e3 * kern["ms"] / kern["launches"],
                     algorithmic_bytes_per_launch=kern["bytes"] / kern["launches"],
-                    timing=f"HIP events on the server's stream around every launch of every 10th tick "
-                           f"({kticks} ticks timed)")
+                    timing=f"HIP events on the server's stream around every launch of every "
+                           f"{args.sample_every}-th tick of the closed loop ({kticks} ticks timed)")
         roof["traffic"] = counter_traffic(kern["name"].split("<")[0], "serve_mixed" if prec else "serve")
     ticks_closed = st_closed["ticks"] - st_open["ticks"]
     out = {
@@ -570,7 +598,7 @@ def serve_main(args):
                        "note": "open loop at the arrival times: submit of an update's first request to its "
                                "commit seen by the server's loop thread"},
         "open_loop": {"rows_per_s": open_rows / (h1 - h0), "offered_rows_per_s": 2000.0 * n_streams,
-                      "updates": len(open_reps), "ticks": st_open["ticks"],
+                      "updates": len(open_reps), "ticks": st_open["ticks"] - st_warm["ticks"],
                       "submit_lag_ms_p99": 1e3 * float(np.percentile(lag, 99)) if lag else None},
         "closed_loop": {"latency_ms_p50": float(np.percentile([r["latency_us"] for r in closed_reps], 50)) / 1e3,
                         "latency_ms_p99": float(np.percentile([r["latency_us"] for r in closed_reps], 99)) / 1e3,
@@ -585,7 +613,8 @@ def serve_main(args):
     srv.close()
     del drows, dnew
     torch.cuda.synchronize()
-    out["queueing"] = serve_queueing(streams[: n_streams], prec, kw_of, to)
+    if not args.no_queue:
+        out["queueing"] = serve_queueing(streams[: n_streams], prec, kw_of, to)
     if not args.no_oracle:
         out["fit_check"], out["cpu_baseline"] = serve_oracle_leg(streams, cuts, fits, sample, args.oracle_seconds)
     print(json.dumps(out, default=_json_default), flush=True)
