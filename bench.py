@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--streams", type=int, default=64, help="serve: number of streams")
     ap.add_argument("--closed-depth", type=int, default=8, help="serve: requests in flight per stream, closed loop")
     ap.add_argument("--no-queue", action="store_true", help="serve: skip the 2 GB admission-queue run")
+    ap.add_argument("--study", default=None, choices=["cycle", "lambda", "static"],
+                    help="instead of the benchmark: time per update against the update cycle, the errors against "
+                         "lambda, or the streaming update against a static recompute (prints its own JSON line)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="N > 0: the warm-up updates try every launch schedule N times and keep the fastest")
     ap.add_argument("--graph", type=int, default=0,
@@ -140,6 +143,8 @@ def main():
               "(the update would shard by slice with one all-reduce of F, G per pass).", file=sys.stderr)
         sys.exit(2)
 
+    if args.study:
+        return study_main(args)
     if args.workload == "serve":
         if args.precision is None:
             args.precision = "mixed"
@@ -664,6 +669,103 @@ def serve_queueing(streams, prec, kw_of, to, budget=2 << 30, windows=10):
     return {"budget_gb": budget / 2 ** 30, "streams": len(streams), "admitted_at_open": admitted0,
             "queued_at_open": len(streams) - admitted0, "served": len(served), "updates": updates,
             "peak_used_gb": peak_used / 2 ** 30, "wall_s": wall}
+
+
+def study_main(args):
+    """Synthetic studies of the update (the paper's update-cycle scalability,
+    lambda sensitivity and the static-recompute comparison, on planted data of
+    the mid workload's shape: J = 88, R = 10, K0 = 2000)."""
+    import torch
+    from paper_2305_18376_amd.dash import Dash
+    from paper_2305_18376_amd.synth import make_workload
+    dev = torch.device("cuda", 0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+    def stream(wl, lam, n_steps, cycle=None, scores=False):
+        ptr, X, U = wl.init_data(want_u=True)
+        g = Dash(wl.J, wl.R, lam=lam, max_slices=wl.K_max + 64, max_rows=1 << 21, max_groups=1 << 16)
+        g.init_from_factors(ptr, to(X), to(U), to(wl.W[: wl.K0]), to(wl.V))
+        if scores:
+            g.anomaly(5)
+        g.spans(True)
+        out = []
+        for s in range(1, n_steps + 1):
+            b = wl.step(s)
+            if cycle is not None:   # cycle / 5 rows per slice per update (the first ones of the batch)
+                keep = np.minimum(np.diff(b.row_ptr), max(1, cycle // 5))
+                rows = np.concatenate([b.rows[b.row_ptr[i]:b.row_ptr[i] + keep[i]] for i in range(b.n_groups)])
+                rptr = np.concatenate([[0], np.cumsum(keep)]).astype(np.int64)
+            else:
+                rows, rptr = b.rows, b.row_ptr
+            rd, nd = to(rows), to(b.new_rows)
+            g.ingest_slices(b.new_ptr, nd)
+            g.ingest_rows(b.row_ids, rptr, rd)
+            torch.cuda.synchronize()
+            rep = g.update()
+            out.append((rep, int(rptr[-1] + b.new_ptr[-1])))
+        spans = g.spans_read()
+        g.spans(False)
+        return g, out, spans, (ptr, X)
+
+    res = {"study": args.study, "data": "synthetic", "n_gpus": 1}
+    if args.study == "cycle":
+        rows = []
+        for cycle in (20, 40, 60, 80, 100):
+            wl = make_workload("mid", n_steps=12, median=24, lo=11, hi=200)
+            wl_cycle = wl
+            g, out, spans, _ = stream(wl_cycle, 0.95, 12, cycle=cycle)
+            sp = np.array(spans[2:]) * 1e3
+            m = np.mean([o[1] for o in out[2:]])
+            rows.append({"cycle": cycle, "rows_per_update": m, "update_us_p50": float(np.median(sp)),
+                         "rows_per_s": m / (float(np.median(sp)) / 1e6)})
+            g.close()
+        res["config"] = ("mid shape (J 88, R 10, K0 2000, initial slices median 24): each update brings cycle/5 "
+                         "rows of every slice and 20 new slices; device span per update (p50 of updates 3..12)")
+        res["points"] = rows
+    elif args.study == "lambda":
+        rows = []
+        for lam in (0.1, 0.3, 0.5, 0.7, 0.9):
+            wl = make_workload("mid", n_steps=12, median=24, lo=11, hi=200)
+            g, out, _, _ = stream(wl, lam, 12, scores=True)
+            te = [o[0]["te"] for o in out[2:]]
+            rows.append({"lambda": lam, "local_error_te_mean": float(np.mean(te)),
+                         "fit_lambda_weighted": out[-1][0]["fit"]})
+            g.close()
+        res["config"] = ("mid shape, 12 updates; local error = te (Definition 2: mean absolute error of the "
+                         "updated model on each update's new rows), global = the lambda-weighted fit of the "
+                         "whole stream after the last update")
+        res["points"] = rows
+    else:
+        wl = make_workload("mid", n_steps=10, median=24, lo=11, hi=200)
+        g, out, spans, (ptr, X) = stream(wl, 1.0, 10)
+        t_update = float(np.median(np.array(spans) * 1e3))
+        # the accumulated tensor: initial rows, then every update's rows, per slice
+        K = wl.K_at(10)
+        parts = [[X[ptr[k]:ptr[k + 1]]] if k < wl.K0 else [] for k in range(K)]
+        for s in range(1, 11):
+            b = wl.step(s)
+            for l, blk in enumerate(b.new_slices()):
+                parts[wl.K_at(s - 1) + l].append(blk)
+            for k, blk in b.groups():
+                parts[k].append(blk)
+        Xa = np.concatenate([np.concatenate(p) for p in parts])
+        pa = np.concatenate([[0], np.cumsum([sum(x.shape[0] for x in p) for p in parts])]).astype(np.int64)
+        h = Dash(wl.J, wl.R, lam=1.0, max_slices=K + 8, max_rows=1024, max_groups=1024,
+                 max_init_rows=int(pa[-1]) + 1, init_max_iter=10)
+        Xd = to(Xa)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ir = h.init(pa, Xd, to(wl.V))
+        torch.cuda.synchronize()
+        t_static = (time.perf_counter() - t0) * 1e6
+        res["config"] = ("mid shape, lambda = 1, 10 updates; the static recompute is the GPU PARAFAC2-ALS "
+                         "(10 iterations, started from the planted V) over every row seen so far")
+        res["points"] = [{"streaming_update_us_p50": t_update, "streaming_fit": out[-1][0]["fit"],
+                          "static_recompute_us": t_static, "static_fit": ir["fit"], "static_iters": ir["iters"],
+                          "rows_total": int(pa[-1]), "speedup": t_static / t_update}]
+        g.close()
+        h.close()
+    print(json.dumps(res, default=_json_default), flush=True)
 
 
 if __name__ == "__main__":
