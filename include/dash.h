@@ -263,18 +263,25 @@ const char *dash_last_error(const dash_ctx *ctx);
 dash_status dash_poll(dash_ctx *ctx, dash_update_report *reports, int32_t cap, int32_t *n_done);
 
 /* Autotuning of the launch schedule: with trials > 0 the next updates run in
- * turn with every candidate -- the sweep variant (one wave per slice, or one
- * workgroup per slice), twice the default slices per chunk or not, the final
- * phase fused into the sweep launch or separate -- each `trials` times; every
- * candidate is scored by device time per algorithmic byte of its updates and
- * the best is kept for the updates after that.  Every schedule computes the
- * same update; results differ between schedules only by the order of the
- * FP64 partial sums.  trials = 0 returns to the default schedule.
- * dash_autotune_read reports the schedule in force. */
+ * turn with every candidate -- the sweep variant (the fused one-wave-per-slice
+ * sweep where it applies, or the split sweep), twice the default slices per F
+ * chunk or not, the final phase fused into the sweep launch or separate, the
+ * split sweep's solve chunks at the default size or a quarter of it -- each
+ * `trials` times; every candidate is scored by device time per algorithmic
+ * byte of its updates and the best is kept for the updates after that.  Every
+ * schedule computes the same update; results differ between schedules only by
+ * the order of the FP64 partial sums.  trials = 0 returns to the default
+ * schedule.  With a cache (dash_autotune_cache) the shape of the first update
+ * of the run -- J, R, precision, statistics mode, passes, and log2 buckets of
+ * the mean rows per touched slice and of the slice count -- is looked up
+ * first: a cached schedule is taken at once, and a finished run stores its
+ * winner.  dash_autotune_read reports the schedule in force. */
 typedef struct dash_schedule {
   int32_t variant;     /* 0: one wave per slice, 1: one workgroup per slice     */
   int32_t spread;      /* slices per chunk relative to the default (1 or 2)     */
   int32_t fused;       /* 1: the final phase runs in the sweep launch           */
+  int32_t solve_div;   /* split sweep: solve chunks of 1/solve_div the default   */
+  int32_t from_cache;  /* 1: the schedule came from the autotuner's cache        */
   int32_t tuned;       /* 1: chosen by a finished autotuning run                */
   int32_t candidates;  /* schedules of the last autotuning run                  */
   double ns_per_kb;    /* measured device ns per KiB of algorithmic traffic of
@@ -282,6 +289,10 @@ typedef struct dash_schedule {
 } dash_schedule;
 dash_status dash_autotune(dash_ctx *ctx, int32_t trials);
 dash_status dash_autotune_read(dash_ctx *ctx, dash_schedule *out);
+/* The autotuner's cache file (JSON lines, one tuned schedule per shape key;
+ * read at the start of a tuning run, rewritten when a run finishes), or NULL
+ * for none.  Errors: DASH_E_INVALID_ARG. */
+dash_status dash_autotune_cache(dash_ctx *ctx, const char *path);
 
 /* Graph mode (enable = 1): each update's launches -- descriptor fetch, the
  * n_iter sweeps and final phases -- are replayed from one executable HIP graph

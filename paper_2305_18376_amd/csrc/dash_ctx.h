@@ -44,6 +44,7 @@ struct Schedule {
   int variant;
   int spread;   // 1: the default chunking; 2: twice the slices per chunk
   int fuse;
+  int solve_div = 1;   // split sweep: solve chunks 1/solve_div of the default (more, shorter)
 };
 
 }  // namespace dash
@@ -109,6 +110,9 @@ struct dash_ctx {
   std::vector<int> tune_n;
   int tune_per = 0, tune_next = 0;
   bool tuned = false;
+  std::string tune_cache;    // JSON-lines file of tuned schedules ("" = none)
+  std::string tune_key;      // key of the update shape being tuned
+  bool tune_from_cache = false;
   int fused_lds = 0;   // > 0: the sweep launch runs the final phase too (its dynamic LDS)
   int n_cu = 0;   // compute units of the device
   // pinned

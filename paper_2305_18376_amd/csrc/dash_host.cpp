@@ -72,7 +72,7 @@ void split_chunks(const dash_ctx *c, int K, int *c3_out, int *c2_out) {
   // solve chunks: two workgroups per CU (one resident round), a multiple of
   // the workgroup's four waves; a served stream plans them for the whole
   // device (short chunks: its latency, not its own throughput, matters)
-  const int ns = c->served ? kServeSolveCUs : n;
+  const int ns = (c->served ? kServeSolveCUs : n) * std::max(1, c->sched.solve_div);
   int c2 = std::max(1, std::min(c3, (K + 2 * ns - 1) / (2 * ns)));
   c2 = (c2 + 3) / 4 * 4;
   while ((K + c2 - 1) / c2 > kMaxChunks2) c2 += 4;
@@ -417,6 +417,74 @@ double device_us(const Report &r) {
   return (r.t_end > r.t_start && r.t_start) ? (double)(r.t_end - r.t_start) / kRealtimeMHz : 0.0;
 }
 
+// The autotuner's cache: one JSON object per line,
+//   {"key": "<shape>", "variant": v, "spread": s, "fuse": f, "solve_div": d, "ns_per_kb": x}
+// keyed by the device architecture, J, R, precision, statistics mode, passes,
+// the mean rows per touched slice (log2 bucket) and the slice count (log2
+// bucket) of the update the tuning started on.
+std::string tune_key_of(const dash_ctx *c) {
+  int touched = 0;
+  int last = -1;
+  std::vector<int> ids;
+  ids.reserve(c->pending.size());
+  for (const PendingGroup &g : c->pending) ids.push_back(g.slice);
+  std::sort(ids.begin(), ids.end());
+  for (int id : ids)
+    if (id != last) {
+      ++touched;
+      last = id;
+    }
+  const double mean = touched ? (double)c->rows_pending / touched : 0.0;
+  const int mb = (int)std::floor(std::log2(1.0 + mean));
+  const int kb = (int)std::floor(std::log2(1.0 + (double)c->K_pending));
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "gfx950/J%d/R%d/p%d/s%d/i%d/m%d/k%d", c->J, c->R, (int)c->cfg.precision,
+                (int)c->cfg.stats_mode, (int)c->cfg.n_iter, mb, kb);
+  return buf;
+}
+
+bool tune_cache_lookup(const dash_ctx *c, const std::string &key, Schedule *out) {
+  FILE *fp = std::fopen(c->tune_cache.c_str(), "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, fp)) {
+    char k[200];
+    Schedule s{};
+    double x = 0.0;
+    if (std::sscanf(line, "{\"key\": \"%199[^\"]\", \"variant\": %d, \"spread\": %d, \"fuse\": %d, \"solve_div\": %d, \"ns_per_kb\": %lf}",
+                    k, &s.variant, &s.spread, &s.fuse, &s.solve_div, &x) == 6 &&
+        key == k && (s.variant == kPassWave || s.variant == kPassSplit) && s.spread >= 1 && s.solve_div >= 1) {
+      *out = s;   // the last entry of a key wins
+      found = true;
+    }
+  }
+  std::fclose(fp);
+  // a cached wave schedule only where the wave sweep applies to this context
+  if (found && out->variant == kPassWave && c->variant != kPassWave) return false;
+  if (found && out->fuse && fused_pass_lds(out->variant, c->J, c->R) == 0) out->fuse = 0;
+  return found;
+}
+
+void tune_cache_store(const dash_ctx *c, const std::string &key, const Schedule &s, double ns_per_kb) {
+  std::vector<std::string> keep;
+  if (FILE *fp = std::fopen(c->tune_cache.c_str(), "r")) {
+    char line[512];
+    const std::string tag = "{\"key\": \"" + key + "\"";
+    while (std::fgets(line, sizeof line, fp))
+      if (std::strncmp(line, tag.c_str(), tag.size()) != 0) keep.push_back(line);
+    std::fclose(fp);
+  }
+  const std::string tmp = c->tune_cache + ".tmp";
+  FILE *fp = std::fopen(tmp.c_str(), "w");
+  if (!fp) return;
+  for (const std::string &l : keep) std::fputs(l.c_str(), fp);
+  std::fprintf(fp, "{\"key\": \"%s\", \"variant\": %d, \"spread\": %d, \"fuse\": %d, \"solve_div\": %d, \"ns_per_kb\": %.4f}\n",
+               key.c_str(), s.variant, s.spread, s.fuse, s.solve_div, ns_per_kb);
+  std::fclose(fp);
+  std::rename(tmp.c_str(), c->tune_cache.c_str());
+}
+
 // Fold one reaped update into the autotuner's scores; once every candidate has
 // run tune_per times, keep the one with the least device time per byte.
 void tune_account(dash_ctx *c, const InFlight &f, const Report &r) {
@@ -433,6 +501,8 @@ void tune_account(dash_ctx *c, const InFlight &f, const Report &r) {
     if (c->tune_us[i] / c->tune_bytes[i] < c->tune_us[best] / c->tune_bytes[best]) best = i;
   c->sched = c->tune_cands[best];
   c->tuned = true;
+  if (!c->tune_cache.empty() && !c->tune_key.empty())
+    tune_cache_store(c, c->tune_key, c->sched, 1e3 * c->tune_us[best] / (c->tune_bytes[best] / 1024.0));
 }
 
 void graph_reset(dash_ctx *c) {
@@ -1183,6 +1253,16 @@ dash_status dash_update_async(dash_ctx *c) {
     dash_status s = dash_wait(c, nullptr);
     if (s != DASH_OK) return s;
   }
+  // a tuning run about to start: a cached schedule for this shape ends it at once
+  if (!c->tune_cands.empty() && !c->tuned && c->tune_next == 0 && c->tune_key.empty()) {
+    c->tune_key = tune_key_of(c);
+    Schedule cached{};
+    if (!c->tune_cache.empty() && tune_cache_lookup(c, c->tune_key, &cached)) {
+      c->sched = cached;
+      c->tuned = true;
+      c->tune_from_cache = true;
+    }
+  }
   BuiltUpdate b;
   if (dash_status st = build_update(c, &b)) return st;
   const int s = b.stage, nch = b.nch, n_items = b.n_items;
@@ -1401,6 +1481,8 @@ dash_status dash_autotune(dash_ctx *c, int32_t trials) {
   c->tune_n.clear();
   c->tune_next = 0;
   c->tuned = false;
+  c->tune_key.clear();
+  c->tune_from_cache = false;
   const int fl = (int)fused_pass_lds(c->variant, c->J, c->R);
   c->sched = Schedule{c->variant, 1, fl > 0 ? 1 : 0};
   if (trials == 0) return DASH_OK;
@@ -1408,10 +1490,12 @@ dash_status dash_autotune(dash_ctx *c, int32_t trials) {
   if (c->variant == kPassWave) variants.push_back(kPassSplit);
   for (int v : variants)
     for (int spread : {1, 2})
-      for (int fuse : {1, 0}) {
-        if (fuse && fused_pass_lds(v, c->J, c->R) == 0) continue;
-        c->tune_cands.push_back(Schedule{v, spread, fuse});
-      }
+      for (int fuse : {1, 0})
+        for (int sd : {1, 4}) {
+          if (fuse && fused_pass_lds(v, c->J, c->R) == 0) continue;
+          if (sd > 1 && v != kPassSplit) continue;   // solve chunks exist in the split sweep only
+          c->tune_cands.push_back(Schedule{v, spread, fuse, sd});
+        }
   c->tune_us.assign(c->tune_cands.size(), 0.0);
   c->tune_bytes.assign(c->tune_cands.size(), 0.0);
   c->tune_n.assign(c->tune_cands.size(), 0);
@@ -1424,15 +1508,23 @@ dash_status dash_autotune_read(dash_ctx *c, dash_schedule *out) {
   out->variant = c->sched.variant;
   out->spread = c->sched.spread;
   out->fused = c->sched.fuse;
+  out->solve_div = c->sched.solve_div;
+  out->from_cache = c->tune_from_cache ? 1 : 0;
   out->tuned = c->tuned ? 1 : 0;
   out->candidates = (int32_t)c->tune_cands.size();
   out->ns_per_kb = 0.0;
   for (size_t i = 0; i < c->tune_cands.size(); ++i) {
     const Schedule &k = c->tune_cands[i];
     if (k.variant == c->sched.variant && k.spread == c->sched.spread && k.fuse == c->sched.fuse &&
-        c->tune_bytes[i] > 0)
+        k.solve_div == c->sched.solve_div && c->tune_bytes[i] > 0)
       out->ns_per_kb = 1e3 * c->tune_us[i] / (c->tune_bytes[i] / 1024.0);
   }
+  return DASH_OK;
+}
+
+dash_status dash_autotune_cache(dash_ctx *c, const char *path) {
+  if (!c) return DASH_E_INVALID_ARG;
+  c->tune_cache = path ? path : "";
   return DASH_OK;
 }
 

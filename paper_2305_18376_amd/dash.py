@@ -64,8 +64,9 @@ class Dims(C.Structure):
 
 
 class Schedule(C.Structure):
-    _fields_ = [("variant", C.c_int32), ("spread", C.c_int32), ("fused", C.c_int32), ("tuned", C.c_int32),
-                ("candidates", C.c_int32), ("ns_per_kb", C.c_double)]
+    _fields_ = [("variant", C.c_int32), ("spread", C.c_int32), ("fused", C.c_int32), ("solve_div", C.c_int32),
+                ("from_cache", C.c_int32), ("tuned", C.c_int32), ("candidates", C.c_int32),
+                ("ns_per_kb", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -127,6 +128,7 @@ _SIGS = {
     "dash_graph": (C.c_int, [_P, C.c_int32]),
     "dash_autotune": (C.c_int, [_P, C.c_int32]),
     "dash_autotune_read": (C.c_int, [_P, C.POINTER(Schedule)]),
+    "dash_autotune_cache": (C.c_int, [_P, C.c_char_p]),
     "dash_spans_read": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_server_create": (C.c_int, [C.c_int32, C.c_int64, C.POINTER(_P)]),
     "dash_server_destroy": (C.c_int, [_P]),
@@ -301,8 +303,12 @@ class Dash:
     def update_async(self):
         self._check(lib().dash_update_async(self._h), "dash_update_async")
 
-    def autotune(self, trials=2):
-        """Try every launch schedule `trials` times over the next updates and keep the fastest."""
+    def autotune(self, trials=2, cache=None):
+        """Try every launch schedule `trials` times over the next updates and keep the fastest;
+        with `cache` (a file path) a schedule tuned earlier for the same update shape is taken
+        at once, and a finished run stores its winner there."""
+        self._check(lib().dash_autotune_cache(self._h, str(cache).encode() if cache else None),
+                    "dash_autotune_cache")
         self._check(lib().dash_autotune(self._h, int(trials)), "dash_autotune")
 
     def schedule(self):

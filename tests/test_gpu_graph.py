@@ -91,4 +91,42 @@ def test_autotune_picks_a_schedule_and_stays_exact():
         rep = g.update()
         assert abs(rep["fit"] - r.fit) <= 1e-5, (s, rep["fit"], r.fit)
     sc = g.schedule()
-    assert sc["tuned"] == 1 and sc["candidates"] >= 4 and sc["ns_per_kb"] > 0, sc
+    assert sc["tuned"] == 1 and sc["candidates"] >= 8 and sc["ns_per_kb"] > 0, sc
+
+
+def test_autotune_cache_reuses_the_schedule_tuned_for_the_same_shape(tmp_path):
+    """A finished tuning run stores its winner under the update's shape key; a
+    second context of the same shape takes it at its first update, and its
+    updates stay exact."""
+    import json
+    from oracle.dash_oracle import DashOracle
+    cache = tmp_path / "tune.jsonl"
+    wl = make_workload("mid", K0=300, n_steps=12)
+    ptr, X, U = wl.init_data(want_u=True)
+    a = make(wl, ptr, X, U, False)
+    a.autotune(1, cache=cache)
+    keep = []
+    for s in range(1, 11):
+        stage(a, wl.step(s), keep)
+        a.update()
+    sa = a.schedule()
+    assert sa["tuned"] == 1 and sa["from_cache"] == 0, sa
+    lines = [json.loads(x) for x in cache.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0]["key"].startswith("gfx950/J88/R10/")
+    assert (lines[0]["variant"], lines[0]["spread"], lines[0]["fuse"], lines[0]["solve_div"]) == \
+        (sa["variant"], sa["spread"], sa["fused"], sa["solve_div"])
+    b = make(wl, ptr, X, U, False)
+    b.autotune(1, cache=cache)
+    o = DashOracle(wl.J, wl.R, wl.lam)
+    o.init_from_factors([X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)], [U[ptr[k]:ptr[k + 1]] for k in range(wl.K0)],
+                        wl.W[: wl.K0], wl.V)
+    for s in range(1, 4):
+        bt = wl.step(s)
+        r = o.update(bt.groups(), bt.new_slices())
+        stage(b, bt, keep)
+        rep = b.update()
+        assert abs(rep["fit"] - r.fit) <= 1e-5, (s, rep["fit"], r.fit)
+        sb = b.schedule()
+        assert sb["tuned"] == 1 and sb["from_cache"] == 1, sb
+        assert (sb["variant"], sb["spread"], sb["fused"], sb["solve_div"]) == \
+            (sa["variant"], sa["spread"], sa["fused"], sa["solve_div"])
