@@ -43,6 +43,7 @@ namespace {
 constexpr int kTickStages = 4;        // pinned launch tables in rotation
 constexpr int kMaxServed = 4096;      // stream ids
 constexpr int kTicksInFlight = 2;     // loop mode: ticks on the device at once
+constexpr int kAuxStreams = 3;        // extra streams: kernel classes of one stage run side by side
 
 double now_us() {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -97,6 +98,7 @@ struct Sel {
 
 // One launch of the tick: a stage's kernel class over its streams.
 struct Launch {
+  int group;          // launches of one (pass, stage): independent of each other
   int stage;          // 0 rows, 1 deferred slices, 2 solve, 3 F, 4 group reduction, 5 final phase
   PassArgs rep;       // a member's host arguments (the class is read from them)
   size_t map_off;     // byte offset of its block map in the table
@@ -133,6 +135,7 @@ double stage_bytes(int stage, const dash_ctx *c, const BuiltUpdate &b) {
 struct dash_server {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t aux[kAuxStreams] = {};   // a stage's further kernel classes, joined back by events
   int64_t budget = 0, used = 0;
   std::vector<Stream> streams;
   std::deque<int32_t> admit_queue;
@@ -211,6 +214,8 @@ dash_status take_tick_buf(dash_server *srv, size_t bytes, TickBuf **out) {
 dash_status ensure_stream(dash_server *srv) {
   if (srv->stream) return DASH_OK;
   if (hipSetDevice(srv->device) != hipSuccess || hipStreamCreate(&srv->stream) != hipSuccess) return DASH_E_DEVICE;
+  for (auto &a : srv->aux)
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) return DASH_E_DEVICE;
   return DASH_OK;
 }
 
@@ -378,10 +383,10 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
   // launch table: fetch jobs (one per stream, one for the block maps), maps
   std::vector<BlockMap> maps;
   std::vector<Launch> launches;
-  int max_iter = 1;
+  int max_iter = 1, n_group = 0;
   for (const Sel &x : sel) max_iter = std::max(max_iter, x.c->cfg.n_iter);
   for (int p = 0; p < max_iter; ++p) {
-    for (int stage = 0; stage < 6; ++stage) {
+    for (int stage = 0; stage < 6; ++stage, ++n_group) {
       // classes in order of first appearance (deterministic)
       std::vector<std::pair<int, std::vector<int>>> classes;
       for (int i = 0; i < (int)sel.size(); ++i) {
@@ -410,6 +415,7 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
       }
       for (const auto &cl : classes) {
         Launch L{};
+        L.group = n_group;
         L.stage = stage;
         L.map_off = maps.size();
         L.n_blocks = 0;
@@ -463,23 +469,38 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
   jobs[sel.size()] = FetchJob{tb->hdev + off_maps, tb->dev + off_maps, (int64_t)map_bytes, nullptr};
   const BlockMap *dmaps = (const BlockMap *)(tb->dev + off_maps);
 
-  hipStream_t s = srv->stream;
+  hipStream_t s0 = srv->stream;
   auto dev_fail = [&](int e) {
     srv->err = std::string("tick launch failed: ") + hipGetErrorString((hipError_t)e);
     return DASH_E_DEVICE;
   };
-  if (int e = launch_fetch_list((const FetchJob *)tb->hdev, n_jobs, max_bytes, s)) return dev_fail(e);
+  if (int e = launch_fetch_list((const FetchJob *)tb->hdev, n_jobs, max_bytes, s0)) return dev_fail(e);
   for (const Sel &x : sel) {
     // the stage's pinned block is free again once the fetch has run
-    if (hipEventRecord(x.c->stage_ev[x.b.stage], s) != hipSuccess) return DASH_E_DEVICE;
+    if (hipEventRecord(x.c->stage_ev[x.b.stage], s0) != hipSuccess) return DASH_E_DEVICE;
     x.c->stage_used[x.b.stage] = true;
   }
   const bool timed = srv->prof_every > 0 && srv->stats.ticks % srv->prof_every == 0;
   if (timed && srv->prof_pending.size() > 4096) {
-    if (hipStreamSynchronize(s) != hipSuccess) return DASH_E_DEVICE;
+    if (hipStreamSynchronize(s0) != hipSuccess) return DASH_E_DEVICE;
     if (dash_status st = prof_fold(srv)) return st;
   }
-  for (const Launch &L : launches) {
+  // the launches of one group run side by side: the first on the tick's
+  // stream, the others on the extra streams after an event, joined back
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const Launch &L = launches[li];
+    const bool first = li == 0 || launches[li - 1].group != L.group;
+    const bool last = li + 1 == launches.size() || launches[li + 1].group != L.group;
+    int slot = 0;   // position within the group
+    for (size_t q = li; q > 0 && launches[q - 1].group == L.group; --q) ++slot;
+    if (first && !last) {
+      fork = take_event(srv);
+      if (!fork || hipEventRecord(fork, s0) != hipSuccess) return DASH_E_DEVICE;
+    }
+    hipStream_t s = slot == 0 ? s0 : srv->aux[(slot - 1) % kAuxStreams];
+    if (slot > 0 && hipStreamWaitEvent(s, fork, 0) != hipSuccess) return DASH_E_DEVICE;
     const BlockMap *m = dmaps + L.map_off;
     ProfRec pr{nullptr, nullptr, 0, L.bytes};
     if (timed) {
@@ -510,7 +531,22 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
       if (hipEventRecord(pr.b, s) != hipSuccess) return DASH_E_DEVICE;
       srv->prof_pending.push_back(pr);
     }
+    if (slot > 0) {
+      hipEvent_t j = take_event(srv);
+      if (!j || hipEventRecord(j, s) != hipSuccess) return DASH_E_DEVICE;
+      joins.push_back(j);
+    }
+    if (last) {
+      for (hipEvent_t j : joins) {
+        if (hipStreamWaitEvent(s0, j, 0) != hipSuccess) return DASH_E_DEVICE;
+        srv->ev_pool.push_back(j);   // the wait holds the state it was given
+      }
+      joins.clear();
+      if (fork) srv->ev_pool.push_back(fork);
+      fork = nullptr;
+    }
   }
+  hipStream_t s = s0;
   if (timed) srv->prof_ticks += 1;
   for (const Sel &x : sel) {
     if (!x.b.scored) continue;
@@ -623,6 +659,8 @@ dash_status dash_server_destroy(dash_server *srv) {
     srv->tev_pool.push_back(p.b);
   }
   for (auto e : srv->tev_pool) (void)hipEventDestroy(e);
+  for (auto a : srv->aux)
+    if (a) (void)hipStreamDestroy(a);
   if (srv->stream) (void)hipStreamDestroy(srv->stream);
   delete srv;
   return DASH_OK;
