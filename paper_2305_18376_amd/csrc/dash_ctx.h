@@ -17,7 +17,7 @@ namespace dash {
 constexpr int kStages = 4;             // pinned descriptor blocks in rotation
 constexpr int kMaxChunks2 = 8192;      // bound on solve-stage chunks of the split sweep
 constexpr int kServeCUs = 16;          // compute units a served stream's schedule plans for
-constexpr int kServeSolveCUs = 256;    // the same, for its solve chunks
+constexpr int kServeSolveCUs = 64;     // the same, for its solve chunks
 constexpr int64_t kServeChunkBytes = 512 << 10;   // Y bytes of a served stream's F-stage chunk
 
 struct PendingGroup {
