@@ -44,20 +44,25 @@ namespace dash {
 // Row stage
 // ---------------------------------------------------------------------------
 struct RowsLds {
-  int XS, MB;
+  int XS, US, J16, MB;
   size_t oP, oX, oU, oZf, oW, oWinv, bytes;
 };
 
-// P (J x R), a row block (MB rows, odd stride) that is also the hand-off
-// buffer of dY (R x J) and the scratch of Lemma 1's pseudo-inverse form, the
-// U block (MB x (R+1), also dD), that form's matrix Z (R x R), w and 1/w.
+// P^T (ranks padded to a multiple of 16, row stride XS, zero beyond R and J),
+// a row block (MB rows of stride XS = J16 + 4, where J16 is J rounded up to
+// 16: 16-byte rows whose four-row steps fall in different banks) that is also
+// the hand-off buffer of dY (R x J) and the scratch of Lemma 1's
+// pseudo-inverse form, the U block (MB x US, US = 16 MT + 4; also dD), that
+// form's matrix Z (R x R), w and 1/w.
 __host__ __device__ inline RowsLds rows_lds(int J, int R) {
   RowsLds L;
-  L.XS = J | 1;
+  L.J16 = (J + 15) / 16 * 16;
+  L.XS = L.J16 + 4;
+  L.US = (R + 15) / 16 * 16 + 4;
   L.MB = (J <= 128) ? 64 : 32;
   size_t o = 0;
   L.oP = o;
-  o = align_up(o + (size_t)J * R * 4, 16);
+  o = align_up(o + (size_t)((R + 15) / 16 * 16) * L.XS * 4, 16);
   L.oX = o;
   size_t xb = (size_t)L.MB * L.XS * 4;
   const size_t scr = (size_t)(2 * R * R + R + 64) * 8 + 64 * 4;
@@ -68,7 +73,7 @@ __host__ __device__ inline RowsLds rows_lds(int J, int R) {
   xb = std::max(xb, (size_t)4 * 8 * 64 * 8);
   o = align_up(o + xb, 16);
   L.oU = o;
-  o = align_up(o + (size_t)L.MB * (R + 1) * 4, 16);
+  o = align_up(o + (size_t)L.MB * L.US * 4, 16);
   L.oZf = o;
   o = align_up(o + (size_t)R * R * 4, 16);
   L.oW = o;
@@ -201,8 +206,16 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
   const int blk = map ? map[blockIdx.x].local : (int)blockIdx.x;
   const int nblk = map ? map[blockIdx.x].pad : (int)gridDim.x;   // this context's workgroups
   __shared__ int sItem, sDefer;
-  __shared__ int sNext[5];   // the next slice: item index, slice, g0, g1, rows
+  __shared__ int sNext[5];   // the deferred-slice kernel's item: index, slice, g0, g1, rows
   __shared__ double sDn[4];
+  // The fast kernel's look-ahead: the descriptors of its items i, i + 1, i + 2
+  // (a ring of three) and the state words of items i, i + 1 (a ring of two),
+  // so that a slice starts its HBM loads without dependent round trips.
+  // Words of sMeta: [0, 32) W row, 32 + b n in buffer b, 34 first row group's
+  // source, 35 its first output row, 36 its row count (low half), 37 the
+  // slice's buffer (low half) and last fold (high half).
+  __shared__ __align__(16) Item sDesc[3];
+  __shared__ uint64_t sMeta[2][38];
   const StepHeader *h = a.hdr;
   const int J = a.J, R = a.R, RR = R * R;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -239,38 +252,71 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       bPt[r * LB.XS + j] = (__bf16)((r < R && j < J) ? vb.P32[j * R + r] : 0.f);
     }
   } else {
-    for (int e = tid; e < J * R; e += 256) sP[e] = vb.P32[e];
+    // P^T, ranks padded to a multiple of 16 and columns to J16 (zero)
+    const int R16 = (R + 15) & ~15;
+    for (int e = tid; e < R16 * L.XS; e += 256) {
+      const int r = e / L.XS, j = e - r * L.XS;
+      sP[e] = (r < R && j < J) ? vb.P32[j * R + r] : 0.f;
+    }
   }
   // the entries of V^T this thread multiplies for c_k
   float vt[RW][JW];
+  {
+    const auto rv = buf_rsrc(vb.Vt32, R * J * 4);
 #pragma unroll
-  for (int rr = 0; rr < RW; ++rr)
+    for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
-    for (int jj = 0; jj < JW; ++jj) {
-      const int r = wv + 4 * rr, j = lane + 64 * jj;
-      vt[rr][jj] = (r < R && j < J) ? vb.Vt32[r * J + j] : 0.f;
-    }
+      for (int jj = 0; jj < JW; ++jj) {
+        const int r = wv + 4 * rr, j = lane + 64 * jj;
+        vt[rr][jj] = buf_ldf(rv, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+      }
+  }
   // pivots and diagonal of V^T V for Lemma 1's acceptance rule (wave 0, lane r)
   const double pivl = lane < R ? vb.piv[lane] : 0.0;
   const double arrl = lane < R ? vb.VtV[lane * R + lane] : 0.0;
 
+  // Wave 0's gather for the fast kernel: lane l loads word l of item it1's
+  // state words (descriptor d1) and lanes 37, 38 the descriptor of item it2;
+  // the values stay in registers until put() stores them, so their latency
+  // hides behind a slice's work.
+  auto gather = [&](int it1, const Item &d1, int it2, uint64_t &g64, uint32_t &g32) {
+    const int l = threadIdx.x & 63;
+    g64 = 0;
+    g32 = 0;
+    if (it1 >= n_items) return;
+    const int k1 = d1.slice;
+    const bool grp = d1.g0 < d1.g1;
+    if (l < R) g64 = (uint64_t)__double_as_longlong(a.W[((int64_t)win * a.K_cap + k1) * R + l]);
+    else if (l == 32 || l == 33) g64 = (uint64_t)__double_as_longlong(a.n[(int64_t)(l - 32) * a.K_cap + k1]);
+    else if (l == 34 && grp) g64 = (uint64_t)(uintptr_t)a.groups[d1.g0].src;
+    else if (l == 35 && grp) g64 = (uint64_t)a.groups[d1.g0].out_row;
+    else if (l == 36 && grp) g64 = *(const uint64_t *)&a.groups[d1.g0].nrows;
+    else if ((l == 37 || l == 38) && it2 < n_items) g64 = ((const uint64_t *)(a.items + it2))[l - 37];
+    if (l == 39) g32 = a.cur[(int64_t)gcur * a.K_cap + k1];
+    else if (l == 40) g32 = (uint32_t)a.tlast[(int64_t)gcur * a.K_cap + k1];
+  };
+  auto put = [&](int slot, int dslot, uint64_t g64, uint32_t g32) {
+    const int l = threadIdx.x & 63;
+    if (l < 37) sMeta[slot][l] = g64;
+    else if (l < 39) ((uint64_t *)&sDesc[dslot])[l - 37] = g64;
+    else if (l < 41) ((uint32_t *)&sMeta[slot][37])[l - 39] = g32;
+  };
   // the fast kernel takes the items blk, blk + nblk, ... (heaviest first, so
-  // the static stride balances like a greedy list schedule) and reads each
-  // next item while the current one is processed
-  if (!SLOW && threadIdx.x == 0) {
-    sNext[0] = blk;
-    if (blk < n_items) {
-      const Item x = a.items[blk];
-      sNext[1] = x.slice;
-      sNext[2] = x.g0;
-      sNext[3] = x.g1;
-      sNext[4] = x.rows;
+  // the static stride balances like a greedy list schedule)
+  if constexpr (!SLOW) {
+    if (threadIdx.x == 0 && blk < n_items) sDesc[0] = a.items[blk];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      uint64_t g64;
+      uint32_t g32;
+      gather(blk, sDesc[0], blk + nblk, g64, g32);
+      put(0, 1, g64, g32);
     }
   }
-  for (;;) {
-    __syncthreads();   // the previous slice is done with LDS and sItem
-    if (threadIdx.x == 0) {
-      if (SLOW) {
+  for (int cnt = 0;; ++cnt) {
+    __syncthreads();   // the previous slice is done with LDS; the look-ahead is stored
+    if constexpr (SLOW) {
+      if (threadIdx.x == 0) {
         const int q = atomicAdd(&a.queue[2], 1);
         sItem = (q < __atomic_load_n(&a.queue[1], __ATOMIC_RELAXED)) ? a.slow_list[q] : n_items;
         if (sItem < n_items) {
@@ -280,12 +326,10 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
           sNext[3] = x.g1;
           sNext[4] = x.rows;
         }
-      } else {
-        sItem = sNext[0];
       }
+      __syncthreads();
     }
-    __syncthreads();
-    const int it = sItem;
+    const int it = SLOW ? sItem : blk + cnt * nblk;
     if (it >= n_items) break;
     // the thread index, opaque to the compiler inside the loop: per-thread
     // address arithmetic is redone per slice instead of being hoisted out of
@@ -294,18 +338,26 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     Item item;
-    item.slice = sNext[1];
-    item.g0 = sNext[2];
-    item.g1 = sNext[3];
-    item.rows = sNext[4];
+    const int ms = cnt & 1;   // this item's slot of sMeta
+    if constexpr (SLOW) {
+      item.slice = sNext[1];
+      item.g0 = sNext[2];
+      item.g1 = sNext[3];
+      item.rows = sNext[4];
+    } else {
+      item = sDesc[cnt % 3];
+    }
     const int k = item.slice;
-    // the next item's descriptor, in flight during this slice (thread 0)
-    Item nx{0, 0, 0, 0};
-    const int it_next = it + nblk;
-    if (!SLOW && tid == 0 && it_next < n_items) nx = a.items[it_next];
+    // the next item's state words and the descriptor after it, in flight
+    // during this slice (wave 0)
+    uint64_t g64 = 0;
+    uint32_t g32 = 0;
+    if (!SLOW && wv == 0) gather(it + nblk, sDesc[(cnt + 1) % 3], it + 2 * nblk, g64, g32);
     const bool is_new = k >= Kp;
-    const int b = a.cur[(int64_t)gcur * a.K_cap + k];
-    const int tl = a.tlast[(int64_t)gcur * a.K_cap + k];
+    const uint32_t btl0 = SLOW ? 0u : ((const uint32_t *)&sMeta[ms][37])[0];
+    const uint32_t btl1 = SLOW ? 0u : ((const uint32_t *)&sMeta[ms][37])[1];
+    const int b = SLOW ? (int)a.cur[(int64_t)gcur * a.K_cap + k] : (int)btl0;
+    const int tl = SLOW ? a.tlast[(int64_t)gcur * a.K_cap + k] : (int)btl1;
     const int64_t ybase = ((int64_t)b * a.K_cap + k) * a.ys;
     const int64_t ynext = ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
     const int64_t dbase = ((int64_t)b * a.K_cap + k) * RR;
@@ -315,29 +367,51 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     float yo[RW][JW];
     float yl[MX ? RW : 1][MX ? JW : 1];
     float dold[4], dlo[4];
+    // (a new slice's buffers have no bytes: every load returns zero)
     auto load_state = [&]() {
+      const int yb = is_new ? 0 : R * J * 4, db = is_new ? 0 : RR * 4;
+      const auto ry = buf_rsrc(a.Y + ybase, yb);
+      const auto rd = buf_rsrc(a.D + dbase, db);
 #pragma unroll
       for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
         for (int jj = 0; jj < JW; ++jj) {
           const int r = wv + 4 * rr, j = lane + 64 * jj;
-          const bool in = !is_new && r < R && j < J;
-          yo[rr][jj] = in ? a.Y[ybase + r * J + j] : 0.f;
-          if constexpr (MX) yl[rr][jj] = in ? a.Yc[ybase + r * J + j] : 0.f;
+          yo[rr][jj] = buf_ldf(ry, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
         }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int q = tid + 256 * i;
-        const bool in = !is_new && q < RR;
-        dold[i] = in ? a.D[dbase + q] : 0.f;
-        dlo[i] = (MX && in) ? a.Dc[dbase + q] : 0.f;
+        dold[i] = buf_ldf(rd, q < RR ? q * 4 : kNoOff);
+      }
+      if constexpr (MX) {
+        const auto ryc = buf_rsrc(a.Yc + ybase, yb);
+        const auto rdc = buf_rsrc(a.Dc + dbase, db);
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+          for (int jj = 0; jj < JW; ++jj) {
+            const int r = wv + 4 * rr, j = lane + 64 * jj;
+            yl[rr][jj] = buf_ldf(ryc, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+          }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int q = tid + 256 * i;
+          dlo[i] = buf_ldf(rdc, q < RR ? q * 4 : kNoOff);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dlo[i] = 0.f;
       }
     };
     if (wv == 0) {
       // the weights Lemma 1 uses (1 for a new slice's first pass) and the
       // acceptance rule of its system S_k V^T V S_k
-      const double w = (lane < R) ? ((is_new && a.pass == 0) ? 1.0 : a.W[((int64_t)win * a.K_cap + k) * R + lane])
-                                  : 0.0;
+      const double w =
+          (lane < R) ? ((is_new && a.pass == 0) ? 1.0
+                        : SLOW ? a.W[((int64_t)win * a.K_cap + k) * R + lane]
+                               : __longlong_as_double((long long)sMeta[ms][lane]))
+                     : 0.0;
       const bool regular = SLOW || lemma1_regular(w, pivl, arrl, R);
       if (lane < R) {
         sW[lane] = w;
@@ -350,13 +424,7 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     }
     __syncthreads();
     if (!SLOW && sDefer) {
-      if (tid == 0) {
-        sNext[0] = it_next;
-        sNext[1] = nx.slice;
-        sNext[2] = nx.g0;
-        sNext[3] = nx.g1;
-        sNext[4] = nx.rows;
-      }
+      if (wv == 0) put((cnt + 1) & 1, (cnt + 2) % 3, g64, g32);
       continue;
     }
     if constexpr (!MX) load_state();
@@ -378,7 +446,15 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     double dn = 0.0;
     const int NTu = (R + 15) >> 4;
     for (int gi = item.g0; gi < item.g1; ++gi) {
-      const Group gr = a.groups[gi];
+      Group gr;
+      if (!SLOW && gi == item.g0) {
+        gr.src = (const float *)(uintptr_t)sMeta[ms][34];
+        gr.out_row = (int64_t)sMeta[ms][35];
+        gr.nrows = (int32_t)(uint32_t)sMeta[ms][36];
+        gr.slice = k;
+      } else {
+        gr = a.groups[gi];
+      }
       for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
         const int m = min(MB, gr.nrows - r0);
         const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
@@ -400,12 +476,14 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
               for (int ks = 0; ks < LB.Jp; ks += 32)
                 acc = mfma_bf16(*(const bf16x8 *)(pa + ks), *(const bf16x8 *)(pb + ks), acc);
               const int row = 16 * rt + (lane & 15);
+              const auto ru = buf_rsrc(a.U_out + (gr.out_row + r0) * R, write_u ? m * R * 4 : 0);
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int r = 16 * nt + (lane >> 4) * 4 + q;
-                const float u = (r < R && row < m) ? acc[q] * sWinv[min(r, R - 1)] : 0.f;
+                const bool in = r < R && row < m;
+                const float u = in ? acc[q] * sWinv[min(r, R - 1)] : 0.f;
                 bUt[r * LB.XC + row] = (__bf16)u;
-                if (write_u && r < R && row < m) a.U_out[(gr.out_row + r0 + row) * R + r] = u;
+                buf_stf(ru, in ? (row * R + r) * 4 : kNoOff, u);
               }
             }
           }
@@ -436,32 +514,36 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
         }
         __syncthreads();
         dn += stage_rows<true>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
-        for (int e = tid; e < (mp - m) * J; e += 256) {
-          const int row = e / J;
-          sX[(m + row) * XS + (e - row * J)] = 0.f;
-        }
+        zero_block_pad(sX, XS, m, mp, J, L.J16, tid);
         __syncthreads();
-        // t = x P per (row tile, rank tile): wave w takes jobs w and w + 4
+        // t = x P per (row tile, rank tile): wave w takes jobs w and w + 4;
+        // U's columns R .. 16 NTu - 1 come out zero
         const int jobs = (mp >> 4) * NTu;
+        const auto ru = buf_rsrc(a.U_out + (gr.out_row + r0) * R, (write_u && !slow) ? m * R * 4 : 0);
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb) {
           const int job = wv + 4 * jb;
           if (job < jobs) {
             const int rt = job / NTu, nt = job - rt * NTu;
-            const f32x4 acc = rows_times_p<MX>(sX + (16 * rt + (lane & 15)) * XS, sP, J, R, nt, lane);
+            const float *xr = sX + (16 * rt + (lane & 15)) * XS;
+            const float *pr = sP + (16 * nt + (lane & 15)) * XS;
+            f32x4 acc;
+            if constexpr (MX)
+              acc = rows_times_pt_bf(xr, pr, J, lane);
+            else
+              acc = rows_times_pt(xr, pr, L.J16, lane >> 4);
             const int n = nt * 16 + (lane & 15);
-            if (n < R) {
-              const float wi = sWinv[n];
+            const float wi = sWinv[min(n, R - 1)];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int rr = 16 * rt + (lane >> 4) * 4 + q;
-                if (slow) {
-                  sU[rr * (R + 1) + n] = (rr < m) ? acc[q] : 0.f;
-                } else {
-                  const float u = (rr < m) ? acc[q] * wi : 0.f;
-                  sU[rr * (R + 1) + n] = u;
-                  if (write_u && rr < m) a.U_out[(gr.out_row + r0 + rr) * R + n] = u;
-                }
+            for (int q = 0; q < 4; ++q) {
+              const int rr = 16 * rt + (lane >> 4) * 4 + q;
+              const bool in = rr < m && n < R;
+              if (slow) {
+                sU[rr * L.US + n] = in ? acc[q] : 0.f;
+              } else {
+                const float u = in ? acc[q] * wi : 0.f;
+                sU[rr * L.US + n] = u;
+                buf_stf(ru, in ? (rr * R + n) * 4 : kNoOff, u);
               }
             }
           }
@@ -477,7 +559,7 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
             if (e < mp * R) {
               const int row = e / R, n = e - row * R;
               float acc = 0.f;
-              for (int mm = 0; mm < R; ++mm) acc = fmaf(sU[row * (R + 1) + mm], sZf[mm * R + n], acc);
+              for (int mm = 0; mm < R; ++mm) acc = fmaf(sU[row * L.US + mm], sZf[mm * R + n], acc);
               uq[i] = (row < m) ? acc : 0.f;
             }
           }
@@ -487,16 +569,16 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
             const int e = tid + 256 * i;
             if (e < mp * R) {
               const int row = e / R, n = e - row * R;
-              sU[row * (R + 1) + n] = uq[i];
+              sU[row * L.US + n] = uq[i];
               if (write_u && row < m) a.U_out[(gr.out_row + r0 + row) * R + n] = uq[i];
             }
           }
         }
         __syncthreads();
         if constexpr (MX)
-          accum_block_mx(sX, sU, XS, mp, J, R, accY, accD, tid);
+          accum_block_mx(sX, sU, XS, L.US, mp, J, R, accY, accD, tid);
         else
-          accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
+          accum_block_f32(sX, sU, XS, L.US, mp, J, R, accY, accD, tid);
       }
     }
     if constexpr (MX) load_state();
@@ -537,31 +619,40 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     const double s_old = is_new ? 0.0 : exp2((double)(step - tl) * a.log2_lambda);
     const float s_old_f = (float)s_old;
     double cpart[RW];
+    {
+      const auto wy = buf_rsrc(a.Y + ynext, R * J * 4);
+      const auto wyc = buf_rsrc(MX ? a.Yc + ynext : a.Y, MX ? R * J * 4 : 0);
+      const bool lag = a.lagged;
 #pragma unroll
-    for (int rr = 0; rr < RW; ++rr) {
-      const int r = wv + 4 * rr;
-      cpart[rr] = 0.0;
+      for (int rr = 0; rr < RW; ++rr) {
+        const int r = wv + 4 * rr;
+        cpart[rr] = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
-        const int j = lane + 64 * jj;
-        const bool in = r < R && j < J;
-        const float dy = in ? sDY[r * J + j] : 0.f;
-        double cv;
-        if constexpr (MX) {
-          // compensated running sum: (hi, lo) folded in FP64 and split again
-          const double v = s_old * ((double)yo[rr][jj] + (double)yl[rr][jj]) + (double)dy;
-          const float hi = (float)v;
-          if (in) {
-            a.Y[ynext + r * J + j] = hi;
-            a.Yc[ynext + r * J + j] = (float)(v - (double)hi);
+        for (int jj = 0; jj < JW; ++jj) {
+          const int j = lane + 64 * jj;
+          const bool in = r < R && j < J;
+          const float dyl = sDY[min(r, R - 1) * J + min(j, J - 1)];
+          const float dy = in ? dyl : 0.f;
+          const int off = in ? (r * J + j) * 4 : kNoOff;
+          double cv;
+          if constexpr (MX) {
+            // compensated running sum: (hi, lo) folded in FP64 and split again
+            const double v = s_old * ((double)yo[rr][jj] + (double)yl[rr][jj]) + (double)dy;
+            const float hi = (float)v;
+            buf_stf(wy, off, hi);
+            buf_stf(wyc, off, (float)(v - (double)hi));
+            cv = lag ? (double)dy : v;
+          } else {
+            const float yv = fmaf(s_old_f, yo[rr][jj], dy);
+            buf_stf(wy, off, yv);
+            cv = lag ? (double)dy : (double)yv;
           }
-          cv = a.lagged ? (double)dy : v;
-        } else {
-          const float yv = fmaf(s_old_f, yo[rr][jj], dy);
-          if (in) a.Y[ynext + r * J + j] = yv;
-          cv = a.lagged ? (double)dy : (double)yv;
+          // V^T's entry converted here, not hoisted out of the slice loop
+          // as 32 more double registers
+          float vtc = vt[rr][jj];
+          asm volatile("" : "+v"(vtc));
+          cpart[rr] = fma(cv, (double)vtc, cpart[rr]);
         }
-        cpart[rr] = fma(cv, (double)vt[rr][jj], cpart[rr]);
       }
     }
     // c_r: each wave sums its ranks' partials across lanes through LDS (the
@@ -597,33 +688,32 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
         }
       }
     }
+    {
+      const auto wd = buf_rsrc(a.D + dnext, RR * 4);
+      const auto wdc = buf_rsrc(MX ? a.Dc + dnext : a.D, MX ? RR * 4 : 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = tid + 256 * i;
-      if (q < RR) {
-        const float dd = sDD[q];
+      for (int i = 0; i < 4; ++i) {
+        const int q = tid + 256 * i;
+        const float dd = sDD[min(q, RR - 1)];
+        const int off = q < RR ? q * 4 : kNoOff;
         if constexpr (MX) {
           const double v = s_old * ((double)dold[i] + (double)dlo[i]) + (double)dd;
           const float hi = (float)v;
-          a.D[dnext + q] = hi;
-          a.Dc[dnext + q] = (float)(v - (double)hi);
+          buf_stf(wd, off, hi);
+          buf_stf(wdc, off, (float)(v - (double)hi));
         } else {
-          a.D[dnext + q] = fmaf(s_old_f, dold[i], dd);
+          buf_stf(wd, off, fmaf(s_old_f, dold[i], dd));
         }
       }
     }
     if (tid == 0) {
-      const double nold = is_new ? 0.0 : a.n[(int64_t)b * a.K_cap + k];
+      const double nold = is_new ? 0.0
+                          : SLOW ? a.n[(int64_t)b * a.K_cap + k]
+                                 : __longlong_as_double((long long)sMeta[ms][32 + b]);
       a.n[(int64_t)(1 - b) * a.K_cap + k] = s_old * nold + (((sDn[0] + sDn[1]) + sDn[2]) + sDn[3]);
       a.tag[k] = seq;
-      if (!SLOW) {
-        sNext[0] = it_next;
-        sNext[1] = nx.slice;
-        sNext[2] = nx.g0;
-        sNext[3] = nx.g1;
-        sNext[4] = nx.rows;
-      }
     }
+    if (!SLOW && wv == 0) put((cnt + 1) & 1, (cnt + 2) % 3, g64, g32);
   }
 }
 
@@ -1256,19 +1346,18 @@ __global__ __launch_bounds__(256) void k_fsum_rows(const PassArgs *args, const B
         const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
         __syncthreads();
         (void)stage_rows<false>(gr.src + (int64_t)r0 * J, m, J, XS, sX, tid);
-        for (int e = tid; e < (mp - m) * J; e += 256) {
-          const int row = e / J;
-          sX[(m + row) * XS + (e - row * J)] = 0.f;
-        }
-        for (int e = tid; e < mp * R; e += 256) {
-          const int row = e / R, n = e - row * R;
-          sU[row * (R + 1) + n] = (row < m) ? (float)(a.U_out[(gr.out_row + r0 + row) * R + n] * sW[n]) : 0.f;
+        zero_block_pad(sX, XS, m, mp, J, L.J16, tid);
+        const int R16 = (R + 15) & ~15;
+        for (int e = tid; e < mp * R16; e += 256) {
+          const int row = e / R16, n = e - row * R16;
+          sU[row * L.US + n] =
+              (row < m && n < R) ? (float)(a.U_out[(gr.out_row + r0 + row) * R + n] * sW[n]) : 0.f;
         }
         __syncthreads();
         if constexpr (MX)
-          accum_block_mx(sX, sU, XS, mp, J, R, accY, accD, tid);
+          accum_block_mx(sX, sU, XS, L.US, mp, J, R, accY, accD, tid);
         else
-          accum_block_f32(sX, sU, XS, mp, J, R, accY, accD, tid);
+          accum_block_f32(sX, sU, XS, L.US, mp, J, R, accY, accD, tid);
       }
     }
     // the slice's tiles into the FP64 sums through LDS

@@ -26,6 +26,39 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Raw buffer access through a bounds-checked descriptor: a load at a byte
+// offset outside [0, bytes) returns zero and a store there is dropped, so
+// ragged tiles and empty slices need no branches around their memory
+// operations.  kNoOff lies outside every buffer.
+constexpr int kNoOff = (int)0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, int off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void buf_stf(__amdgpu_buffer_rsrc_t r, int off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+
+// Zero rows m .. mp - 1 (all J16 columns) and columns J .. J16 - 1 of rows
+// 0 .. m - 1 of a staged row block (stride XS).
+__device__ __forceinline__ void zero_block_pad(float *sX, int XS, int m, int mp, int J, int J16, int tid) {
+  for (int e = tid; e < (mp - m) * J16; e += 256) {
+    const int row = e / J16;
+    sX[(m + row) * XS + (e - row * J16)] = 0.f;
+  }
+  const int pc = J16 - J;
+  if (pc > 0)
+    for (int e = tid; e < m * pc; e += 256) {
+      const int row = e / pc;
+      sX[row * XS + J + (e - row * pc)] = 0.f;
+    }
+}
+
 
 // Mixed precision (BF16 MFMA) row products of the block variant.
 // v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][8 (l / 16) + i] and
@@ -36,73 +69,92 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4 &c) {
 // w, w+4, w+8, w+12 (16 columns each) for both rank tiles (accY[2 c + mt]), and
 // the dD tile w of the (R / 16)^2 rank-tile pairs
 constexpr int kMxTiles = 8;
-// One 16 x 16 tile of X P: rows xrow (lane's row of the 16-row tile, stride
-// XS in LDS, zero rows beyond the block), columns 16 nt .. 16 nt + 15 of P
-// (J x R, LDS); columns >= R come out as garbage and are dropped by the
-// caller.  v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16]; BF16 (16x16x32): A[l % 16][8 (l / 16) + i], i < 8.
-template <bool MX>
-__device__ __forceinline__ f32x4 rows_times_p(const float *xrow, const float *sP, int J, int R, int nt,
-                                               int lane) {
-  const int n = min(nt * 16 + (lane & 15), R - 1);
+// One 16 x 16 tile of X P in FP32 with P held transposed: xrow is the lane's
+// row of the 16-row tile and prow the lane's rank of the 16-rank tile, both
+// with J16 (J rounded up to 16) entries, zero beyond J, 16-byte aligned.  The
+// sum over j is split so that lane quad q takes columns 16 s + 4 q .. + 3 of
+// each 16-column step s (four MFMAs, one float4 of each operand), so every
+// operand comes from one vector LDS read.
+__device__ __forceinline__ f32x4 rows_times_pt(const float *xrow, const float *prow, int J16, int lq) {
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  if constexpr (MX) {
-    const int lk = (lane >> 4) * 8;
-    for (int ks = 0; ks < J; ks += 32) {
-      bf16x8 av, bv;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int kk = ks + lk + q;
-        av[q] = (__bf16)((kk < J) ? xrow[kk] : 0.f);
-        bv[q] = (__bf16)((kk < J) ? sP[kk * R + n] : 0.f);
-      }
-      acc0 = mfma_bf16(av, bv, acc0);
-    }
-  } else {
-    const int lq = lane >> 4;
-    int ks = 0;
-    // two independent chains; the tail (J % 8) goes to the first
-    for (; ks + 8 <= J; ks += 8) {
-      const float a0 = xrow[ks + lq], a1 = xrow[ks + 4 + lq];
-      const float b0 = sP[(ks + lq) * R + n], b1 = sP[(ks + 4 + lq) * R + n];
-      acc0 = mfma_f32(a0, b0, acc0);
-      acc1 = mfma_f32(a1, b1, acc1);
-    }
-    for (; ks < J; ks += 4) {
-      const int kk = ks + lq;
-      const float a0 = (kk < J) ? xrow[kk] : 0.f;
-      const float b0 = (kk < J) ? sP[kk * R + n] : 0.f;
-      acc0 = mfma_f32(a0, b0, acc0);
-    }
+  const float4 *xa = reinterpret_cast<const float4 *>(xrow) + lq;
+  const float4 *pb = reinterpret_cast<const float4 *>(prow) + lq;
+  const int n4 = J16 >> 2;
+  // the next step's operands are read while this step's MFMAs run
+  float4 a = xa[0], b = pb[0];
+  for (int q = 4; q < n4; q += 4) {
+    const float4 an = xa[q], bn = pb[q];
+    acc0 = mfma_f32(a.x, b.x, acc0);
+    acc1 = mfma_f32(a.y, b.y, acc1);
+    acc0 = mfma_f32(a.z, b.z, acc0);
+    acc1 = mfma_f32(a.w, b.w, acc1);
+    a = an;
+    b = bn;
   }
+  acc0 = mfma_f32(a.x, b.x, acc0);
+  acc1 = mfma_f32(a.y, b.y, acc1);
+  acc0 = mfma_f32(a.z, b.z, acc0);
+  acc1 = mfma_f32(a.w, b.w, acc1);
   return acc0 + acc1;
 }
 
-// dY += U^T X, dD += U^T U in FP32 on MFMA (16x16x4) for one staged block
-// (rows >= m are zero in sX and sU; mp = m rounded up to 16).  Same tile
-// ownership as the BF16 version below.
-__device__ __forceinline__ void accum_block_f32(const float *sX, const float *sU, int XS, int mp, int J,
+// The same tile with BF16-rounded operands (16x16x32 MFMA, FP32 sums).
+__device__ __forceinline__ f32x4 rows_times_pt_bf(const float *xrow, const float *prow, int J, int lane) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int lk = (lane >> 4) * 8;
+  for (int ks = 0; ks < J; ks += 32) {
+    bf16x8 av, bv;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kk = ks + lk + q;
+      av[q] = (__bf16)((kk < J) ? xrow[kk] : 0.f);
+      bv[q] = (__bf16)((kk < J) ? prow[kk] : 0.f);
+    }
+    acc = mfma_bf16(av, bv, acc);
+  }
+  return acc;
+}
+
+// dY += U^T X, dD += U^T U in FP32 on MFMA (16x16x4) for one staged block:
+// sX rows of stride XS and sU rows of stride US, rows m .. mp - 1 zero in
+// both (mp = m rounded up to 16), sX columns J .. J16 - 1 and sU columns
+// R .. 16 MT - 1 zero.  Lane quad q takes rows 4 q .. 4 q + 3 of each 16-row
+// step, four MFMAs per tile and step; a step's LDS reads all go out before
+// its MFMAs.  Wave w owns the column tiles w, w + 4, w + 8, w + 12 of both
+// rank tiles and the rank-tile pair w of dD.
+__device__ __forceinline__ void accum_block_f32(const float *sX, const float *sU, int XS, int US, int mp, int J,
                                                 int R, f32x4 (&accY)[kMxTiles], f32x4 &accD, int tid) {
   const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
   const int li = lane & 15, lq = lane >> 4;
-  const int r0c = min(li, R - 1), r1c = min(16 + li, R - 1);
-  for (int ks = 0; ks < mp; ks += 4) {
-    const float *urow = sU + (ks + lq) * (R + 1);
-    const float au0 = urow[r0c], au1 = urow[r1c];
-    const float *xrow = sX + (ks + lq) * XS;
+  const bool dtile = wv < MT * MT;
+  const int mt = dtile ? wv / MT : 0, st = dtile ? wv - mt * MT : 0;
+#pragma unroll 1
+  for (int ks = 0; ks < mp; ks += 16) {
+    const float *urow = sU + (ks + 4 * lq) * US + li;
+    const float *xrow = sX + (ks + 4 * lq) * XS + li;
+    float au0[4], au1[4], bx[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      au0[i] = urow[i * US];
+      au1[i] = (MT > 1) ? urow[i * US + 16] : 0.f;
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int nt = wv + 4 * c;
-      if (nt < NT) {
-        const float bx = xrow[min(nt * 16 + li, J - 1)];
-        accY[2 * c] = mfma_f32(au0, bx, accY[2 * c]);
-        if (MT > 1) accY[2 * c + 1] = mfma_f32(au1, bx, accY[2 * c + 1]);
-      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bx[c][i] = (nt < NT) ? xrow[i * XS + 16 * nt] : 0.f;
     }
-    if (wv < MT * MT) {
-      const int mt = wv / MT, st = wv - mt * MT;
-      accD = mfma_f32(mt == 0 ? au0 : au1, st == 0 ? au0 : au1, accD);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (wv + 4 * c < NT) {
+          accY[2 * c] = mfma_f32(au0[i], bx[c][i], accY[2 * c]);
+          if (MT > 1) accY[2 * c + 1] = mfma_f32(au1[i], bx[c][i], accY[2 * c + 1]);
+        }
+      }
+      if (dtile) accD = mfma_f32(mt == 0 ? au0[i] : au1[i], st == 0 ? au0[i] : au1[i], accD);
     }
   }
 }
@@ -111,7 +163,7 @@ __device__ __forceinline__ void accum_block_f32(const float *sX, const float *sU
 // in both sX and sU; mp = m rounded up to 32).  The U^T operand of a rank
 // tile is loaded once per 32-row step and serves every column tile, and, as
 // the B operand of dD, the rank-tile pairs too.
-__device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU, int XS, int mp, int J,
+__device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU, int XS, int US, int mp, int J,
                                                int R, f32x4 (&accY)[kMxTiles], f32x4 &accD, int tid) {
   const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int MT = (R + 15) >> 4, NT = (J + 15) >> 4;
@@ -122,7 +174,7 @@ __device__ __forceinline__ void accum_block_mx(const float *sX, const float *sU,
     for (int mt = 0; mt < 2; ++mt) {
       const int r = mt * 16 + li;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) au[mt][q] = (__bf16)((r < R) ? sU[(ks + lk + q) * (R + 1) + r] : 0.f);
+      for (int q = 0; q < 8; ++q) au[mt][q] = (__bf16)((r < R) ? sU[(ks + lk + q) * US + r] : 0.f);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
