@@ -266,7 +266,6 @@ int launch_reduce_groups(const PassArgs *args, const BlockMap *map, int n_blocks
 // workgroup running the instantiation of its own context's R (and J).  lds:
 // the largest dynamic LDS among the members.
 int launch_split_solve_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds);
-int launch_split_fsum_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds);
 int launch_finish_dev_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds);
 size_t split_rows_lds(int J, int R, int mixed);
 size_t split_solve_lds(int J, int R);

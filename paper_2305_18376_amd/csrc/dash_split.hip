@@ -347,7 +347,9 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     } else {
       item = sDesc[cnt % 3];
     }
-    const int k = item.slice;
+    const int k = uni(item.slice);
+    item.g0 = uni(item.g0);
+    item.g1 = uni(item.g1);
     // the next item's state words and the descriptor after it, in flight
     // during this slice (wave 0)
     uint64_t g64 = 0;
@@ -356,8 +358,8 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     const bool is_new = k >= Kp;
     const uint32_t btl0 = SLOW ? 0u : ((const uint32_t *)&sMeta[ms][37])[0];
     const uint32_t btl1 = SLOW ? 0u : ((const uint32_t *)&sMeta[ms][37])[1];
-    const int b = SLOW ? (int)a.cur[(int64_t)gcur * a.K_cap + k] : (int)btl0;
-    const int tl = SLOW ? a.tlast[(int64_t)gcur * a.K_cap + k] : (int)btl1;
+    const int b = uni(SLOW ? (int)a.cur[(int64_t)gcur * a.K_cap + k] : (int)btl0);
+    const int tl = uni(SLOW ? a.tlast[(int64_t)gcur * a.K_cap + k] : (int)btl1);
     const int64_t ybase = ((int64_t)b * a.K_cap + k) * a.ys;
     const int64_t ynext = ((int64_t)(1 - b) * a.K_cap + k) * a.ys;
     const int64_t dbase = ((int64_t)b * a.K_cap + k) * RR;
@@ -455,6 +457,9 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       } else {
         gr = a.groups[gi];
       }
+      gr.src = uniptr(gr.src);
+      gr.out_row = uni64(gr.out_row);
+      gr.nrows = uni(gr.nrows);
       for (int r0 = 0; r0 < gr.nrows; r0 += MB) {
         const int m = min(MB, gr.nrows - r0);
         const int mp = MX ? (m + 31) & ~31 : (m + 15) & ~15;
@@ -1123,7 +1128,11 @@ __host__ __device__ inline int fsum_tps(int ys) {
   return tps;
 }
 
-template <int EPT>
+// WHOLE: J is a multiple of 4, so each float4 of a slice lies in one row of
+// Y_k (one weight); otherwise every float's row is found where it is used
+// (a separate kernel, so that this code does not weigh on the common one's
+// registers).
+template <int EPT, bool WHOLE>
 __device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
   CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
@@ -1146,17 +1155,10 @@ __device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *
   double *sw = (double *)smem;   // [kFsumBatch][R]: sigma_k w_k
   const int spi = kFsumThreads / tps, sg = tid / tps, tq = tid - sg * tps;
   const int nq = a.ys >> 2;
-  // the rows of this thread's floats: float4 e starts in row r0[e]; its
-  // floats from index brk[e] on lie in the next row (J >= 4; with J < 4 the
-  // row of every float is computed where it is used)
-  int r0[EPT], brk[EPT];
+  // the row of this thread's float4 e (WHOLE)
+  int r0[EPT];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int el = 4 * (tq + tps * e);
-    r0[e] = el / J;
-    brk[e] = (r0[e] + 1) * J - el;
-  }
-  const bool narrow = J < 4;
+  for (int e = 0; e < EPT; ++e) r0[e] = min(4 * (tq + tps * e) / max(J, 1), R - 1);
   double acc[EPT][4];
 #pragma unroll
   for (int e = 0; e < EPT; ++e)
@@ -1166,56 +1168,89 @@ __device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *
   for (int kb = k0; kb < k1; kb += kFsumBatch) {
     const int nb = min(kFsumBatch, k1 - kb);
     __syncthreads();
-    for (int e = tid; e < nb * R; e += kFsumThreads) {
-      const int i = e / R, r = e - i * R, k = kb + i;
-      const int tl = a.tlast[(int64_t)bsel * a.K_cap + k];
-      const double sig = exp2((double)(step - tl) * a.log2_lambda);
-      sw[e] = sig * a.W[((int64_t)wsel * a.K_cap + k) * R + r];
+    // sigma_k w_k of the batch's slices and their buffers: a thread's loads
+    // (four entries at a time) all go out before their first use
+    for (int e0 = tid; e0 < nb * R; e0 += 4 * kFsumThreads) {
+      int tl[4];
+      double wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * kFsumThreads, nb * R - 1);
+        const int i = e / R, r = e - i * R, k = kb + i;
+        tl[u] = a.tlast[(int64_t)bsel * a.K_cap + k];
+        wv[u] = a.W[((int64_t)wsel * a.K_cap + k) * R + r];
+      }
+      const int ib = min(e0, nb - 1);
+      const int cb = a.cur[(int64_t)bsel * a.K_cap + kb + ib];
+      if (e0 < nb) sb[e0] = cb;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kFsumThreads;
+        if (e < nb * R) sw[e] = exp2((double)(step - tl[u]) * a.log2_lambda) * wv[u];
+      }
     }
-    for (int i = tid; i < nb; i += kFsumThreads) sb[i] = a.cur[(int64_t)bsel * a.K_cap + kb + i];
     __syncthreads();
-    // two slices per thread group in flight where the registers allow it
+    // Two slices per thread group per step where the registers allow it,
+    // and the next step's slices loaded while this step's are summed.  A
+    // slice's Y comes through a bounds-checked buffer of its a.ys floats: the
+    // lanes beyond it, and a missing second slice, read zeros.
     constexpr int NS = EPT <= 2 ? 2 : 1;
+    struct V4 {
+      float4 v[EPT];
+    };
+    // (a thread group may be narrower than a wave, so the slice address is
+    // per lane: plain loads from clamped addresses; what a lane loads beyond
+    // its slice, or for a slice past the batch, is never summed)
+    auto load = [&](int i) {
+      V4 o;
+      const int ic = min(i, nb - 1);
+      const float4 *y = (const float4 *)(a.Y + ((int64_t)sb[ic] * a.K_cap + kb + ic) * a.ys);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) o.v[e] = y[min(tq + tps * e, nq - 1)];
+      return o;
+    };
+    V4 c1 = load(sg), c2;
+    if constexpr (NS == 2) c2 = load(sg + spi);
 #pragma unroll 1
     for (int i = sg; i < nb; i += NS * spi) {
       const int i2 = i + spi;
       const bool two = NS == 2 && i2 < nb;
-      const float4 *y1 = (const float4 *)(a.Y + ((int64_t)sb[i] * a.K_cap + kb + i) * a.ys);
-      const float4 *y2 = two ? (const float4 *)(a.Y + ((int64_t)sb[i2] * a.K_cap + kb + i2) * a.ys) : y1;
-      float4 v1[EPT], v2[EPT];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int q = tq + tps * e;
-        v1[e] = (q < nq) ? y1[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        v2[e] = (q < nq && two) ? y2[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      const V4 x1 = c1;
+      V4 x2;
+      if constexpr (NS == 2) x2 = c2;
+      // the next step's slices (unconditionally: past the batch the clamped
+      // load repeats its last slice, which is not summed again)
+      c1 = load(i + NS * spi);
+      if constexpr (NS == 2) c2 = load(i + NS * spi + spi);
       const double *w1 = sw + i * R, *w2 = sw + (two ? i2 : i) * R;
+      // weights of entries outside the slice, or of a missing second
+      // slice, are zero: every lane runs the same FMAs
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const float a1[4] = {v1[e].x, v1[e].y, v1[e].z, v1[e].w};
-        const float a2[4] = {v2[e].x, v2[e].y, v2[e].z, v2[e].w};
         const int el = 4 * (tq + tps * e);
-        if (el >= RJ) continue;
-        if (!narrow) {
-          // the float4's two possible rows: r0 (and r0 + 1 from brk on)
-          const int ra = r0[e], rb = min(ra + 1, R - 1);
-          const double wa1 = w1[ra], wb1 = w1[rb];
+        const float a1[4] = {x1.v[e].x, x1.v[e].y, x1.v[e].z, x1.v[e].w};
+        if constexpr (WHOLE) {
+          const bool in = el < RJ;
+          const double wa1 = w1[r0[e]];
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            if (el + c < RJ) acc[e][c] = fma(c >= brk[e] ? wb1 : wa1, (double)a1[c], acc[e][c]);
-          if (two) {
-            const double wa2 = w2[ra], wb2 = w2[rb];
+          for (int c = 0; c < 4; ++c) acc[e][c] = fma(in ? wa1 : 0.0, (double)a1[c], acc[e][c]);
+          if constexpr (NS == 2) {
+            const float a2[4] = {x2.v[e].x, x2.v[e].y, x2.v[e].z, x2.v[e].w};
+            const double wa2 = w2[r0[e]];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-              if (el + c < RJ) acc[e][c] = fma(c >= brk[e] ? wb2 : wa2, (double)a2[c], acc[e][c]);
+            for (int c = 0; c < 4; ++c) acc[e][c] = fma((in && two) ? wa2 : 0.0, (double)a2[c], acc[e][c]);
           }
         } else {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            if (el + c < RJ) {
-              const int r = (el + c) / J;
-              acc[e][c] = fma(w1[r], (double)a1[c], acc[e][c]);
-              if (two) acc[e][c] = fma(w2[r], (double)a2[c], acc[e][c]);
+            const bool in = el + c < RJ;
+            const int r = min((el + c) / J, R - 1);
+            const double wr1 = w1[r];
+            acc[e][c] = fma(in ? wr1 : 0.0, (double)a1[c], acc[e][c]);
+            if constexpr (NS == 2) {
+              const float a2c = c == 0 ? x2.v[e].x : c == 1 ? x2.v[e].y : c == 2 ? x2.v[e].z : x2.v[e].w;
+              const double wr2 = w2[r];
+              acc[e][c] = fma((in && two) ? wr2 : 0.0, (double)a2c, acc[e][c]);
             }
           }
         }
@@ -1258,7 +1293,12 @@ __device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *
 
 template <int EPT>
 __global__ __launch_bounds__(kFsumThreads, 4) void k_fsum(const PassArgs *args, const BlockMap *map) {
-  fsum_body<EPT>(args, map);
+  fsum_body<EPT, true>(args, map);
+}
+
+// J not a multiple of 4 (any slice size up to 4 float4 per thread)
+__global__ __launch_bounds__(kFsumThreads, 4) void k_fsum_odd(const PassArgs *args, const BlockMap *map) {
+  fsum_body<4, false>(args, map);
 }
 
 // float4 positions per thread of a slice's F-stage work (1, 2 or 4).
@@ -1267,15 +1307,6 @@ __host__ __device__ inline int ept_bucket(int ys) {
   return e <= 1 ? 1 : (e <= 2 ? 2 : 4);
 }
 
-// Every float4-per-thread class in one launch (a server tick).
-__global__ __launch_bounds__(kFsumThreads, 4) void k_fsum_any(const PassArgs *args, const BlockMap *map) {
-  const int ys = ((CPassArgs *)map[blockIdx.x].args)->ys;
-  switch (ept_bucket(ys)) {
-    case 1: fsum_body<1>(args, map); break;
-    case 2: fsum_body<2>(args, map); break;
-    default: fsum_body<4>(args, map); break;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Second reduction level before the final phase: the group partials summed in
@@ -1438,7 +1469,7 @@ static inline int rm_bucket(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
 int split_rows_class(int J, int R, int mixed) { return (rw_bucket(R) * 8 + jw_bucket(J)) * 2 + (mixed ? 1 : 0); }
 int split_solve_class(int R) { return rm_bucket(R); }
 int split_fsum_class(int J, int R, int lagged, int mixed) {
-  return lagged ? 1000 + split_rows_class(J, R, mixed) : ept_bucket(y_stride(J, R));
+  return lagged ? 1000 + split_rows_class(J, R, mixed) : (J & 3) ? 5 : ept_bucket(y_stride(J, R));
 }
 
 // the fast row kernel's LDS: BF16-staged blocks in the mixed path
@@ -1465,6 +1496,8 @@ void split_kernel_name(int stage, const PassArgs &a, char *buf, size_t n) {
     case 3:
       if (a.lagged && a.mode == 0)
         snprintf(buf, n, "k_fsum_rows<%d, %d, %s>", rw_bucket(a.R), jw_bucket(a.J), mx ? "true" : "false");
+      else if (a.J & 3)
+        snprintf(buf, n, "k_fsum_odd");
       else
         snprintf(buf, n, "k_fsum<%d>", ept_bucket(a.ys));
       break;
@@ -1591,6 +1624,10 @@ int launch_split_fsum(const PassArgs &a, const PassArgs *args, const BlockMap *m
       DASH_RW_JW_SWITCH(launch_fsum_rows_t, false, args, map, n_blocks, bytes, s)
     }
   }
+  if (a.J & 3) {
+    hipLaunchKernelGGL(k_fsum_odd, dim3(n_blocks), dim3(kFsumThreads), bytes, s, args, map);
+    return (int)hipGetLastError();
+  }
   switch (ept_bucket(a.ys)) {
     case 1: return launch_fsum_t<1>(args, map, n_blocks, bytes, s);
     case 2: return launch_fsum_t<2>(args, map, n_blocks, bytes, s);
@@ -1605,12 +1642,6 @@ int launch_split_solve_any(const BlockMap *map, int n_blocks, hipStream_t s, siz
   return (int)hipGetLastError();
 }
 
-int launch_split_fsum_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds) {
-  if (n_blocks <= 0) return 0;
-  if (int e = allow_lds_s(k_fsum_any, lds)) return e;
-  hipLaunchKernelGGL(k_fsum_any, dim3(n_blocks), dim3(kFsumThreads), lds, s, nullptr, map);
-  return (int)hipGetLastError();
-}
 
 #undef DASH_RW_JW_SWITCH
 

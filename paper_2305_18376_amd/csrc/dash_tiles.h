@@ -44,6 +44,19 @@ __device__ __forceinline__ void buf_stf(__amdgpu_buffer_rsrc_t r, int off, float
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
 }
 
+// A value the whole wave shares, read from lane 0 (so that the compiler keeps
+// it, and what is derived from it, in scalar registers).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T *uniptr(T *p) {
+  return (T *)(uintptr_t)uni64((int64_t)(uintptr_t)p);
+}
+
 // Zero rows m .. mp - 1 (all J16 columns) and columns J .. J16 - 1 of rows
 // 0 .. m - 1 of a staged row block (stride XS).
 __device__ __forceinline__ void zero_block_pad(float *sX, int XS, int m, int mp, int J, int J16, int tid) {

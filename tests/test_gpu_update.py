@@ -164,10 +164,17 @@ def test_init_from_factors_state_matches_oracle():
     assert abs(rep["fit"] - o.fit()) <= 1e-6
 
 
+@pytest.mark.parametrize("variant", ["default", "split"])
 @pytest.mark.parametrize("J,R,n_iter", [(1, 1, 1), (7, 3, 2), (20, 5, 3), (64, 8, 1), (65, 5, 1),
                                         (88, 10, 1), (128, 20, 1), (200, 17, 2), (128, 16, 1), (64, 32, 1), (256, 32, 1)])
-def test_teacher_forced_update_shapes(J, R, n_iter):
-    """One update from an identical state, every (R, J) register class."""
+def test_teacher_forced_update_shapes(J, R, n_iter, variant, monkeypatch):
+    """One update from an identical state, every (R, J) register class, with
+    the sweep the library picks and with the split sweep (row stage, solve
+    stage, F stage; J not a multiple of 4 or 16 takes its own code there)."""
+    if variant == "split":
+        monkeypatch.setenv("DASH_VARIANT", "1")
+    else:
+        monkeypatch.delenv("DASH_VARIANT", raising=False)
     Dash = _dash()
     cfg = random_stream(J * 100 + R, K0=37, J=J, R=R, steps=3, n_iter=n_iter)
     o, g = start_pair(cfg, Dash)
