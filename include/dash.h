@@ -254,6 +254,28 @@ dash_status dash_profile_read(dash_ctx *ctx, dash_profile_stats *out);
 const char *dash_status_string(dash_status s);
 const char *dash_last_error(const dash_ctx *ctx);
 
+/* Fault injection, for tests of the error paths: the next call that reaches
+ * `site` fails there as the real failure would, then the injection is spent.
+ * Sites: DASH_SITE_INGEST -- the next dash_ingest_rows / dash_ingest_slices
+ * with work to stage returns DASH_E_CAPACITY, nothing staged;
+ * DASH_SITE_LAUNCH -- the next dash_update / dash_update_async with staged
+ * rows returns DASH_E_DEVICE before enqueuing anything, the rows stay staged;
+ * DASH_SITE_COMMIT -- the next enqueued update's commit check (final phase,
+ * on the device) treats its factors as non-finite: the update is rolled back
+ * exactly as for NaN input (DASH_E_NUMERIC, staged data dropped, state as
+ * before); DASH_SITE_INIT_ALLOC -- the next dash_init's scratch allocation
+ * fails (DASH_E_OUT_OF_MEMORY, context stays uninitialised).  DASH_SITE_NONE
+ * cancels a pending injection.  Host only; no device call.  Errors:
+ * DASH_E_INVALID_ARG (NULL ctx, unknown site). */
+typedef enum dash_fail_site {
+  DASH_SITE_NONE = 0,
+  DASH_SITE_INGEST = 1,
+  DASH_SITE_LAUNCH = 2,
+  DASH_SITE_COMMIT = 3,
+  DASH_SITE_INIT_ALLOC = 4
+} dash_fail_site;
+dash_status dash_debug_fail_next(dash_ctx *ctx, int32_t site);
+
 /* Non-blocking completion check (Algorithm 1's outputs as they become ready):
  * reaps, in order, the enqueued updates that have finished, up to cap, and
  * writes their reports to reports[0 .. *n_done).  If one of them was not

@@ -59,6 +59,7 @@ struct dash_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool served = false;   // a server's stream: launched in the server's batched ticks
+  int32_t fail_next = 0; // dash_debug_fail_next: the site whose next call fails (0: none)
   bool server_ingest = false;   // the server is staging a request (dash_ingest_* allowed)
   std::string err;
   int64_t K_cap = 0, M_cap = 0, G_cap = 0, N_init_cap = 0;

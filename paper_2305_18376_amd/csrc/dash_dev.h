@@ -38,7 +38,7 @@ struct StepHeader {
   int32_t n_chunks2;  // split sweep: solve-stage chunks (chunk2 slices each)
   int32_t chunk2;     // a sweep chunk is (chunk / chunk2) solve chunks
   int32_t seq;        // enqueue sequence number (never reused, rolled-back updates included)
-  int32_t pad;
+  int32_t force_fail; // 1: the commit check treats this update as non-finite (injected failure)
 };
 
 // One touched slice of an update: its row groups are groups[g0 .. g1).

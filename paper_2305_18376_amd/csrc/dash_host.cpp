@@ -1049,6 +1049,10 @@ dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const floa
   // the initialisation's scratch lives for this call only
   const size_t ws_doubles = init_workspace_doubles(c, K, V0 != nullptr);
   double *ws = nullptr;
+  if (c->fail_next == DASH_SITE_INIT_ALLOC) {
+    c->fail_next = 0;
+    return fail(c, DASH_E_OUT_OF_MEMORY, "initialisation scratch (%zu doubles): injected failure", ws_doubles);
+  }
   if (hipMalloc((void **)&ws, ws_doubles * sizeof(double)) != hipSuccess)
     return fail(c, DASH_E_OUT_OF_MEMORY, "initialisation scratch (%zu doubles)", ws_doubles);
   const dash_status s = init_with_workspace(c, K, row_ptr, X, V0, report, ws);
@@ -1070,6 +1074,10 @@ dash_status dash_ingest_rows(dash_ctx *c, int32_t n, const int32_t *slice_id, co
   if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
   if (n < 0) return fail(c, DASH_E_INVALID_ARG, "n < 0");
   if (n == 0) return DASH_OK;
+  if (c->fail_next == DASH_SITE_INGEST) {
+    c->fail_next = 0;
+    return fail(c, DASH_E_CAPACITY, "dash_ingest_rows: injected failure, nothing staged");
+  }
   if (!slice_id) return fail(c, DASH_E_INVALID_ARG, "slice_id is NULL");
   if (dash_status s = validate_ptr(c, row_ptr, n, false)) return s;
   const int64_t add = row_ptr[n] - row_ptr[0];
@@ -1102,6 +1110,10 @@ dash_status dash_ingest_slices(dash_ctx *c, int32_t L, const int64_t *row_ptr, c
   if (L < 0) return fail(c, DASH_E_INVALID_ARG, "L < 0");
   if (first_id) *first_id = c->K_pending;
   if (L == 0) return DASH_OK;
+  if (c->fail_next == DASH_SITE_INGEST) {
+    c->fail_next = 0;
+    return fail(c, DASH_E_CAPACITY, "dash_ingest_slices: injected failure, nothing staged");
+  }
   if (dash_status s = validate_ptr(c, row_ptr, L, true)) return s;
   if (!rows) return fail(c, DASH_E_INVALID_ARG, "rows is NULL");
   const int64_t add = row_ptr[L] - row_ptr[0];
@@ -1117,6 +1129,14 @@ dash_status dash_ingest_slices(dash_ctx *c, int32_t L, const int64_t *row_ptr, c
     c->rows_pending += m;
   }
   c->K_pending += L;
+  return DASH_OK;
+}
+
+dash_status dash_debug_fail_next(dash_ctx *c, int32_t site) {
+  if (!c) return DASH_E_INVALID_ARG;
+  if (site < DASH_SITE_NONE || site > DASH_SITE_INIT_ALLOC)
+    return fail(c, DASH_E_INVALID_ARG, "dash_debug_fail_next: unknown site %d", site);
+  c->fail_next = site;
   return DASH_OK;
 }
 
@@ -1203,6 +1223,10 @@ dash_status build_update(dash_ctx *c, BuiltUpdate *bu) {
   h->chunk2 = c2;
   h->n_chunks2 = (K + c2 - 1) / c2;
   h->seq = ++c->seq;
+  if (c->fail_next == DASH_SITE_COMMIT) {
+    h->force_fail = 1;
+    c->fail_next = 0;
+  }
   c->hreport[slot].done = 0;
   c->hreport[slot].t_start = c->hreport[slot].t_end = 0;
   const char *dblk = c->desc_fetch ? c->dstep[s] : c->hstage_dev[s];
@@ -1249,6 +1273,10 @@ dash_status dash_update_async(dash_ctx *c) {
   if (!c->initialized) return fail(c, DASH_E_BAD_STATE, "context not initialised");
   if (c->served) return fail(c, DASH_E_BAD_STATE, "a served stream is updated by its server's ticks");
   if (c->rows_pending == 0) return DASH_OK;  // empty update: no-op, no forgetting
+  if (c->fail_next == DASH_SITE_LAUNCH) {
+    c->fail_next = 0;
+    return fail(c, DASH_E_DEVICE, "injected launch failure: nothing enqueued, the staged rows stay staged");
+  }
   if ((int)c->inflight.size() >= kReportRing - 1) {
     dash_status s = dash_wait(c, nullptr);
     if (s != DASH_OK) return s;

@@ -186,7 +186,8 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   }
   const double loss = sum_n - 2.0 * VF + VG;
   const double fit = sum_n > 0.0 ? 1.0 - sqrt(fmax(0.0, loss)) / sqrt(sum_n) : 1.0;
-  const bool ok = isfinite(loss) && !sFlag[1];
+  // (an injected failure takes the same path as non-finite factors)
+  const bool ok = isfinite(loss) && !sFlag[1] && !(mode == 0 && h->force_fail);
   if (tid == 0) {
     a.ctl->loss = loss;
     a.ctl->fit = fit;

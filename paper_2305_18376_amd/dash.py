@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdash.so")
 
 OK, E_INVALID_ARG, E_OUT_OF_MEMORY, E_BAD_STATE, E_CAPACITY, E_NUMERIC, E_DEVICE, E_IO = range(8)
 PREC_FP32, PREC_MIXED = 0, 1
+SITE_NONE, SITE_INGEST, SITE_LAUNCH, SITE_COMMIT, SITE_INIT_ALLOC = range(5)   # dash_debug_fail_next
 STATS_EXACT, STATS_LAGGED = 0, 1
 
 
@@ -119,6 +120,7 @@ _SIGS = {
     "dash_profile": (C.c_int, [_P, C.c_int32]),
     "dash_profile_read": (C.c_int, [_P, C.POINTER(ProfileStats)]),
     "dash_status_string": (C.c_char_p, [C.c_int]),
+    "dash_debug_fail_next": (C.c_int, [_P, C.c_int32]),
     "dash_last_error": (C.c_char_p, [_P]),
     "dash_poll": (C.c_int, [_P, C.POINTER(UpdateReport), C.c_int32, C.POINTER(C.c_int32)]),
     "dash_footprint": (C.c_int, [C.POINTER(DashConfig), C.POINTER(C.c_int64)]),
@@ -257,6 +259,11 @@ class Dash:
             self.close()
         except Exception:
             pass
+
+    def debug_fail_next(self, site):
+        """Make the next call reaching `site` (SITE_INGEST, SITE_LAUNCH,
+        SITE_COMMIT, SITE_INIT_ALLOC; SITE_NONE cancels) fail there."""
+        self._check(lib().dash_debug_fail_next(self._h, int(site)), "dash_debug_fail_next")
 
     def dims(self):
         d = Dims()

@@ -68,6 +68,7 @@ def test_null_arguments():
     assert L.dash_update(None, None) == D.E_INVALID_ARG
     assert L.dash_get_dims(None, None) == D.E_INVALID_ARG
     assert L.dash_last_error(None) == b""
+    assert L.dash_debug_fail_next(None, D.SITE_COMMIT) == D.E_INVALID_ARG
 
 
 def test_footprint_and_admission_without_a_device():

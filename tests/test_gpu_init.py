@@ -108,3 +108,18 @@ def test_init_shapes_then_one_update(J, R):
     upd = g.update()
     print("update fit", upd["fit"], r.fit, flush=True)
     assert abs(upd["fit"] - r.fit) <= 1e-5
+
+
+def test_init_at_the_mid_workload_size():
+    """The initial decomposition at the mid workload's full size: K0 = 2000
+    slices of log-normal length (median 800, clipped to [100, 4000]; about 2.3
+    million rows), J = 88, R = 10, two ALS iterations from the same V0 on both
+    sides, held to the toy-size bounds of compare()."""
+    wl = make_workload("mid", n_steps=1)
+    ptr, X = wl.init_data()
+    print("rows", int(ptr[-1]), flush=True)
+    slices = [X[ptr[k]:ptr[k + 1]] for k in range(wl.K0)]
+    rng = np.random.default_rng(11)
+    V0 = np.linalg.qr(rng.standard_normal((wl.J, wl.R)))[0]
+    o, res, g, rep = run_pair(slices, wl.R, max_iter=2, tol=0.0, V0=V0, lam=wl.lam)
+    compare(o, res, g, rep, tag="mid full size")
