@@ -1209,22 +1209,21 @@ __device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *
       for (int e = 0; e < EPT; ++e) o.v[e] = y[min(tq + tps * e, nq - 1)];
       return o;
     };
-    V4 c1 = load(sg), c2;
-    if constexpr (NS == 2) c2 = load(sg + spi);
-#pragma unroll 1
-    for (int i = sg; i < nb; i += NS * spi) {
+    // the sums of one step: slices i and, with NS = 2, i + spi; weights of
+    // entries outside the slice, or of a missing second slice, are zero, so
+    // every lane runs the same FMAs
+    auto sum_step = [&](V4 &x1, V4 &x2, int i) {
+      // this step's floats as floats: their wait and conversion happen here,
+      // one step after their loads went out
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        asm volatile("" : "+v"(x1.v[e].x), "+v"(x1.v[e].y), "+v"(x1.v[e].z), "+v"(x1.v[e].w));
+        if constexpr (NS == 2)
+          asm volatile("" : "+v"(x2.v[e].x), "+v"(x2.v[e].y), "+v"(x2.v[e].z), "+v"(x2.v[e].w));
+      }
       const int i2 = i + spi;
       const bool two = NS == 2 && i2 < nb;
-      const V4 x1 = c1;
-      V4 x2;
-      if constexpr (NS == 2) x2 = c2;
-      // the next step's slices (unconditionally: past the batch the clamped
-      // load repeats its last slice, which is not summed again)
-      c1 = load(i + NS * spi);
-      if constexpr (NS == 2) c2 = load(i + NS * spi + spi);
       const double *w1 = sw + i * R, *w2 = sw + (two ? i2 : i) * R;
-      // weights of entries outside the slice, or of a missing second
-      // slice, are zero: every lane runs the same FMAs
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int el = 4 * (tq + tps * e);
@@ -1255,6 +1254,27 @@ __device__ __forceinline__ void fsum_body(const PassArgs *args, const BlockMap *
           }
         }
       }
+    };
+    // Two register sets in turn (A, B): a step's sums run while the next
+    // step's slices load into the other set.  The next loads go out
+    // unconditionally (past the batch the clamped load repeats its last
+    // slice, which is not summed again); the empty asm keeps them ahead of
+    // the sums (without it the compiler proves a set equals a fresh load of
+    // its slice and moves the load down to its use).
+    const int step = NS * spi;
+    V4 a1 = load(sg), a2, b1, b2;
+    if constexpr (NS == 2) a2 = load(sg + spi);
+#pragma unroll 1
+    for (int i = sg; i < nb; i += 2 * step) {
+      b1 = load(i + step);
+      if constexpr (NS == 2) b2 = load(i + step + spi);
+      asm volatile("" ::: "memory");
+      sum_step(a1, a2, i);
+      if (i + step >= nb) break;
+      a1 = load(i + 2 * step);
+      if constexpr (NS == 2) a2 = load(i + 2 * step + spi);
+      asm volatile("" ::: "memory");
+      sum_step(b1, b2, i + step);
     }
   }
   // the slice groups' sums added in group order
