@@ -33,23 +33,25 @@ constexpr int kFinishThreads = 512;   // 2 waves per SIMD: up to 256 VGPRs for t
 constexpr int kFinishRed = 48;        // doubles of the reduction scratch
 constexpr int kFinishScr = 1024;      // doubles of the split-product scratch (>= R^2)
 
+// F^T (R rows of stride J | 1), G, G^{-1}, (V^T V)^{-1}, V^T V, the
+// pseudo-inverse scratch, reductions and flags
 __host__ __device__ inline size_t finish_lds_bytes(int J, int R) {
-  return (size_t)(R * J + 5 * R * R + 64 + kFinishRed + kFinishScr) * 8 + 68 * 4;
-}
-// with a copy of V (J x R, FP64) kept in LDS as well
-__host__ __device__ inline size_t finish_lds_bytes_v(int J, int R) {
-  return finish_lds_bytes(J, R) + (size_t)J * R * 8;
+  return (size_t)(R * (J | 1) + 5 * R * R + 64 + kFinishRed + kFinishScr) * 8 + 68 * 4;
 }
 
 
 template <int RM>
 __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroups, int mode,
                             unsigned char *smem, size_t lds_avail) {
+  (void)lds_avail;
   const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
   const int J = a.J, R = a.R, RR = R * R, RJ = R * J;
+  const int JS = J | 1;            // row stride of F^T and V^T: a column's rows in different banks
   const int plen = partial_len(J, R);
-  double *sF = (double *)smem;   // F^T, R x J
-  double *sG = sF + RJ;
+  // F^T (R x J); V^T replaces it in place once V is formed, and every later
+  // product reads V from there
+  double *sF = (double *)smem;
+  double *sG = sF + R * JS;
   double *sGi = sG + RR;         // G^{-1}
   double *sB = sGi + RR;         // (V^T V)^{-1}
   double *sVtV = sB + RR;
@@ -59,13 +61,9 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   double *sScr = sRed + kFinishRed;   // kFinishScr: split products
   int *sPair = (int *)(sScr + kFinishScr);
   int *sFlag = sPair + 64;       // [0], [2]: inverse ok, [1]: non-finite seen
-  // V (J x R) in LDS when the workgroup has room, else worked on in V64 directly
-  double *sVl = (double *)(smem + finish_lds_bytes(J, R));
-  const bool v_lds = lds_avail >= finish_lds_bytes_v(J, R);
   const int gcur = a.ctl->gcur;
   const int out = (mode == 0) ? 1 - gcur : gcur;
   const VBundleView vo = vb_view(a.vb + (int64_t)out * a.vb_stride, J, R);
-  double *Vw = v_lds ? sVl : vo.V64;   // V, row-major J x R
   if (tid == 0) {
     sFlag[0] = 1;
     sFlag[1] = 0;
@@ -75,7 +73,8 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
   if (mode != 1) {
     for (int e = tid; e < plen; e += nt) {
       const double s = ordered_sum(a.gpart, plen, e, 0, n_rgroups);
-      if (e < RJ + RR) sF[e] = s;   // sF and sG are contiguous
+      if (e < RJ) sF[(e / J) * JS + e % J] = s;
+      else if (e < RJ + RR) sG[e - RJ] = s;
       else sRed[kFinishRed - 1] = s;
     }
   }
@@ -86,68 +85,89 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
     // terms are the committed F, G scaled by lambda; the partials hold the
     // new rows' terms
     const double *fg = a.FG + (int64_t)gcur * (RJ + RR);
-    for (int e = tid; e < RJ + RR; e += nt) sF[e] = fma(a.lambda, fg[e], sF[e]);
+    for (int e = tid; e < RJ + RR; e += nt) {
+      double *d = e < RJ ? sF + (e / J) * JS + e % J : sG + (e - RJ);
+      *d = fma(a.lambda, fg[e], *d);
+    }
     __syncthreads();
   }
   if (a.lagged && mode != 1) {
     // the lagged F, G of this pass (committed with it), or, evaluating the
     // initial state, the exact ones the recursions start from
     double *fg = a.FG + (int64_t)(mode == 0 ? 1 - gcur : gcur) * (RJ + RR);
-    for (int e = tid; e < RJ + RR; e += nt) fg[e] = sF[e];
+    for (int e = tid; e < RJ + RR; e += nt) fg[e] = e < RJ ? sF[(e / J) * JS + e % J] : sG[e - RJ];
   }
   double vf = 0.0;
   if (mode == 0) {
-    // Lemma 3: V = F G^{-1}
+    // Lemma 3: V = F G^{-1}, formed as V^T[:, j] = G^{-T} F^T[:, j] by one
+    // thread per column j, in place (the column is read into registers first)
     if (!block_spd_inverse<RM>(sG, sGi, R) && lane == 0) sFlag[0] = 0;
     __syncthreads();
     if (!sFlag[0]) block_pinv_of(sG, sGi, sB, sZ, R, sRot, sPair);
     bool bad = false;
-    for (int e = tid; e < J * R; e += nt) {
-      const int j = e / R, r = e - j * R;
-      double x = 0.0;
-#pragma unroll 4
-      for (int c = 0; c < R; ++c) x = fma(sF[c * J + j], sGi[c * R + r], x);
-      Vw[e] = x;
-      if (v_lds) vo.V64[e] = x;
-      vf = fma(x, sF[r * J + j], vf);
-      bad |= !isfinite(x);
+    for (int j = tid; j < J; j += nt) {
+      double f[RM];
+#pragma unroll
+      for (int c = 0; c < RM; ++c) f[c] = (c < R) ? sF[c * JS + j] : 0.0;
+      for (int r = 0; r < R; ++r) {
+        double x = 0.0;
+#pragma unroll
+        for (int c = 0; c < RM; ++c)
+          if (c < R) x = fma(f[c], sGi[c * R + r], x);
+        const double fr = sF[r * JS + j];   // F^T[r][j], not yet replaced
+        vf = fma(x, fr, vf);
+        bad |= !isfinite(x);
+        sF[r * JS + j] = x;
+        vo.V64[(size_t)j * R + r] = x;
+      }
     }
     if (bad) sFlag[1] = 1;
   } else {
     for (int e = tid; e < J * R; e += nt) {
+      const int j = e / R, r = e - j * R;
       const double x = vo.V64[e];
-      if (v_lds) sVl[e] = x;
-      if (mode == 2) {
-        const int j = e / R, r = e - j * R;
-        vf = fma(x, sF[r * J + j], vf);
-      }
+      if (mode == 2) vf = fma(x, sF[r * JS + j], vf);
+      sF[r * JS + j] = x;
     }
   }
   __syncthreads();
 
   if (mode != 2) {
-    // next pass operands: V^T V, B = (V^T V)^{-1}, P = V B, V^T in float32
-    // V^T V with S threads per entry over interleaved rows j, the S partial
-    // sums added in a fixed order
-    const int S = max(1, min(8, kFinishScr / RR));
-    for (int t = tid; t < RR * S; t += nt) {
-      const int q = t / S, part = t - q * S;
-      const int r = q / R, c = q - r * R;
-      double acc = 0.0;
+    // next pass operands: V^T V, B = (V^T V)^{-1}, P = V B, V^T in float32.
+    // V^T V by 2 x 2 blocks on and above the diagonal (each entry one FMA
+    // chain over j in order; the mirror entry is the same chain)
+    const int RH = (R + 1) >> 1;
+    for (int t = tid; t < RH * RH; t += nt) {
+      const int rb = t / RH, cb = t - rb * RH;
+      if (cb < rb) continue;
+      const int r0 = 2 * rb, c0 = 2 * cb, r1 = min(r0 + 1, R - 1), c1 = min(c0 + 1, R - 1);
+      const double *v0 = sF + r0 * JS, *v1 = sF + r1 * JS, *w0 = sF + c0 * JS, *w1 = sF + c1 * JS;
+      double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
 #pragma unroll 4
-      for (int j = part; j < J; j += S) acc = fma(Vw[(size_t)j * R + r], Vw[(size_t)j * R + c], acc);
-      sScr[t] = acc;
+      for (int j = 0; j < J; ++j) {
+        const double x0 = v0[j], x1 = v1[j], y0 = w0[j], y1 = w1[j];
+        a00 = fma(x0, y0, a00);
+        a01 = fma(x0, y1, a01);
+        a10 = fma(x1, y0, a10);
+        a11 = fma(x1, y1, a11);
+      }
+      const double acc[2][2] = {{a00, a01}, {a10, a11}};
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int r = r0 + i, c = c0 + k;
+          if (r < R && c < R) {
+            sVtV[r * R + c] = acc[i][k];
+            sVtV[c * R + r] = acc[i][k];
+            vo.VtV[r * R + c] = acc[i][k];
+            vo.VtV[c * R + r] = acc[i][k];
+          }
+        }
     }
     for (int e = tid; e < RJ; e += nt) {
       const int r = e / J, j = e - r * J;
-      vo.Vt32[e] = (float)Vw[(size_t)j * R + r];
-    }
-    __syncthreads();
-    for (int q = tid; q < RR; q += nt) {
-      double acc = 0.0;
-      for (int part = 0; part < S; ++part) acc += sScr[q * S + part];
-      sVtV[q] = acc;
-      vo.VtV[q] = acc;
+      vo.Vt32[e] = (float)sF[r * JS + j];
     }
     __syncthreads();
     if (!block_spd_inverse<RM>(sVtV, sB, R, vo.piv) && lane == 0) sFlag[2] = 0;
@@ -157,12 +177,19 @@ __device__ void finish_pass(const PassArgs &a, const StepHeader *h, int n_rgroup
       if (tid < R) vo.piv[tid] = 0.0;
       block_pinv_of(sVtV, sB, sGi, sZ, R, sRot, sPair);
     }
-    for (int e = tid; e < J * R; e += nt) {
-      const int j = e / R, c = e - j * R;
-      double acc = 0.0;
-#pragma unroll 4
-      for (int r = 0; r < R; ++r) acc = fma(Vw[(size_t)j * R + r], sB[r * R + c], acc);
-      vo.P32[e] = (float)acc;
+    // P = V B, four columns per thread
+    const int CB = (R + 3) >> 2;
+    for (int e = tid; e < J * CB; e += nt) {
+      const int j = e / CB, c0 = 4 * (e - j * CB);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int r = 0; r < R; ++r) {
+        const double v = sF[r * JS + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = fma(v, sB[r * R + min(c0 + i, R - 1)], acc[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (c0 + i < R) vo.P32[(size_t)j * R + c0 + i] = (float)acc[i];
     }
   } else {
     for (int q = tid; q < RR; q += nt) sVtV[q] = vo.VtV[q];
@@ -232,10 +259,7 @@ struct FinishBucket {
 };
 
 // Final phase of a pass as its own single-workgroup launch (modes as finish_pass).
-__host__ __device__ inline size_t finish_launch_lds(int J, int R) {
-  const size_t with_v = finish_lds_bytes_v(J, R);
-  return with_v <= 150 * 1024 ? with_v : finish_lds_bytes(J, R);
-}
+__host__ __device__ inline size_t finish_launch_lds(int J, int R) { return finish_lds_bytes(J, R); }
 
 template <int RM>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(PassArgs a, int mode) {
@@ -1012,10 +1036,8 @@ size_t fused_pass_lds(int variant, int J, int R) {
   if (variant != kPassWave) return 0;   // the split sweep ends in a separate final-phase launch
   const size_t sweep = wave_lds(J, R).bytes;
   const size_t cap = 160 * 1024 - 1024;   // the kernels' static LDS (flags, small sums) stays under 1 KiB
-  const size_t with_v = std::max(sweep, finish_launch_lds(J, R));
-  if (with_v <= cap) return with_v;
-  const size_t base = std::max(sweep, finish_lds_bytes(J, R));
-  return base <= cap ? base : 0;
+  const size_t need = std::max(sweep, finish_lds_bytes(J, R));
+  return need <= cap ? need : 0;
 }
 
 template <int RW, int JW>
