@@ -444,8 +444,8 @@ dash_status dash_server_poll(dash_server *srv, int32_t wait, dash_server_report 
                              int32_t *n);
 /* Run ticks and completion polling on a host thread of the server's own: a
  * tick starts when rows are waiting, tick_us microseconds have passed since the
- * last one (0: at once) and either no tick is in flight or one is and a
- * quarter of the open streams have rows waiting.  Errors: DASH_E_BAD_STATE
+ * last one (0: at once) and either no tick is in flight or one is and
+ * every open stream has rows waiting.  Errors: DASH_E_BAD_STATE
  * when already running. */
 dash_status dash_server_start(dash_server *srv, int32_t tick_us);
 /* Stop the loop thread (updates in flight continue; poll with wait = 1). */

@@ -265,8 +265,6 @@ int launch_reduce_groups(const PassArgs *args, const BlockMap *map, int n_blocks
 // solve stage, the exact-mode F stage and the final phase (mode 0), each
 // workgroup running the instantiation of its own context's R (and J).  lds:
 // the largest dynamic LDS among the members.
-int launch_split_solve_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds);
-int launch_finish_dev_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds);
 size_t split_rows_lds(int J, int R, int mixed);
 size_t split_solve_lds(int J, int R);
 size_t split_fsum_lds(int J, int R, int lagged);

@@ -278,26 +278,6 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish_dev(const PassArgs *a
   finish_pass<RM>(a, h, ng, mode, smem, finish_launch_lds(a.J, a.R));
 }
 
-// Every rank class in one launch (a server tick, mode 0): each workgroup runs
-// the final phase of its own context with the instantiation of its R.
-__global__ __launch_bounds__(kFinishThreads) void k_finish_dev_any(const BlockMap *map) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const PassArgs a = *map[blockIdx.x].args;
-  const StepHeader *h = a.hdr;
-  const int ng = a.pre_reduced ? 1 : h->n_rgroups;
-  const size_t lds = finish_launch_lds(a.J, a.R);
-  if (a.R <= 8)
-    finish_pass<8>(a, h, ng, 0, smem, lds);
-  else if (a.R <= 12)
-    finish_pass<12>(a, h, ng, 0, smem, lds);
-  else if (a.R <= 16)
-    finish_pass<16>(a, h, ng, 0, smem, lds);
-  else if (a.R <= 24)
-    finish_pass<24>(a, h, ng, 0, smem, lds);
-  else
-    finish_pass<32>(a, h, ng, 0, smem, lds);
-}
-
 // ---------------------------------------------------------------------------
 // Sweep variant 1: one wave per slice ("wave" variant, R*J <= 2048, J <= 128).
 // 8 waves per workgroup; wave w handles slices k0+w, k0+w+8, ... of the chunk.
@@ -1093,13 +1073,6 @@ int launch_finish_dev(const PassArgs &a, const PassArgs *args, const BlockMap *m
     case 24: return launch_finish_dev_t<24>(args, map, n_blocks, mode, bytes, s);
     default: return launch_finish_dev_t<32>(args, map, n_blocks, mode, bytes, s);
   }
-}
-
-int launch_finish_dev_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds) {
-  if (n_blocks <= 0) return 0;
-  if (int e = allow_lds(k_finish_dev_any, lds)) return e;
-  hipLaunchKernelGGL(k_finish_dev_any, dim3(n_blocks), dim3(kFinishThreads), lds, s, map);
-  return (int)hipGetLastError();
 }
 
 int launch_finish(const PassArgs &a, int mode, hipStream_t s) {

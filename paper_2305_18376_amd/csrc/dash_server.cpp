@@ -16,9 +16,9 @@
 // does not fit may wait in a FIFO queue and is admitted when closes free the
 // budget.  dash_server_start runs the tick/poll loop on a host thread of its
 // own: a tick is launched as soon as rows are waiting and no tick is in
-// flight, or beside the one in flight once a quarter of the open streams have
-// rows waiting, so requests that arrive while the GPU works join the next tick
-// (continuous batching) and ticks stay full under load.
+// flight, or beside the one in flight once every open stream has rows
+// waiting, so requests that arrive while the GPU works join the next tick
+// (continuous batching) and a second tick in flight is a full one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -399,12 +399,12 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
         switch (stage) {
           case 0: key = split_rows_class(c->J, c->R, mixed); break;
           case 1: key = mixed; break;
-          // solve and final phase: one launch for every class; the F stage per
-          // class (its instantiations differ in registers and occupancy)
-          case 2: key = 0; break;
+          // one launch per kernel instantiation (they differ in registers and
+          // occupancy), the classes of a stage side by side
+          case 2: key = split_solve_class(c->R); break;
           case 3: key = split_fsum_class(c->J, c->R, lagged, mixed); break;
           case 4: key = 0; break;
-          default: key = 0; break;
+          default: key = finish_class(c->R); break;
         }
         auto it = std::find_if(classes.begin(), classes.end(), [&](const auto &e) { return e.first == key; });
         if (it == classes.end()) {
@@ -505,10 +505,7 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
     ProfRec pr{nullptr, nullptr, 0, L.bytes};
     if (timed) {
       char name[48];
-      if (L.stage == 2 || L.stage == 5)
-        std::snprintf(name, sizeof name, "%s", L.stage == 2 ? "k_solve_any" : "k_finish_dev_any");
-      else
-        split_kernel_name(L.stage, L.rep, name, sizeof name);
+      split_kernel_name(L.stage, L.rep, name, sizeof name);
       pr.entry = prof_entry(srv, name);
       pr.a = take_timing_event(srv);
       pr.b = take_timing_event(srv);
@@ -519,12 +516,12 @@ dash_status run_tick(dash_server *srv, int32_t *launched) {
       case 0: e = launch_split_rows(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 1: e = launch_split_rows_slow(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 2:
-        e = launch_split_solve_any(m, L.n_blocks, s, L.lds);
+        e = launch_split_solve(L.rep, nullptr, m, L.n_blocks, s, L.lds);
         if (!e) e = launch_split_solve_fix(nullptr, m, L.n_blocks, s, L.lds);
         break;
       case 3: e = launch_split_fsum(L.rep, nullptr, m, L.n_blocks, s, L.lds); break;
       case 4: e = launch_reduce_groups(nullptr, m, L.n_blocks, s); break;
-      default: e = launch_finish_dev_any(m, L.n_blocks, s, L.lds); break;
+      default: e = launch_finish_dev(L.rep, nullptr, m, L.n_blocks, 0, s, L.lds); break;
     }
     if (e) return dev_fail(e);
     if (timed) {
@@ -594,13 +591,14 @@ void loop_main(dash_server *srv) {
     dash_status s = collect(srv);
     if (s != DASH_OK && srv->loop_err == DASH_OK) srv->loop_err = s;
     // a tick starts when none is in flight, or beside the one in flight when
-    // a quarter of the open streams are ready (so ticks stay full when the
-    // device is busy, and requests never wait for an idle device)
+    // every open stream is ready (a stream's update costs work in proportion
+    // to its slices whatever its rows, so under load ticks should carry every
+    // stream; requests never wait for an idle device)
     const bool due = srv->tick_us <= 0 || now_us() - srv->last_tick >= (double)srv->tick_us;
     int open = 0, ready = 0;
     ready_count(srv, &open, &ready);
     const int inflight = (int)srv->ticks_in_flight.size();
-    if (due && ready > 0 && (inflight == 0 || (inflight < kTicksInFlight && 4 * ready >= open))) {
+    if (due && ready > 0 && (inflight == 0 || (inflight < kTicksInFlight && ready >= open))) {
       s = run_tick(srv, nullptr);
       if (s != DASH_OK && srv->loop_err == DASH_OK) srv->loop_err = s;
     }

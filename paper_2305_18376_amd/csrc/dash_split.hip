@@ -1098,18 +1098,6 @@ __global__ __launch_bounds__(64 * kSolveWaves, 2) void k_solve(const PassArgs *a
   solve_body<RM>(args, map);
 }
 
-// Every rank class in one launch (a server tick): each workgroup takes the
-// body of its own context's R.
-__global__ __launch_bounds__(64 * kSolveWaves, 2) void k_solve_any(const PassArgs *args, const BlockMap *map) {
-  const int R = ((CPassArgs *)map[blockIdx.x].args)->R;
-  if (R <= 8)
-    solve_body<8>(args, map);
-  else if (R <= 16)
-    solve_body<16>(args, map);
-  else
-    solve_body<32>(args, map);
-}
-
 // ---------------------------------------------------------------------------
 // F stage, exact mode: F^T = sum_k sigma_k diag(w_k) Y_k over every slice of
 // the chunk, streamed as float4 from the flat R x J layout.  512 threads; TPS
@@ -1654,14 +1642,6 @@ int launch_split_fsum(const PassArgs &a, const PassArgs *args, const BlockMap *m
     default: return launch_fsum_t<4>(args, map, n_blocks, bytes, s);
   }
 }
-
-int launch_split_solve_any(const BlockMap *map, int n_blocks, hipStream_t s, size_t lds) {
-  if (n_blocks <= 0) return 0;
-  if (int e = allow_lds_s(k_solve_any, lds)) return e;
-  hipLaunchKernelGGL(k_solve_any, dim3(n_blocks), dim3(64 * kSolveWaves), lds, s, nullptr, map);
-  return (int)hipGetLastError();
-}
-
 
 #undef DASH_RW_JW_SWITCH
 
