@@ -836,6 +836,38 @@ __device__ __forceinline__ void load_d_row(const SolveSlice &x, int R, int r, do
   }
 }
 
+// Row r of D_k and its compensation words as loaded (R a multiple of 4):
+// issued early, converted where the row is used.
+template <int RM>
+struct DRowRaw {
+  float4 v[RM / 4], e[RM / 4];
+};
+
+template <int RM>
+__device__ __forceinline__ void load_d_row_raw(const SolveSlice &x, int R, int r, DRowRaw<RM> &o) {
+  const float4 *d4 = reinterpret_cast<const float4 *>(x.Dp + min(r, R - 1) * R);
+  const float4 *e4 = x.Dcp ? reinterpret_cast<const float4 *>(x.Dcp + min(r, R - 1) * R) : d4;
+#pragma unroll
+  for (int c4 = 0; c4 < RM / 4; ++c4) {
+    const int cc = min(c4, R / 4 - 1);
+    o.v[c4] = d4[cc];
+    o.e[c4] = e4[cc];
+  }
+}
+
+template <int RM>
+__device__ __forceinline__ void d_row_from_raw(const DRowRaw<RM> &o, bool comp, int R, int r, double (&d)[RM]) {
+#pragma unroll
+  for (int c4 = 0; c4 < RM / 4; ++c4) {
+    const bool in = r < R && 4 * c4 < R;
+    const float4 v = o.v[c4], e = o.e[c4];
+    d[4 * c4 + 0] = in ? (double)v.x + (comp ? (double)e.x : 0.0) : 0.0;
+    d[4 * c4 + 1] = in ? (double)v.y + (comp ? (double)e.y : 0.0) : 0.0;
+    d[4 * c4 + 2] = in ? (double)v.z + (comp ? (double)e.z : 0.0) : 0.0;
+    d[4 * c4 + 3] = in ? (double)v.w + (comp ? (double)e.w : 0.0) : 0.0;
+  }
+}
+
 // Gauss-Jordan of one group of RM lanes: lane base + r holds row r of an
 // RM x RM system (rows n .. RM - 1 are padding) and entry r of the right-hand
 // side; pivot rows are exchanged within the group.  The acceptance rule of the
@@ -985,11 +1017,26 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
       const SolveSlice x = solve_slice(a, k, gcur, step, seq, upd, RR);
       double w = 0.0;
       bool use = true;
+      // n_k goes out with the first loads of the slice (the 32-rank kernel,
+      // short of registers, loads it where it is used)
+      double nk = 0.0;
+      if (RM < 32 && r == 0) nk = a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k];
       if (upd) {
+        // the D row too (R a multiple of 4, and only where the registers
+        // allow it without spills or a lower occupancy: the 16-rank kernel):
+        // one round trip with the first c_k loads instead of one after them;
+        // the empty asm keeps these loads ahead of the dot products
+        const bool raw = RM == 16 && (R & 3) == 0;
+        DRowRaw<RM> dr;
+        if (raw) load_d_row_raw<RM>(x, R, r, dr);
+        asm volatile("" ::: "memory");
         double b = solve_c_row(a, x, k, J, R, r, sVt, L.vts);
         // Lemma 2: (V^T V * D_k) w = c
         double m[RM];
-        load_d_row<RM>(x, R, r, m);
+        if (raw)
+          d_row_from_raw<RM>(dr, x.Dcp != nullptr, R, r, m);
+        else
+          load_d_row<RM>(x, R, r, m);
 #pragma unroll
         for (int c = 0; c < RM; ++c) m[c] = (r < R && c < R) ? sVtV[r * (R + 1) + c] * m[c] : 0.0;
         double dpiv;
@@ -1022,7 +1069,10 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
             gacc[i] = fma(sr * wi, d[i], gacc[i]);
           }
         }
-        if (r == 0) nacc = fma(x.sig, a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k], nacc);
+        if (r == 0) {
+          if (RM == 32) nk = a.n[(int64_t)(x.touched ? 1 - x.b : x.b) * a.K_cap + k];
+          nacc = fma(x.sig, nk, nacc);
+        }
       }
     }
   }
