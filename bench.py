@@ -50,15 +50,23 @@ WORKLOAD_TEXT = {
 }
 
 
+def state_entry_bytes(words):
+    """Bytes per Y_k and per D_k entry: float32 (words = 1), or the mixed
+    path's float32 word plus its compensation word (BF16 for Y, float32 for
+    D)."""
+    return (4, 4) if words == 1 else (6, 8)
+
+
 def algorithmic_bytes(M, K, K_t, J, R, words=1):
     """Bytes one update pass must move (the per-pass model of the design notes):
-    new rows read, U_new written, every slice's Y_k / D_k / n_k / W row read,
-    touched slices' Y_k / D_k / n_k written, every W row written.  `words` = 2
-    counts the compensation word the mixed path keeps beside each Y_k / D_k
-    entry."""
+    new rows read, U_new written, every slice's Y_k (value words) / D_k / n_k /
+    W row read, touched slices' Y_k / D_k / n_k written, every W row written.
+    `words` = 2: the mixed path, whose touched slices move their compensation
+    words too (state_entry_bytes)."""
+    yb, db = state_entry_bytes(words)
     return (M * J * 4 + M * R * 4
-            + K * (words * (R * J * 4 + R * R * 4) + 8 + R * 8)
-            + K_t * (words * (R * J * 4 + R * R * 4) + 8)
+            + K * (R * J * 4 + R * R * db + 8 + R * 8)
+            + K_t * (R * J * yb + R * R * db + 8)
             + K * R * 8)
 
 
@@ -68,9 +76,10 @@ KERNEL_SOURCES = ("dash_dev.h", "dash_math.h", "dash_tiles.h", "dash_kernels.hip
 def rows_stage_bytes(M, K_t, J, R, words=1):
     """Bytes the split sweep's row stage must move: the new rows read, U_new
     written, and each touched slice's Y_k / D_k read and the folded ones
-    written (words per entry as above), its n_k read and written and its c_k
-    written."""
-    return M * J * 4 + M * R * 4 + K_t * (2 * words * (R * J + R * R) * 4 + 16 + R * 8)
+    written (bytes per entry as state_entry_bytes), its n_k read and written
+    and its c_k written."""
+    yb, db = state_entry_bytes(words)
+    return M * J * 4 + M * R * 4 + K_t * (2 * (R * J * yb + R * R * db) + 16 + R * 8)
 
 
 def _source_digest():

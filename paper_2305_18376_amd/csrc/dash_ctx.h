@@ -65,7 +65,7 @@ struct dash_ctx {
   int64_t K_cap = 0, M_cap = 0, G_cap = 0, N_init_cap = 0;
   // device state
   float *Y = nullptr;
-  float *Yc = nullptr;   // compensation words of Y and D (mixed precision only)
+  uint16_t *Yc = nullptr;   // compensation words of Y (BF16 bits) and D (mixed precision only)
   float *Dc = nullptr;
   float *D = nullptr;
   double *n = nullptr;

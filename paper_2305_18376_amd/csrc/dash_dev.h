@@ -124,7 +124,7 @@ struct PassArgs {
   const int32_t *chunk_gptr;   // [n_chunks+1]
   const Group *groups;
   float *Y;            // [2][K_cap][ys]: R x J row-major, zero padded
-  float *Yc;           // mixed precision: compensation of Y (same layout), else NULL
+  uint16_t *Yc;        // mixed precision: compensation of Y as BF16 bits (same layout), else NULL
   float *Dc;           // mixed precision: compensation of D, else NULL
   float *D;            // [2][K_cap][R][R]
   double *n;           // [2][K_cap]
@@ -320,11 +320,13 @@ int launch_v_from_f32(int J, int R, const float *V, char *vb_committed, hipStrea
 int launch_w_from_f32(int R, int K, const float *W, double *Wc, hipStream_t s);
 int launch_export_state(int J, int R, int K, int64_t step, double lambda, const float *Y,
                         const float *D, const double *n, const uint8_t *cur, const int32_t *tlast,
-                        int64_t K_cap, double *Yo, double *Do, double *no, const float *Yc, const float *Dc,
+                        int64_t K_cap, double *Yo, double *Do, double *no, const uint16_t *Yc, const float *Dc,
                         hipStream_t s);
 int launch_gather_state(int J, int R, int K, const float *Y, const float *D, const double *n,
                         const uint8_t *cur, int64_t K_cap, float *Yo, float *Do, double *no,
                         hipStream_t s);
+int launch_gather_carry(int J, int R, int K, const uint16_t *Yc, const float *Dc, const uint8_t *cur, int64_t K_cap,
+                        float *Yo, float *Do, hipStream_t s);
 int launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 
 }  // namespace dash

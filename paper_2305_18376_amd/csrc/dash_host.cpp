@@ -53,6 +53,15 @@ dash_status fail(dash_ctx *c, dash_status s, const char *fmt, ...) {
                   hipGetErrorString((hipError_t)e_));                                  \
   } while (0)
 
+// float -> BF16 bits, rounded to nearest even (the compensation words of Y)
+inline uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 template <typename T>
 hipError_t dalloc(T **p, size_t bytes) {
   return hipMalloc((void **)p, bytes < 256 ? 256 : bytes);
@@ -360,7 +369,7 @@ dash_status enqueue_prep(dash_ctx *c) {
 dash_status reset_device_state(dash_ctx *c, int32_t K, int32_t tl) {
   HIP_OR_FAIL(c, hipMemsetAsync(c->cur, 0, (size_t)(2 * c->K_cap), c->stream));
   if (c->Yc) {
-    HIP_OR_FAIL(c, hipMemsetAsync(c->Yc, 0, sizeof(float) * 2 * c->K_cap * y_stride(c->J, c->R), c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->Yc, 0, sizeof(uint16_t) * 2 * c->K_cap * y_stride(c->J, c->R), c->stream));
     HIP_OR_FAIL(c, hipMemsetAsync(c->Dc, 0, sizeof(float) * 2 * c->K_cap * c->R * c->R, c->stream));
   }
   if (tl == 0) {
@@ -400,7 +409,7 @@ int64_t context_footprint(const dash_config *cfg) {
   const int64_t step_bytes = (int64_t)align_up(
       align_up(align_up(off_gptr + sizeof(int32_t) * (n_chunks_cap + 1), 64) + sizeof(Group) * G_cap, 64) +
           sizeof(Item) * G_cap, 256);
-  const int64_t carry = cfg->precision == DASH_PREC_MIXED ? al(4 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) : 0;
+  const int64_t carry = cfg->precision == DASH_PREC_MIXED ? al(2 * 2 * Kc * YS) + al(4 * 2 * Kc * R * R) : 0;
   const int64_t lag = cfg->stats_mode == DASH_STATS_LAGGED
                           ? al(8 * 2 * Kc * R) + al(8 * 2 * ((int64_t)cfg->J * R + R * R)) : 0;
   const int64_t split = al(8 * Kc * R) + al(8 * std::min<int64_t>(Kc, kMaxChunks2) * (R * R + 1)) +
@@ -793,7 +802,7 @@ dash_status create_context(const dash_config *cfg, hipStream_t stream, bool serv
     ok = dalloc(&c->cst, sizeof(double) * 2 * Kc * R) == hipSuccess &&
          dalloc(&c->FG, sizeof(double) * 2 * (J * R + R * R)) == hipSuccess;
   if (ok && cfg->precision == DASH_PREC_MIXED)
-    ok = dalloc(&c->Yc, sizeof(float) * 2 * Kc * YS) == hipSuccess &&
+    ok = dalloc(&c->Yc, sizeof(uint16_t) * 2 * Kc * YS) == hipSuccess &&
          dalloc(&c->Dc, sizeof(float) * 2 * Kc * R * R) == hipSuccess;
   if (!ok) return bail(DASH_E_OUT_OF_MEMORY);
   c->off_args = align_up(sizeof(StepHeader), 64);
@@ -817,7 +826,7 @@ dash_status create_context(const dash_config *cfg, hipStream_t stream, bool serv
   if (hipHostGetDevicePointer((void **)&c->dreport, c->hreport, 0) != hipSuccess) return bail(DASH_E_DEVICE);
   if (hipMemsetAsync(c->Y, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess ||
       hipMemsetAsync(c->cur, 0, (size_t)(2 * Kc), c->stream) != hipSuccess ||
-      (c->Yc && hipMemsetAsync(c->Yc, 0, sizeof(float) * 2 * Kc * YS, c->stream) != hipSuccess) ||
+      (c->Yc && hipMemsetAsync(c->Yc, 0, sizeof(uint16_t) * 2 * Kc * YS, c->stream) != hipSuccess) ||
       (c->Dc && hipMemsetAsync(c->Dc, 0, sizeof(float) * 2 * Kc * R * R, c->stream) != hipSuccess) ||
       hipMemsetAsync(c->tlast, 0, sizeof(int32_t) * 2 * Kc, c->stream) != hipSuccess ||
       hipMemsetAsync(c->counters, 0, sizeof(int32_t) * (kMaxChunks + 1), c->stream) != hipSuccess ||
@@ -1674,15 +1683,16 @@ dash_status dash_set_state(dash_ctx *c, int32_t K, const double *V, const double
   // only host-side arithmetic (a mixed-precision context also keeps the
   // remainder of the cast as its compensation word)
   std::vector<float> f((size_t)std::max<int64_t>(K * R * J, K * R * R)), lo(c->Yc ? f.size() : 0);
+  std::vector<uint16_t> lob(c->Yc ? (size_t)(K * R * J) : 0);
   for (int64_t i = 0; i < K * R * J; ++i) {
     f[i] = (float)Y[i];
-    if (c->Yc) lo[i] = (float)(Y[i] - (double)f[i]);
+    if (c->Yc) lob[i] = bf16_bits((float)(Y[i] - (double)f[i]));
   }
   HIP_OR_FAIL(c, hipMemcpy2D(c->Y, sizeof(float) * y_stride(c->J, c->R), f.data(), sizeof(float) * R * J,
                              sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
   if (c->Yc)
-    HIP_OR_FAIL(c, hipMemcpy2D(c->Yc, sizeof(float) * y_stride(c->J, c->R), lo.data(), sizeof(float) * R * J,
-                               sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
+    HIP_OR_FAIL(c, hipMemcpy2D(c->Yc, sizeof(uint16_t) * y_stride(c->J, c->R), lob.data(), sizeof(uint16_t) * R * J,
+                               sizeof(uint16_t) * R * J, (size_t)K, hipMemcpyHostToDevice));
   for (int64_t i = 0; i < K * R * R; ++i) {
     f[i] = (float)D[i];
     if (c->Dc) lo[i] = (float)(D[i] - (double)f[i]);
@@ -1747,9 +1757,9 @@ dash_status dash_save(dash_ctx *c, const char *path) {
   if (he == hipSuccess) he = hipMemcpy(n.data(), dn, sizeof(double) * n.size(), hipMemcpyDeviceToHost);
   std::vector<float> Yc(c->Yc ? Y.size() : 0), Dc(c->Dc ? D.size() : 0);
   if (c->Yc && he == hipSuccess) {
-    // the carry arrays share the layout of Y and D: gathered by the same kernel
-    he = (hipError_t)launch_gather_state(c->J, c->R, c->K, c->Yc, c->Dc, c->n,
-                                         c->cur + (int64_t)ctl.gcur * c->K_cap, c->K_cap, dY, dD, dn, c->stream);
+    // the carry arrays share the layout of Y and D (Y's widened from BF16)
+    he = (hipError_t)launch_gather_carry(c->J, c->R, c->K, c->Yc, c->Dc, c->cur + (int64_t)ctl.gcur * c->K_cap,
+                                         c->K_cap, dY, dD, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he == hipSuccess) he = hipMemcpy(Yc.data(), dY, sizeof(float) * Yc.size(), hipMemcpyDeviceToHost);
     if (he == hipSuccess) he = hipMemcpy(Dc.data(), dD, sizeof(float) * Dc.size(), hipMemcpyDeviceToHost);
@@ -1818,8 +1828,10 @@ dash_status dash_load(dash_ctx *c, const char *path) {
                              sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
   HIP_OR_FAIL(c, hipMemcpy(c->D, D.data(), sizeof(float) * D.size(), hipMemcpyHostToDevice));
   if (c->Yc && h.carry) {   // a float32 context drops the words; a mixed one without them starts at zero
-    HIP_OR_FAIL(c, hipMemcpy2D(c->Yc, sizeof(float) * y_stride(c->J, c->R), Yc.data(), sizeof(float) * R * J,
-                               sizeof(float) * R * J, (size_t)K, hipMemcpyHostToDevice));
+    std::vector<uint16_t> yb(Yc.size());
+    for (size_t i = 0; i < Yc.size(); ++i) yb[i] = bf16_bits(Yc[i]);
+    HIP_OR_FAIL(c, hipMemcpy2D(c->Yc, sizeof(uint16_t) * y_stride(c->J, c->R), yb.data(), sizeof(uint16_t) * R * J,
+                               sizeof(uint16_t) * R * J, (size_t)K, hipMemcpyHostToDevice));
     HIP_OR_FAIL(c, hipMemcpy(c->Dc, Dc.data(), sizeof(float) * Dc.size(), hipMemcpyHostToDevice));
   }
   HIP_OR_FAIL(c, hipMemcpy(c->n, n.data(), sizeof(double) * n.size(), hipMemcpyHostToDevice));

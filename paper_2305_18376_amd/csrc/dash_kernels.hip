@@ -922,7 +922,7 @@ __global__ void k_f64_to_f32(int64_t count, const double *src, float *dst) {
 __global__ void k_export_state(int J, int R, int K, int64_t step, double lambda, const float *Y,
                                const float *D, const double *n, const uint8_t *cur,
                                const int32_t *tlast, int64_t K_cap, double *Yo, double *Do,
-                               double *no, const float *Yc, const float *Dc) {
+                               double *no, const uint16_t *Yc, const float *Dc) {
   const int k = blockIdx.x;
   if (k >= K) return;
   const int b = cur[k];
@@ -930,7 +930,7 @@ __global__ void k_export_state(int J, int R, int K, int64_t step, double lambda,
   const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R, YS = y_stride(J, R);
   for (int e = threadIdx.x; e < RJ; e += 256) {
     const int64_t i = ((int64_t)b * K_cap + k) * YS + e;
-    Yo[k * RJ + e] = s * ((double)Y[i] + (Yc ? (double)Yc[i] : 0.0));
+    Yo[k * RJ + e] = s * ((double)Y[i] + (Yc ? (double)__uint_as_float((uint32_t)Yc[i] << 16) : 0.0));
   }
   for (int e = threadIdx.x; e < RR; e += 256) {
     const int64_t i = ((int64_t)b * K_cap + k) * RR + e;
@@ -949,6 +949,19 @@ __global__ void k_gather_state(int J, int R, int K, const float *Y, const float 
   for (int e = threadIdx.x; e < RJ; e += 256) Yo[k * RJ + e] = Y[((int64_t)b * K_cap + k) * YS + e];
   for (int e = threadIdx.x; e < RR; e += 256) Do[k * RR + e] = D[((int64_t)b * K_cap + k) * RR + e];
   if (threadIdx.x == 0) no[k] = n[(int64_t)b * K_cap + k];
+}
+
+// The compensation words of the current buffers (Y's as BF16, widened), same
+// layout as k_gather_state's output.
+__global__ void k_gather_carry(int J, int R, int K, const uint16_t *Yc, const float *Dc, const uint8_t *cur,
+                               int64_t K_cap, float *Yo, float *Do) {
+  const int k = blockIdx.x;
+  if (k >= K) return;
+  const int b = cur[k];
+  const int64_t RJ = (int64_t)R * J, RR = (int64_t)R * R, YS = y_stride(J, R);
+  for (int e = threadIdx.x; e < RJ; e += 256)
+    Yo[k * RJ + e] = __uint_as_float((uint32_t)Yc[((int64_t)b * K_cap + k) * YS + e] << 16);
+  for (int e = threadIdx.x; e < RR; e += 256) Do[k * RR + e] = Dc[((int64_t)b * K_cap + k) * RR + e];
 }
 
 // ---------------------------------------------------------------------------
@@ -1147,7 +1160,7 @@ int launch_to_f32(const double *src, float *dst, int64_t count, hipStream_t s) {
 
 int launch_export_state(int J, int R, int K, int64_t step, double lambda, const float *Y,
                         const float *D, const double *n, const uint8_t *cur, const int32_t *tlast,
-                        int64_t K_cap, double *Yo, double *Do, double *no, const float *Yc, const float *Dc,
+                        int64_t K_cap, double *Yo, double *Do, double *no, const uint16_t *Yc, const float *Dc,
                         hipStream_t s) {
   if (K <= 0) return 0;
   hipLaunchKernelGGL(k_export_state, dim3(K), dim3(256), 0, s, J, R, K, step, lambda, Y, D, n, cur,
@@ -1160,6 +1173,13 @@ int launch_gather_state(int J, int R, int K, const float *Y, const float *D, con
                         hipStream_t s) {
   if (K <= 0) return 0;
   hipLaunchKernelGGL(k_gather_state, dim3(K), dim3(256), 0, s, J, R, K, Y, D, n, cur, K_cap, Yo, Do, no);
+  return (int)hipGetLastError();
+}
+
+int launch_gather_carry(int J, int R, int K, const uint16_t *Yc, const float *Dc, const uint8_t *cur, int64_t K_cap,
+                        float *Yo, float *Do, hipStream_t s) {
+  if (K <= 0) return 0;
+  hipLaunchKernelGGL(k_gather_carry, dim3(K), dim3(256), 0, s, J, R, K, Yc, Dc, cur, K_cap, Yo, Do);
   return (int)hipGetLastError();
 }
 

@@ -114,16 +114,17 @@ struct ProfRec {
   double bytes;
 };
 
-// Algorithmic bytes one stage must move for one stream's update (the model
-// of the design notes): w = 2 words per Y_k / D_k entry in the mixed path
-// (value and compensation), 1 in float32.
+// Algorithmic bytes one stage must move for one stream's update: 4 bytes per
+// Y_k / D_k entry in float32; in the mixed path 6 per Y_k entry (float32
+// value, BF16 compensation word) and 8 per D_k entry.
 double stage_bytes(int stage, const dash_ctx *c, const BuiltUpdate &b) {
   const double J = c->J, R = c->R, M = (double)b.rows, K = b.K, Kt = b.n_items;
-  const double w = c->cfg.precision == DASH_PREC_MIXED ? 2.0 : 1.0;
+  const bool mx = c->cfg.precision == DASH_PREC_MIXED;
+  const double yb = mx ? 6.0 : 4.0, db = mx ? 8.0 : 4.0;   // bytes per Y / D entry (BF16 / float32 carry)
   switch (stage) {
-    case 0: return M * J * 4 + M * R * 4 + Kt * (2 * w * (R * J + R * R) * 4 + 16 + R * 8);
+    case 0: return M * J * 4 + M * R * 4 + Kt * (2 * (R * J * yb + R * R * db) + 16 + R * 8);
     case 1: return 0.0;   // deferred slices: counted with the row stage
-    case 2: return (K - Kt) * R * J * 4 + K * w * R * R * 4 + K * (2 * R * 8 + 8) + Kt * R * 8;
+    case 2: return (K - Kt) * R * J * 4 + K * R * R * db + K * (2 * R * 8 + 8) + Kt * R * 8;
     case 3: return K * R * J * 4 + K * R * 8;
     case 4: return ((double)b.nch / kChunksPerRGroup + 1) * (R * J + R * R) * 8;
     default: return 2 * (R * J + R * R) * 8;

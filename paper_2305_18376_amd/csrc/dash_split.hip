@@ -199,7 +199,7 @@ __device__ inline double stage_rows_bf(const float *__restrict__ src, int m, int
 // the others are deferred to a list.  SLOW = true: the deferred slices, with
 // the pseudo-inverse form (a separate launch, so that its code does not weigh
 // on the registers of the common case).
-template <int RW, int JW, bool MX, bool SLOW>
+template <int RW, int JW, bool MX, bool SLOW, bool VEC = false>
 __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const BlockMap *map) {
   extern __shared__ __align__(16) unsigned char smem[];
   CPassArgs &a = *(CPassArgs *)(map ? map[blockIdx.x].args : args);
@@ -259,17 +259,29 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       sP[e] = (r < R && j < J) ? vb.P32[j * R + r] : 0.f;
     }
   }
+  // Column ownership in the [rank][column] layout: VEC (J a multiple of JW)
+  // gives lane l the JW consecutive columns JW l .. JW l + JW - 1, so each of
+  // its ranks is one 4 JW-byte access (a CU's outstanding memory requests,
+  // not bytes, bound this stage); otherwise it owns columns l, l + 64, ...
+  // (separate instantiations: carrying both costs the registers of both)
+  constexpr bool vecj = VEC;
   // the entries of V^T this thread multiplies for c_k
   float vt[RW][JW];
   {
     const auto rv = buf_rsrc(vb.Vt32, R * J * 4);
 #pragma unroll
-    for (int rr = 0; rr < RW; ++rr)
+    for (int rr = 0; rr < RW; ++rr) {
+      const int r = wv + 4 * rr;
+      if (vecj) {
+        buf_ldfn<JW>(rv, (r < R && lane * JW < J) ? (r * J + lane * JW) * 4 : kNoOff, vt[rr]);
+      } else {
 #pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
-        const int r = wv + 4 * rr, j = lane + 64 * jj;
-        vt[rr][jj] = buf_ldf(rv, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+        for (int jj = 0; jj < JW; ++jj) {
+          const int j = lane + 64 * jj;
+          vt[rr][jj] = buf_ldf(rv, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+        }
       }
+    }
   }
   // pivots and diagonal of V^T V for Lemma 1's acceptance rule (wave 0, lane r)
   const double pivl = lane < R ? vb.piv[lane] : 0.0;
@@ -375,27 +387,41 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
       const auto ry = buf_rsrc(a.Y + ybase, yb);
       const auto rd = buf_rsrc(a.D + dbase, db);
 #pragma unroll
-      for (int rr = 0; rr < RW; ++rr)
+      for (int rr = 0; rr < RW; ++rr) {
+        const int r = wv + 4 * rr;
+        if (vecj) {
+          buf_ldfn<JW>(ry, (r < R && lane * JW < J) ? (r * J + lane * JW) * 4 : kNoOff, yo[rr]);
+        } else {
 #pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
-          const int r = wv + 4 * rr, j = lane + 64 * jj;
-          yo[rr][jj] = buf_ldf(ry, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+          for (int jj = 0; jj < JW; ++jj) {
+            const int j = lane + 64 * jj;
+            yo[rr][jj] = buf_ldf(ry, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+          }
         }
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int q = tid + 256 * i;
         dold[i] = buf_ldf(rd, q < RR ? q * 4 : kNoOff);
       }
       if constexpr (MX) {
-        const auto ryc = buf_rsrc(a.Yc + ybase, yb);
+        // Y's compensation words are BF16 (the residual of the float32 word:
+        // 8 more bits, 2^-33 relative per fold, half the bytes)
+        const auto ryc = buf_rsrc(a.Yc + ybase, yb / 2);
         const auto rdc = buf_rsrc(a.Dc + dbase, db);
 #pragma unroll
-        for (int rr = 0; rr < RW; ++rr)
+        for (int rr = 0; rr < RW; ++rr) {
+          const int r = wv + 4 * rr;
+          if (vecj) {
+            buf_ldbfn<JW>(ryc, (r < R && lane * JW < J) ? (r * J + lane * JW) * 2 : kNoOff, yl[rr]);
+          } else {
 #pragma unroll
-          for (int jj = 0; jj < JW; ++jj) {
-            const int r = wv + 4 * rr, j = lane + 64 * jj;
-            yl[rr][jj] = buf_ldf(ryc, (r < R && j < J) ? (r * J + j) * 4 : kNoOff);
+            for (int jj = 0; jj < JW; ++jj) {
+              const int j = lane + 64 * jj;
+              yl[rr][jj] = buf_ldbf(ryc, (r < R && j < J) ? (r * J + j) * 2 : kNoOff);
+            }
           }
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int q = tid + 256 * i;
@@ -626,37 +652,50 @@ __global__ __launch_bounds__(256, 2) void k_rows(const PassArgs *args, const Blo
     double cpart[RW];
     {
       const auto wy = buf_rsrc(a.Y + ynext, R * J * 4);
-      const auto wyc = buf_rsrc(MX ? a.Yc + ynext : a.Y, MX ? R * J * 4 : 0);
+      const auto wyc = buf_rsrc(MX ? (const void *)(a.Yc + ynext) : (const void *)a.Y, MX ? R * J * 2 : 0);
       const bool lag = a.lagged;
 #pragma unroll
       for (int rr = 0; rr < RW; ++rr) {
         const int r = wv + 4 * rr;
         cpart[rr] = 0.0;
+        float yv[JW], lo[JW];
 #pragma unroll
         for (int jj = 0; jj < JW; ++jj) {
-          const int j = lane + 64 * jj;
+          const int j = vecj ? lane * JW + jj : lane + 64 * jj;
           const bool in = r < R && j < J;
           const float dyl = sDY[min(r, R - 1) * J + min(j, J - 1)];
           const float dy = in ? dyl : 0.f;
-          const int off = in ? (r * J + j) * 4 : kNoOff;
           double cv;
           if constexpr (MX) {
             // compensated running sum: (hi, lo) folded in FP64 and split again
             const double v = s_old * ((double)yo[rr][jj] + (double)yl[rr][jj]) + (double)dy;
             const float hi = (float)v;
-            buf_stf(wy, off, hi);
-            buf_stf(wyc, off, (float)(v - (double)hi));
+            yv[jj] = hi;
+            lo[jj] = (float)(v - (double)hi);
             cv = lag ? (double)dy : v;
           } else {
-            const float yv = fmaf(s_old_f, yo[rr][jj], dy);
-            buf_stf(wy, off, yv);
-            cv = lag ? (double)dy : (double)yv;
+            yv[jj] = fmaf(s_old_f, yo[rr][jj], dy);
+            lo[jj] = 0.f;
+            cv = lag ? (double)dy : (double)yv[jj];
           }
           // V^T's entry converted here, not hoisted out of the slice loop
           // as 32 more double registers
           float vtc = vt[rr][jj];
           asm volatile("" : "+v"(vtc));
           cpart[rr] = fma(cv, (double)vtc, cpart[rr]);
+        }
+        if (vecj) {
+          const bool in = r < R && lane * JW < J;
+          buf_stfn<JW>(wy, in ? (r * J + lane * JW) * 4 : kNoOff, yv);
+          if constexpr (MX) buf_stbfn<JW>(wyc, in ? (r * J + lane * JW) * 2 : kNoOff, lo);
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < JW; ++jj) {
+            const int j = lane + 64 * jj;
+            const bool in = r < R && j < J;
+            buf_stf(wy, in ? (r * J + j) * 4 : kNoOff, yv[jj]);
+            if constexpr (MX) buf_stbf(wyc, in ? (r * J + j) * 2 : kNoOff, lo[jj]);
+          }
         }
       }
     }
@@ -1524,7 +1563,9 @@ static inline int rw_bucket(int R) { return R <= 8 ? 2 : (R <= 16 ? 4 : 8); }
 static inline int jw_bucket(int J) { return J <= 64 ? 1 : (J <= 128 ? 2 : 4); }
 static inline int rm_bucket(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
 
-int split_rows_class(int J, int R, int mixed) { return (rw_bucket(R) * 8 + jw_bucket(J)) * 2 + (mixed ? 1 : 0); }
+int split_rows_class(int J, int R, int mixed) {
+  return ((rw_bucket(R) * 8 + jw_bucket(J)) * 2 + (mixed ? 1 : 0)) * 2 + (J % jw_bucket(J) == 0 ? 1 : 0);
+}
 int split_solve_class(int R) { return rm_bucket(R); }
 int split_fsum_class(int J, int R, int lagged, int mixed) {
   return lagged ? 1000 + split_rows_class(J, R, mixed) : (J & 3) ? 5 : ept_bucket(y_stride(J, R));
@@ -1548,7 +1589,10 @@ int launch_split_solve_fix(const PassArgs *args, const BlockMap *map, int n_bloc
 void split_kernel_name(int stage, const PassArgs &a, char *buf, size_t n) {
   const int mx = a.mixed ? 1 : 0;
   switch (stage) {
-    case 0: snprintf(buf, n, "k_rows<%d, %d, %s, false>", rw_bucket(a.R), jw_bucket(a.J), mx ? "true" : "false"); break;
+    case 0:
+      snprintf(buf, n, "k_rows<%d, %d, %s, false, %s>", rw_bucket(a.R), jw_bucket(a.J), mx ? "true" : "false",
+               a.J % jw_bucket(a.J) == 0 ? "true" : "false");
+      break;
     case 1: snprintf(buf, n, "k_rows<8, 4, %s, true>", mx ? "true" : "false"); break;
     case 2: snprintf(buf, n, "k_solve<%d>", rm_bucket(a.R)); break;
     case 3:
@@ -1570,18 +1614,24 @@ size_t split_fsum_lds(int J, int R, int lagged) {
 }
 
 template <int RW, int JW, bool MX>
-static int launch_rows_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes, hipStream_t s) {
-  if (int e = allow_lds_s(k_rows<RW, JW, MX, false>, bytes)) return e;
-  hipLaunchKernelGGL((k_rows<RW, JW, MX, false>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+static int launch_rows_t(const PassArgs *args, const BlockMap *map, int n_blocks, size_t bytes, hipStream_t s,
+                         bool vec) {
+  if (vec) {
+    if (int e = allow_lds_s(k_rows<RW, JW, MX, false, true>, bytes)) return e;
+    hipLaunchKernelGGL((k_rows<RW, JW, MX, false, true>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  } else {
+    if (int e = allow_lds_s(k_rows<RW, JW, MX, false>, bytes)) return e;
+    hipLaunchKernelGGL((k_rows<RW, JW, MX, false>), dim3(n_blocks), dim3(256), bytes, s, args, map);
+  }
   return (int)hipGetLastError();
 }
 
 template <int RW, int JW, bool MX>
 static int rows_occupancy_t(int J, int R) {
   const size_t bytes = rows_fast_lds(J, R, MX);
-  if (allow_lds_s(k_rows<RW, JW, MX, false>, bytes)) return 1;
+  if (allow_lds_s(k_rows<RW, JW, MX, false, true>, bytes)) return 1;
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows<RW, JW, MX, false>, 256, bytes) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows<RW, JW, MX, false, true>, 256, bytes) != hipSuccess ||
       n < 1)
     return 1;
   return n;
@@ -1614,9 +1664,9 @@ int launch_split_rows(const PassArgs &a, const PassArgs *args, const BlockMap *m
   if (n_blocks <= 0) return 0;
   const size_t bytes = lds ? lds : rows_fast_lds(a.J, a.R, a.mixed != 0);
   if (a.mixed) {
-    DASH_RW_JW_SWITCH(launch_rows_t, true, args, map, n_blocks, bytes, s)
+    DASH_RW_JW_SWITCH(launch_rows_t, true, args, map, n_blocks, bytes, s, a.J % jw_bucket(a.J) == 0)
   } else {
-    DASH_RW_JW_SWITCH(launch_rows_t, false, args, map, n_blocks, bytes, s)
+    DASH_RW_JW_SWITCH(launch_rows_t, false, args, map, n_blocks, bytes, s, a.J % jw_bucket(a.J) == 0)
   }
 }
 

@@ -44,6 +44,83 @@ __device__ __forceinline__ void buf_stf(__amdgpu_buffer_rsrc_t r, int off, float
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
 }
 
+// N consecutive float words (N = 1, 2, 4) in one access; with a range check
+// per access, all N must lie inside or outside the buffer together.
+template <int N>
+__device__ __forceinline__ void buf_ldfn(__amdgpu_buffer_rsrc_t r, int off, float (&o)[N]) {
+  if constexpr (N == 1) {
+    o[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else if constexpr (N == 2) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    o[0] = __uint_as_float(v[0]);
+    o[1] = __uint_as_float(v[1]);
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = __uint_as_float(v[i]);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void buf_stfn(__amdgpu_buffer_rsrc_t r, int off, const float (&x)[N]) {
+  if constexpr (N == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[0]), r, off, 0, 0);
+  } else if constexpr (N == 2) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = {__float_as_uint(x[0]), __float_as_uint(x[1])};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  } else {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 v = {__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]), __float_as_uint(x[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+  }
+}
+
+// N consecutive BF16 words widened to float (N = 1, 2, 4: 2, 4 or 8 bytes)
+template <int N>
+__device__ __forceinline__ void buf_ldbfn(__amdgpu_buffer_rsrc_t r, int off, float (&o)[N]) {
+  if constexpr (N == 1) {
+    o[0] = __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
+  } else if constexpr (N == 2) {
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    o[0] = __uint_as_float(v << 16);
+    o[1] = __uint_as_float(v & 0xffff0000u);
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    o[0] = __uint_as_float(v[0] << 16);
+    o[1] = __uint_as_float(v[0] & 0xffff0000u);
+    o[2] = __uint_as_float(v[1] << 16);
+    o[3] = __uint_as_float(v[1] & 0xffff0000u);
+  }
+}
+
+// N floats rounded to nearest even BF16 and stored as N consecutive words
+template <int N>
+__device__ __forceinline__ void buf_stbfn(__amdgpu_buffer_rsrc_t r, int off, const float (&x)[N]) {
+  uint32_t b[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) b[i] = __builtin_bit_cast(uint16_t, (__bf16)x[i]);
+  if constexpr (N == 1) {
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)b[0], r, off, 0, 0);
+  } else if constexpr (N == 2) {
+    __builtin_amdgcn_raw_buffer_store_b32(b[0] | (b[1] << 16), r, off, 0, 0);
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = {b[0] | (b[1] << 16), b[2] | (b[3] << 16)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  }
+}
+
+// BF16 words (the compensation words of Y): loaded widened to float, stored
+// rounded to nearest even
+__device__ __forceinline__ float buf_ldbf(__amdgpu_buffer_rsrc_t r, int off) {
+  return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
+}
+
+__device__ __forceinline__ void buf_stbf(__amdgpu_buffer_rsrc_t r, int off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (__bf16)v), r, off, 0, 0);
+}
+
 // A value the whole wave shares, read from lane 0 (so that the compiler keeps
 // it, and what is derived from it, in scalar registers).
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }

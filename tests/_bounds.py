@@ -30,6 +30,7 @@ import numpy as np
 
 U32 = 2.0 ** -24
 UB = 2.0 ** -8        # a product of two BF16-rounded operands (2^-9 each)
+UC = 2.0 ** -33       # the mixed path's Y pair: float32 word plus the residual rounded to BF16 (2^-24 * 2^-9)
 SAFETY = 4.0
 
 
@@ -62,10 +63,12 @@ def update_bounds(pre, post, lam, xs, us, mixed=False):
         if k in xs:
             X, U = xs[k], us[k]
             m = X.shape[0]
-            store = 0.0 if mixed else U32   # the mixed path keeps a compensation word
+            # the mixed path keeps a compensation word: BF16 for Y, float32 for D
+            store = UC if mixed else U32
+            store_d = 0.0 if mixed else U32
             bY[k] = store * (2 * lam * np.abs(Y_old) + np.abs(Yp[k])) + U32 * np.abs(Yp[k]) \
                 + (m + 2) * prod_u * (np.abs(U).T @ np.abs(X)) + bU[k].T @ np.abs(X)
-            bD[k] = store * (2 * lam * np.abs(D_old) + np.abs(Dp[k])) + U32 * np.abs(Dp[k]) \
+            bD[k] = store_d * (2 * lam * np.abs(D_old) + np.abs(Dp[k])) + U32 * np.abs(Dp[k]) \
                 + (m + 2) * prod_u * (np.abs(U).T @ np.abs(U)) + bU[k].T @ np.abs(U) + np.abs(U).T @ bU[k]
         else:
             bY[k] = 2 * U32 * np.abs(Yp[k])
