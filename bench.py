@@ -92,10 +92,13 @@ def _source_digest():
     return h.hexdigest()
 
 
-def counter_traffic(kernel, workload):
+def counter_traffic(kernel, workload, algorithmic_per_launch=None):
     """HBM bytes per dispatch of `kernel` from the committed byte-counter
-    summary (profiles/<kernel>_<workload>_counters.md), or None when that
-    summary is missing or was taken on a different kernel source."""
+    summary (profiles/<kernel>_<workload>_counters.md): the summary's
+    traffic-to-algorithmic ratio times this run's algorithmic bytes per launch
+    when given (a serving launch's size depends on the tick), else its bytes
+    per dispatch; None when that summary is missing or was taken on a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
@@ -108,6 +111,8 @@ def counter_traffic(kernel, workload):
     if vals.get("kernel_source_sha256") != _source_digest():
         return None
     try:
+        if algorithmic_per_launch:
+            return float(vals["traffic_over_algorithmic"]) * float(algorithmic_per_launch)
         return float(vals["traffic_bytes_per_dispatch"])
     except (KeyError, ValueError):
         return None
@@ -296,7 +301,8 @@ def main():
         "gen_s": t_gen,
     }
 
-    tr = counter_traffic(kernel, args.workload + ("" if args.precision == "fp32" else "_mixed"))
+    tr = counter_traffic(kernel, args.workload + ("" if args.precision == "fp32" else "_mixed"),
+                         out["roofline"].get("algorithmic_bytes_per_launch"))
     out["roofline"]["traffic"] = tr
     if not args.no_oracle:
         out["fit_check"], out["cpu_baseline"] = oracle_leg(wl, ptr, X, U, batches, gpu_fits, last["fit"],
@@ -590,7 +596,8 @@ def serve_main(args):
                     algorithmic_bytes_per_launch=kern["bytes"] / kern["launches"],
                     timing=f"HIP events on the server's stream around every launch of every "
                            f"{args.sample_every}-th tick of the closed loop ({kticks} ticks timed)")
-        roof["traffic"] = counter_traffic(kern["name"].split("<")[0], "serve_mixed" if prec else "serve")
+        roof["traffic"] = counter_traffic(kern["name"].split("<")[0], "serve_mixed" if prec else "serve",
+                                          kern["bytes"] / kern["launches"])
     ticks_closed = st_closed["ticks"] - st_open["ticks"]
     out = {
         "metric": METRIC,
