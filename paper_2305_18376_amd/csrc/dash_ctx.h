@@ -103,6 +103,7 @@ struct dash_ctx {
   bool desc_fetch = true;   // true: copy each descriptor to device memory first; false: kernels read it in place
   size_t off_args = 0, off_gptr = 0, off_groups = 0, step_bytes = 0;   // descriptor layout
   int variant = kPassWave;
+  bool variant_forced = false;   // the wave sweep at every K (a test override)
   Schedule sched{kPassWave, 1, 1};         // current schedule
   // autotuning (dash_autotune): candidates tried in turn over the next updates,
   // each scored by device time per algorithmic byte; the best is kept

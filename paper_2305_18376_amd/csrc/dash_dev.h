@@ -15,6 +15,8 @@ constexpr double kPivotRel = 1e-12;   // Cholesky pivot threshold relative to ma
 constexpr double kEigCutoff = 1e-12;  // pseudo-inverse / inverse-sqrt eigenvalue cutoff
 constexpr int kReportRing = 64;       // pinned report slots (updates in flight)
 constexpr int kMaxChunks = 4096;      // bound on sweep chunks (partials memory)
+constexpr int kWaveWarps = 8;         // waves per workgroup of the wave sweep
+constexpr int kWaveMaxSlices = 4;     // default schedule: the wave sweep while each wave holds at most this many slices
 constexpr int kChunksPerRGroup = 16;  // first-level reduction fan-in
 
 // Per-update descriptor block, written by the host into pinned memory and

@@ -742,8 +742,10 @@ dash_status create_context(const dash_config *cfg, hipStream_t stream, bool serv
   c->N_init_cap = cfg->max_init_rows;
   c->served = served;
   c->variant = pass_variant(cfg->J, cfg->R, cfg->precision, cfg->stats_mode == DASH_STATS_LAGGED);
-  if (const char *e = std::getenv("DASH_VARIANT"))
+  if (const char *e = std::getenv("DASH_VARIANT")) {
     if (std::atoi(e) == kPassSplit) c->variant = kPassSplit;
+    else if (std::atoi(e) == kPassWave && c->variant == kPassWave) c->variant_forced = true;
+  }
   if (served) c->variant = kPassSplit;   // the batched launches of a server tick run the split sweep
   c->fused_lds = served ? 0 : (int)fused_pass_lds(c->variant, cfg->J, cfg->R);
   if (const char *e = std::getenv("DASH_FUSE"))
@@ -1299,6 +1301,16 @@ dash_status dash_update_async(dash_ctx *c) {
       c->tuned = true;
       c->tune_from_cache = true;
     }
+  }
+  // The default schedule of a context the wave sweep fits: that sweep while
+  // each wave holds at most kWaveMaxSlices slices, the split sweep beyond
+  // (faster there on this device, and its F sums stay FP64 throughout).  A
+  // tuned or cached schedule is left as it is.
+  if (c->variant == kPassWave && !c->variant_forced && c->tune_cands.empty()) {
+    const int slots = kWaveWarps * std::max(1, c->n_cu);
+    const bool wave = c->K_pending <= kWaveMaxSlices * slots;
+    c->sched.variant = wave ? kPassWave : kPassSplit;
+    c->sched.fuse = (wave && c->fused_lds > 0) ? 1 : 0;
   }
   BuiltUpdate b;
   if (dash_status st = build_update(c, &b)) return st;

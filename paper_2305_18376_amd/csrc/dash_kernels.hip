@@ -296,7 +296,6 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish_dev(const PassArgs *a
 // depend on the common factor lambda^dt -- and enter F, G with sigma = lambda^dt.
 // ---------------------------------------------------------------------------
 constexpr int kWaveRows = 16;   // rows per staged block
-constexpr int kWaveWarps = 8;   // waves per workgroup
 
 struct WaveLds {
   int XS;

@@ -40,10 +40,9 @@ def oracle_run(name, R_over=None):
 
 def gpu_update(wl, ptr, X, U, pre, precision, variant, monkeypatch):
     from paper_2305_18376_amd.dash import Dash
-    if variant == "split":
-        monkeypatch.setenv("DASH_VARIANT", "1")
-    else:
-        monkeypatch.delenv("DASH_VARIANT", raising=False)
+    # "wave" forces the fused wave sweep even where the default schedule
+    # (past four slices per wave) would take the split sweep
+    monkeypatch.setenv("DASH_VARIANT", "1" if variant == "split" else "0")
     g = Dash(wl.J, wl.R, lam=wl.lam, max_slices=wl.K_max + 8, max_rows=1 << 20, max_groups=1 << 16,
              precision=precision)
     g.set_state(pre["V"], pre["W"], pre["Y"], pre["D"], pre["n"])
