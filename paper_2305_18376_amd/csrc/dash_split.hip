@@ -787,7 +787,12 @@ __host__ __device__ inline SolveLds solve_lds(int J, int R) {
   o += (size_t)R * 8;
   L.oScr = o;
   const size_t pinv = (size_t)(2 * R * R + 2 * R + 3 * 64) * 8 + 64 * 4;
-  o += pinv + (size_t)2 * (R * R + 1) * 8;   // pseudo-inverse scratch, deferred G, combined G
+  // pseudo-inverse scratch, deferred G, combined G; during the solve loop the
+  // same space holds each lane group's D_k rows (solve_drows_bytes)
+  const size_t scr = pinv + (size_t)2 * (R * R + 1) * 8;
+  const size_t rm = R <= 8 ? 8 : (R <= 16 ? 16 : 32);
+  const size_t drows = (size_t)kSolveWaves * 64 * (rm + 1) * 4;
+  o += scr > drows ? scr : drows;
   L.bytes = align_up(o, 16);
   return L;
 }
@@ -1031,6 +1036,9 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
   float *sVt = (float *)(smem + L.oVt);
   double *sScr = (double *)(smem + L.oScr);
   double *sG = sScr;   // the waves' combined G
+  // this lane group's D_k rows (row stride RM + 1: the lanes of a wave fall in
+  // distinct banks), kept from the system's load for the G terms
+  float *sD = (float *)sScr + (wv * S + grp) * RM * (RM + 1) + r * (RM + 1);
   const int chunk2 = blk;
   const int k0 = chunk2 * h->chunk2;
   const int k1 = min(K, k0 + h->chunk2);
@@ -1076,6 +1084,12 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
           d_row_from_raw<RM>(dr, x.Dcp != nullptr, R, r, m);
         else
           load_d_row<RM>(x, R, r, m);
+        if (do_g) {
+          // D_k's row rounded to float (the mixed path's (hi, lo) pair to its
+          // nearest float, the G terms' FP32 operand); zeros beyond R
+#pragma unroll
+          for (int c = 0; c < RM; ++c) sD[c] = (float)m[c];
+        }
 #pragma unroll
         for (int c = 0; c < RM; ++c) m[c] = (r < R && c < R) ? sVtV[r * (R + 1) + c] * m[c] : 0.0;
         double dpiv;
@@ -1100,7 +1114,12 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
         // row r of G += sigma_k diag(w_k) D_k diag(w_k)
         if (do_g) {
           double d[RM];
-          load_d_row<RM>(x, R, r, d);
+          if (upd) {
+#pragma unroll
+            for (int i = 0; i < RM; ++i) d[i] = (double)sD[i];
+          } else {
+            load_d_row<RM>(x, R, r, d);
+          }
           const double sr = x.sig * w;
 #pragma unroll
           for (int i = 0; i < RM; ++i) {
@@ -1122,7 +1141,9 @@ __device__ __forceinline__ void solve_body(const PassArgs *args, const BlockMap 
     for (int i = 0; i < RM; ++i) gacc[i] += __shfl_xor(gacc[i], o, 64);
     nacc += __shfl_xor(nacc, o, 64);
   }
-  // the waves' partials in wave order (lanes 0 .. R - 1 of each hold the rows)
+  // the waves' partials in wave order (lanes 0 .. R - 1 of each hold the rows),
+  // once every wave is done with its D_k rows in the same space
+  __syncthreads();
   for (int v = 0; v < kSolveWaves; ++v) {
     if (wv == v && lane < R) {
 #pragma unroll
