@@ -294,6 +294,7 @@ def main():
                      "kernel": kernel, "algorithmic_bytes_per_step": bytes_all / K_,
                      "algorithmic_bytes_per_launch": bytes_pass / n_sampled if n_sampled else None,
                      "avg_launch_us": 1e3 * pass_ms / n_sampled if n_sampled else None,
+                     "launches": n_sampled,
                      "timing": f"HIP events around the row stage (and its deferred-slice launch) of every "
                                f"{args.sample_every}-th update" if split else
                                f"HIP events around the sweep of every {args.sample_every}-th update"},
@@ -592,7 +593,7 @@ def serve_main(args):
     if kern and kern["ms"] > 0:
         ach = kern["bytes"] / (kern["ms"] / 1e3) / 1e9
         roof.update(achieved=ach, frac=ach / HBM_PEAK_GBS, kernel=kern["name"],
-                    avg_launch_us=1e3 * kern["ms"] / kern["launches"],
+                    avg_launch_us=1e3 * kern["ms"] / kern["launches"], launches=kern["launches"],
                     algorithmic_bytes_per_launch=kern["bytes"] / kern["launches"],
                     timing=f"HIP events on the server's stream around every launch of every "
                            f"{args.sample_every}-th tick of the closed loop ({kticks} ticks timed)")
