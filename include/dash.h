@@ -135,8 +135,11 @@ dash_status dash_destroy(dash_ctx *ctx);
  * and a CP-ALS sweep H -> V -> W on Y_k = Q_k^T X_k), then the helper terms of
  * eq. [updateC_init]-[updateG_init] in the exact form Y_k = U_k^T X_k,
  * D_k = U_k^T U_k, n_k = ||X_k||^2 with U_k = Q_k H.
- *   row_ptr  host int64[K+1], row_ptr[0] = 0, non-decreasing; slice k is rows
- *            row_ptr[k] .. row_ptr[k+1]-1 of X (each slice needs >= 1 row).
+ *   row_ptr  int64[K+1] in device or host memory, row_ptr[0] = 0,
+ *            non-decreasing; slice k is rows row_ptr[k] .. row_ptr[k+1]-1 of X
+ *            (each slice needs >= 1 row).  A device array is copied to the host
+ *            (the passes are planned there) once the context's stream is idle;
+ *            borrowed for the call only.
  *   X        device float[row_ptr[K] * J].
  *   V0       device float[J*R] or NULL.
  *   report   host, may be NULL.
@@ -155,7 +158,9 @@ dash_status dash_init(dash_ctx *ctx, int32_t K, const int64_t *row_ptr, const fl
  * doubles, plus a Gram matrix's partials when V0 is NULL); larger problems get
  * DASH_E_CAPACITY with nothing done.  The call is synchronous and every call
  * on a device shares that device's array: calls that overlap on one device
- * (from several threads) race.  Other errors as dash_init. */
+ * (from several threads) race.  row_ptr must be host memory here (a device
+ * array would need a host copy): DASH_E_INVALID_ARG otherwise.  Other errors
+ * as dash_init. */
 dash_status dash_init_noalloc(dash_ctx *ctx, int32_t K, const int64_t *row_ptr, const float *X,
                               const float *V0, dash_init_report *report);
 /* Bytes of dash_init_noalloc's per-device workspace. */

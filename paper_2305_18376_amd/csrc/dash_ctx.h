@@ -198,6 +198,10 @@ dash_status create_context(const dash_config *cfg, hipStream_t stream, bool serv
 // doubles), and the initialisation itself on a given workspace (synchronous:
 // the workspace is free again when it returns).
 dash_status init_check(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X);
+// Whether p points to device memory; the initial row_ptr as host memory (a
+// device array is copied into tmp and p redirected there).
+bool on_device(const void *p);
+dash_status host_row_ptr(dash_ctx *c, const int64_t *&p, int32_t K, std::vector<int64_t> &tmp);
 size_t init_workspace_doubles(const dash_ctx *c, int32_t K, bool has_v0);
 dash_status init_with_workspace(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
                                 dash_init_report *report, double *ws);

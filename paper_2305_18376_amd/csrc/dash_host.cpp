@@ -923,6 +923,8 @@ dash_status dash_init_from_factors(dash_ctx *c, int32_t K, const int64_t *row_pt
   if (K < 1) return fail(c, DASH_E_INVALID_ARG, "K must be >= 1");
   if (K > c->K_cap) return fail(c, DASH_E_CAPACITY, "K=%d exceeds max_slices", K);
   if (!X || !U || !W || !V) return fail(c, DASH_E_INVALID_ARG, "NULL factor or data pointer");
+  std::vector<int64_t> rp_host;
+  if (dash_status s = dash::host_row_ptr(c, row_ptr, K, rp_host)) return s;
   if (dash_status s = validate_ptr(c, row_ptr, K, true)) return s;
   if (row_ptr[0] != 0) return fail(c, DASH_E_INVALID_ARG, "row_ptr[0] must be 0");
   if (dash_status s = reset_device_state(c, K, 0)) return s;
@@ -947,6 +949,30 @@ dash_status dash_init_from_factors(dash_ctx *c, int32_t K, const int64_t *row_pt
 }  // extern "C"
 
 namespace dash {
+
+// Whether p points to device memory.  Host memory the runtime does not know
+// may fail the query; that error is cleared here so that no later call
+// reports it.
+bool on_device(const void *p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+// The initial decomposition's row_ptr as host memory (the host plans the
+// passes from it): a device array of K + 1 entries is copied into tmp once the
+// context's stream is idle, and p then points there.
+dash_status host_row_ptr(dash_ctx *c, const int64_t *&p, int32_t K, std::vector<int64_t> &tmp) {
+  if (!p || K < 1 || !on_device(p)) return DASH_OK;
+  tmp.resize((size_t)K + 1);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  HIP_OR_FAIL(c, hipMemcpy(tmp.data(), p, sizeof(int64_t) * ((size_t)K + 1), hipMemcpyDeviceToHost));
+  p = tmp.data();
+  return DASH_OK;
+}
 
 dash_status init_check(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X) {
   if (!c) return DASH_E_INVALID_ARG;
@@ -1056,6 +1082,10 @@ extern "C" {
 
 dash_status dash_init(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
                       dash_init_report *report) {
+  if (!c) return DASH_E_INVALID_ARG;
+  std::vector<int64_t> rp_host;
+  if (!c->initialized && K >= 1 && K <= c->K_cap)
+    if (dash_status s = host_row_ptr(c, row_ptr, K, rp_host)) return s;
   if (dash_status s = init_check(c, K, row_ptr, X)) return s;
   // the initialisation's scratch lives for this call only
   const size_t ws_doubles = init_workspace_doubles(c, K, V0 != nullptr);

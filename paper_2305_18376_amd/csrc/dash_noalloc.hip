@@ -52,6 +52,8 @@ size_t dash_init_noalloc_limit(void) { return kScratchBytes; }
 
 dash_status dash_init_noalloc(dash_ctx *c, int32_t K, const int64_t *row_ptr, const float *X, const float *V0,
                               dash_init_report *report) {
+  if (c && row_ptr && dash::on_device(row_ptr))
+    return dash::fail(c, DASH_E_INVALID_ARG, "dash_init_noalloc takes row_ptr in host memory");
   if (dash_status s = dash::init_check(c, K, row_ptr, X)) return s;
   const size_t need = dash::init_workspace_doubles(c, K, V0 != nullptr);
   if (need > kScratchDoubles)

@@ -219,6 +219,17 @@ def _host(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
+def _init_row_ptr(row_ptr):
+    """(K, array) of an initial decomposition's row_ptr: a contiguous int64
+    device tensor goes to the library as it is (the library copies it to the
+    host), anything else as a host int64 array."""
+    if getattr(row_ptr, "is_cuda", False):
+        assert str(row_ptr.dtype) == "torch.int64" and row_ptr.dim() == 1, "row_ptr: 1-D int64 tensor"
+        return row_ptr.numel() - 1, row_ptr
+    rp = _host(row_ptr, np.int64)
+    return rp.shape[0] - 1, rp
+
+
 class Dash:
     """One streaming decomposition (one C context)."""
 
@@ -272,15 +283,14 @@ class Dash:
 
     # ---------------------------------------------------------------- init
     def init_from_factors(self, row_ptr, X, U, W, V):
-        rp = _host(row_ptr, np.int64)
-        K = rp.shape[0] - 1
+        K, rp = _init_row_ptr(row_ptr)
         self._check(lib().dash_init_from_factors(self._h, K, _ptr(rp), _ptr(X), _ptr(U), _ptr(W), _ptr(V)),
                     "dash_init_from_factors")
 
     def init(self, row_ptr, X, V0=None):
-        rp = _host(row_ptr, np.int64)
+        K, rp = _init_row_ptr(row_ptr)
         rep = InitReport()
-        self._check(lib().dash_init(self._h, rp.shape[0] - 1, _ptr(rp), _ptr(X), _ptr(V0), C.byref(rep)),
+        self._check(lib().dash_init(self._h, K, _ptr(rp), _ptr(X), _ptr(V0), C.byref(rep)),
                     "dash_init")
         return rep.as_dict()
 

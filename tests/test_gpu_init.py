@@ -8,6 +8,8 @@ the oracle's to float32 accuracy amplified by the conditioning of the ALS map:
 factors and state normwise within 1e-5; the loss, a difference of terms of
 size sum_n, within 1e-6 sum_n; the fit within 1e-5.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -123,3 +125,41 @@ def test_init_at_the_mid_workload_size():
     V0 = np.linalg.qr(rng.standard_normal((wl.J, wl.R)))[0]
     o, res, g, rep = run_pair(slices, wl.R, max_iter=2, tol=0.0, V0=V0, lam=wl.lam)
     compare(o, res, g, rep, tag="mid full size")
+
+
+def test_init_takes_row_ptr_in_device_memory():
+    """dash_init and dash_init_from_factors accept row_ptr in device memory
+    (copied to the host by the library) with results bit-identical to a host
+    row_ptr; dash_init_noalloc, which must not allocate, refuses it."""
+    from paper_2305_18376_amd import dash as D
+    wl = make_workload("tiny")
+    ptr, X, U = wl.init_data(want_u=True)
+    Xd = dev(X)
+    states = []
+    for where in ("host", "device"):
+        rp = ptr if where == "host" else torch.from_numpy(np.asarray(ptr, dtype=np.int64)).cuda()
+        g = D.Dash(wl.J, wl.R, lam=wl.lam, max_slices=256, max_rows=1 << 14, max_groups=1024,
+                   max_init_rows=int(ptr[-1]), init_max_iter=4, init_tol=0.0)
+        rep = g.init(rp, Xd)
+        f = D.Dash(wl.J, wl.R, lam=wl.lam, max_slices=256, max_rows=1 << 14, max_groups=1024)
+        f.init_from_factors(rp, Xd, dev(U), dev(wl.W[: wl.K0]), dev(wl.V))
+        print(where, rep["iters"], rep["fit"], flush=True)
+        states.append((rep, g.get_state(), f.get_state()))
+        g.close()
+        f.close()
+    (ra, ga, fa), (rb, gb, fb) = states
+    assert ra == rb, (ra, rb)
+    for key in ("V", "W", "Y", "D", "n"):
+        np.testing.assert_array_equal(ga[key], gb[key], err_msg=key)
+        np.testing.assert_array_equal(fa[key], fb[key], err_msg=key)
+    # the allocation-free variant: a device row_ptr is refused, nothing done
+    K = wl.K0
+    h = C.c_void_p()
+    cfg = D.make_config(wl.J, wl.R, wl.lam, 1, 256, 1 << 14, 1024, int(ptr[-1]), 4, 0.0, 0, D.PREC_FP32,
+                        D.STATS_EXACT)
+    assert D.lib().dash_create(C.byref(cfg), C.byref(h)) == D.OK
+    rpd = torch.from_numpy(np.asarray(ptr, dtype=np.int64)).cuda()
+    st = D.lib().dash_init_noalloc(h, K, rpd.data_ptr(), Xd.data_ptr(), None, None)
+    assert st == D.E_INVALID_ARG
+    assert b"host memory" in D.lib().dash_last_error(h)
+    assert D.lib().dash_destroy(h) == D.OK
