@@ -698,8 +698,20 @@ def study_main(args):
     dev = torch.device("cuda", 0)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
 
-    def stream(wl, lam, n_steps, cycle=None, scores=False):
+    def mean_slice_error(X, U, S, W, V):
+        # mean over slices of each slice's mean absolute error |X - U S_k V^T|
+        r = np.abs(X - (U * W[S]) @ V.T).mean(axis=1)
+        cnt = np.bincount(S)
+        tot = np.bincount(S, weights=r)
+        has = cnt > 0
+        return float(np.mean(tot[has] / cnt[has]))
+
+    def stream(wl, lam, n_steps, cycle=None, scores=False, global_err=None):
         ptr, X, U = wl.init_data(want_u=True)
+        if global_err is not None:
+            # every row seen, with its U row as the update that brought it computed it
+            acc_x, acc_u = [X.astype(np.float64)], [U.astype(np.float64)]
+            acc_s = [np.repeat(np.arange(wl.K0), np.diff(ptr))]
         g = Dash(wl.J, wl.R, lam=lam, max_slices=wl.K_max + 64, max_rows=1 << 21, max_groups=1 << 16)
         g.init_from_factors(ptr, to(X), to(U), to(wl.W[: wl.K0]), to(wl.V))
         if scores:
@@ -720,6 +732,20 @@ def study_main(args):
             torch.cuda.synchronize()
             rep = g.update()
             out.append((rep, int(rptr[-1] + b.new_ptr[-1])))
+            if global_err is not None:
+                # the global error of the evaluation section: old rows with their
+                # stored U rows, plus this update's rows, both reconstructed
+                # with the current S_k and V
+                Vc, Wc, Un = (t.cpu().numpy().astype(np.float64) for t in g.get_factors())
+                K_old = wl.K_at(s - 1)
+                new_x = np.concatenate([b.new_rows, rows]).astype(np.float64)
+                new_s = np.concatenate([np.repeat(K_old + np.arange(b.n_new), np.diff(b.new_ptr)),
+                                        np.repeat(b.row_ids.astype(np.int64), np.diff(rptr))])
+                old = mean_slice_error(np.concatenate(acc_x), np.concatenate(acc_u), np.concatenate(acc_s), Wc, Vc)
+                global_err.append(old + mean_slice_error(new_x, Un, new_s, Wc, Vc))
+                acc_x.append(new_x)
+                acc_u.append(Un)
+                acc_s.append(new_s)
         spans = g.spans_read()
         g.spans(False)
         return g, out, spans, (ptr, X)
@@ -741,16 +767,23 @@ def study_main(args):
         res["points"] = rows
     elif args.study == "lambda":
         rows = []
-        for lam in (0.1, 0.3, 0.5, 0.7, 0.9):
-            wl = make_workload("mid", n_steps=12, median=24, lo=11, hi=200)
-            g, out, _, _ = stream(wl, lam, 12, scores=True)
-            te = [o[0]["te"] for o in out[2:]]
-            rows.append({"lambda": lam, "local_error_te_mean": float(np.mean(te)),
-                         "fit_lambda_weighted": out[-1][0]["fit"]})
-            g.close()
-        res["config"] = ("mid shape, 12 updates; local error = te (Definition 2: mean absolute error of the "
-                         "updated model on each update's new rows), global = the lambda-weighted fit of the "
-                         "whole stream after the last update")
+        for drift in (0.0, 0.05):
+            for lam in (0.1, 0.3, 0.5, 0.7, 0.9):
+                wl = make_workload("mid", n_steps=16, median=24, lo=11, hi=200, drift=drift)
+                ge = []
+                g, out, _, _ = stream(wl, lam, 16, scores=True, global_err=ge)
+                te = [o[0]["te"] for o in out]
+                rows.append({"drift": drift, "lambda": lam, "local_error_mean": float(np.mean(te)),
+                             "global_error_mean": float(np.mean(ge)),
+                             "fit_lambda_weighted_last": out[-1][0]["fit"]})
+                g.close()
+        res["config"] = ("mid shape (J 88, R 10, K0 2000, initial slices median 24), 16 updates, planted V "
+                         "stationary (drift 0) or moved 5 % of the way to a second planted V per update "
+                         "(drift 0.05); local error = te (Definition 2: mean absolute error of the updated "
+                         "model on each update's new rows), global error = the evaluation section's sum of "
+                         "the mean per-slice absolute errors over the rows seen before the update (their U "
+                         "rows as computed on arrival) and over the update's rows, with the current S_k and "
+                         "V; both averaged over the updates")
         res["points"] = rows
     else:
         wl = make_workload("mid", n_steps=10, median=24, lo=11, hi=200)

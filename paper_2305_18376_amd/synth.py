@@ -94,6 +94,10 @@ class Workload:
     heavy_tail: bool = False
     arrivals: str = "uniform20"  # or "zipf"
     _tiny: dict | None = field(repr=False, default=None)
+    # concept drift: update s draws its rows with V_s = (1 - a) V + a V_end,
+    # a = min(1, drift * s); the initial tensor uses V (drift = 0: no drift)
+    drift: float = 0.0
+    V_end: np.ndarray | None = field(repr=False, default=None)
 
     @property
     def K_max(self) -> int:
@@ -109,7 +113,14 @@ class Workload:
             return rng.standard_t(3.0, size=(n, self.R))
         return rng.standard_normal((n, self.R))
 
-    def _rows_for(self, rng, slice_ids: np.ndarray, want_u: bool):
+    def V_at(self, s: int) -> np.ndarray:
+        """The planted V that update ``s`` draws its rows with (s = 0: the initial tensor)."""
+        if self.drift <= 0.0 or s == 0:
+            return self.V
+        a = min(1.0, self.drift * s)
+        return (1.0 - a) * self.V + a * self.V_end
+
+    def _rows_for(self, rng, slice_ids: np.ndarray, want_u: bool, V: np.ndarray | None = None):
         """Draw planted rows x = (u * w_k) V^T + e for each entry of slice_ids."""
         n = int(slice_ids.shape[0])
         if n == 0:
@@ -117,7 +128,7 @@ class Workload:
             return z, (np.zeros((0, self.R)) if want_u else None)
         u = self._draw_u(rng, n)
         w = self.W[slice_ids]
-        x = (u * w) @ self.V.T
+        x = (u * w) @ (self.V if V is None else V).T
         if self.noise > 0:
             sig = self.noise * np.sqrt((w * w).sum(axis=1) * (3.0 if self.heavy_tail else 1.0))
             if self.heavy_tail:
@@ -183,9 +194,10 @@ class Workload:
         row_ids = keep.astype(np.int32)
         row_ptr = _ptr(cnt[keep])
         ids = np.repeat(keep.astype(np.int64), cnt[keep])
-        rows, u = self._rows_for(rng, ids, want_u)
+        Vs = self.V_at(s)
+        rows, u = self._rows_for(rng, ids, want_u, Vs)
         new_ids = np.repeat(np.arange(K_old, K_old + self.new_per_step, dtype=np.int64), new_cnt)
-        new_rows, u_new = self._rows_for(rng, new_ids, want_u)
+        new_rows, u_new = self._rows_for(rng, new_ids, want_u, Vs)
         return StepBatch(row_ids, row_ptr, rows, _ptr(new_cnt), new_rows, u, u_new)
 
     def _tiny_step(self, s, want_u):
@@ -254,16 +266,18 @@ def _tiny(seed=1001, noise=0.01, K0=50, J=20, R=5, n_steps=10, new_per_step=5, l
 
 
 def _iid(name, seed, J, R, K0, median, lo, hi, lam, n_iter, n_steps, new_per_step, noise,
-         arrivals, heavy_tail=False, col_scale=False):
+         arrivals, heavy_tail=False, col_scale=False, drift=0.0):
     rng = _rng(seed, 0)
     K_max = K0 + new_per_step * n_steps
     V = rng.standard_normal((J, R))
     W = rng.uniform(0.5, 1.5, size=(K_max, R))
     init_len = _lognormal_lengths(rng, K0, median, lo, hi)
     cs = 10.0 ** rng.uniform(-3.0, 3.0, size=J) if col_scale else None
+    # drawn from a stream of its own, so that the other draws do not depend on it
+    V_end = _rng(seed, 7).standard_normal((J, R)) if drift > 0 else None
     return Workload(name, J, R, lam, n_iter, K0, n_steps, seed, noise, V=V, W=W,
                     init_len=init_len, kind="iid", new_per_step=new_per_step, col_scale=cs,
-                    heavy_tail=heavy_tail, arrivals=arrivals)
+                    heavy_tail=heavy_tail, arrivals=arrivals, drift=drift, V_end=V_end)
 
 
 WORKLOADS = ("tiny", "mid", "batch_r10", "batch_r20", "precision")
@@ -282,6 +296,8 @@ def make_workload(name: str, **kw) -> Workload:
     batch_r20  R=20; truncated-Zipf(1.2) arrivals of 0..200 rows per slice per update.
     precision  as batch with J=256, R=32, Student-t(3) rows and noise, column
                scales 10^U[-3,3].
+    drift=d (any iid workload): update s draws its rows with V moved a fraction
+               min(1, d s) of the way to a second planted V.
     """
     if name == "tiny":
         return _tiny(**kw)
