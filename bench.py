@@ -151,6 +151,9 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed region, one plain device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
+    ap.add_argument("--pcie", action="store_true",
+                    help="single stream: after the timed region, the same number of further updates whose rows "
+                         "are first copied from pinned host memory (reported as pcie_inclusive)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -176,22 +179,24 @@ def main():
         W_ = max(W_, 8 * args.autotune + 2)   # at most 8 candidate schedules
     K_ = args.steps if args.steps is not None else (20 if big else 90)
     n_total = W_ + K_
+    n_pcie = K_ if args.pcie else 0
     if big:
         # initial slices of log-normal length median 24 (the update cost depends on K, not on them)
-        wl = make_workload(args.workload, n_steps=n_total, median=24, lo=1, hi=200)
+        wl = make_workload(args.workload, n_steps=n_total + n_pcie, median=24, lo=1, hi=200)
         wl.init_len = np.maximum(wl.init_len, wl.R + 1)
     else:
-        wl = make_workload("mid", n_steps=max(100, n_total))
+        wl = make_workload("mid", n_steps=max(100, n_total + n_pcie))
     t0 = time.time()
     ptr, X, U = wl.init_data(want_u=True)
     batches = [wl.step(s) for s in range(1, n_total + 1)]
+    pcie_batches = [wl.step(s) for s in range(n_total + 1, n_total + n_pcie + 1)]
     t_gen = time.time() - t0
 
     dev = torch.device("cuda", 0)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
     from paper_2305_18376_amd.dash import PREC_FP32, PREC_MIXED
-    max_rows = max(64 * 1024, max(b.M for b in batches) + 1)
-    max_groups = max(8192, max(b.n_groups + b.n_new for b in batches) + 1)
+    max_rows = max(64 * 1024, max(b.M for b in batches + pcie_batches) + 1)
+    max_groups = max(8192, max(b.n_groups + b.n_new for b in batches + pcie_batches) + 1)
     g = Dash(wl.J, wl.R, lam=wl.lam, n_iter=wl.n_iter, max_slices=wl.K_max + 64,
              max_rows=max_rows, max_groups=max_groups,
              precision=PREC_MIXED if args.precision == "mixed" else PREC_FP32)
@@ -305,6 +310,8 @@ def main():
     tr = counter_traffic(kernel, args.workload + ("" if args.precision == "fp32" else "_mixed"),
                          out["roofline"].get("algorithmic_bytes_per_launch"))
     out["roofline"]["traffic"] = tr
+    if pcie_batches:
+        out["pcie_inclusive"] = pcie_phase(g, pcie_batches, dev)
     if not args.no_oracle:
         out["fit_check"], out["cpu_baseline"] = oracle_leg(wl, ptr, X, U, batches, gpu_fits, last["fit"],
                                                            args.oracle_seconds)
@@ -640,6 +647,36 @@ def serve_main(args):
     if not args.no_oracle:
         out["fit_check"], out["cpu_baseline"] = serve_oracle_leg(streams, cuts, fits, sample, args.oracle_seconds)
     print(json.dumps(out, default=_json_default), flush=True)
+
+
+def pcie_phase(g, pcie_batches, dev):
+    """Rows handed over from host memory: each update's rows are copied from
+    pinned host buffers to the device on torch's null stream, then ingested
+    and the update enqueued; the library's blocking stream follows the null
+    stream, so copy and update run in turn (no overlap).  Whole-job rows/s
+    over these updates, between two synchronisations."""
+    import torch
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).pin_memory()
+    host = [(pin(b.rows), pin(b.new_rows)) for b in pcie_batches]
+    devb = [(torch.empty(hr.shape, dtype=torch.float32, device=dev),
+             torch.empty(hn.shape, dtype=torch.float32, device=dev)) for hr, hn in host]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, (hr, hn), (dr, dn) in zip(pcie_batches, host, devb):
+        dr.copy_(hr, non_blocking=True)
+        dn.copy_(hn, non_blocking=True)
+        g.ingest_rows(b.row_ids, b.row_ptr, dr)
+        g.ingest_slices(b.new_ptr, dn)
+        g.update_async()
+    g.wait()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rows = sum(b.M for b in pcie_batches)
+    nbytes = sum(hr.numel() * 4 + hn.numel() * 4 for hr, hn in host)
+    return {"rows_per_s": rows / (t1 - t0), "updates": len(pcie_batches),
+            "h2d_bytes_per_update": nbytes / len(pcie_batches), "ms_per_update": 1e3 * (t1 - t0) / len(pcie_batches),
+            "note": "rows copied from pinned host memory on the null stream before each update; copy and "
+                    "update run in turn"}
 
 
 def serve_queueing(streams, prec, kw_of, to, budget=2 << 30, windows=10):
