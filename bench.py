@@ -135,9 +135,10 @@ def main():
     ap.add_argument("--streams", type=int, default=64, help="serve: number of streams")
     ap.add_argument("--closed-depth", type=int, default=8, help="serve: requests in flight per stream, closed loop")
     ap.add_argument("--no-queue", action="store_true", help="serve: skip the 2 GB admission-queue run")
-    ap.add_argument("--study", default=None, choices=["cycle", "lambda", "static"],
+    ap.add_argument("--study", default=None, choices=["cycle", "lambda", "static", "lagged"],
                     help="instead of the benchmark: time per update against the update cycle, the errors against "
-                         "lambda, or the streaming update against a static recompute (prints its own JSON line)")
+                         "lambda, the streaming update against a static recompute, or the exact statistics "
+                         "against the lagged recursions (prints its own JSON line)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="N > 0: the warm-up updates try every launch schedule N times and keep the fastest")
     ap.add_argument("--graph", type=int, default=0,
@@ -743,13 +744,15 @@ def study_main(args):
         has = cnt > 0
         return float(np.mean(tot[has] / cnt[has]))
 
-    def stream(wl, lam, n_steps, cycle=None, scores=False, global_err=None):
+    def stream(wl, lam, n_steps, cycle=None, scores=False, global_err=None, lagged=False):
+        from paper_2305_18376_amd.dash import STATS_EXACT, STATS_LAGGED
         ptr, X, U = wl.init_data(want_u=True)
         if global_err is not None:
             # every row seen, with its U row as the update that brought it computed it
             acc_x, acc_u = [X.astype(np.float64)], [U.astype(np.float64)]
             acc_s = [np.repeat(np.arange(wl.K0), np.diff(ptr))]
-        g = Dash(wl.J, wl.R, lam=lam, max_slices=wl.K_max + 64, max_rows=1 << 21, max_groups=1 << 16)
+        g = Dash(wl.J, wl.R, lam=lam, max_slices=wl.K_max + 64, max_rows=1 << 21, max_groups=1 << 16,
+                 stats_mode=STATS_LAGGED if lagged else STATS_EXACT)
         g.init_from_factors(ptr, to(X), to(U), to(wl.W[: wl.K0]), to(wl.V))
         if scores:
             g.anomaly(5)
@@ -821,6 +824,34 @@ def study_main(args):
                          "the mean per-slice absolute errors over the rows seen before the update (their U "
                          "rows as computed on arrival) and over the update's rows, with the current S_k and "
                          "V; both averaged over the updates")
+        res["points"] = rows
+    elif args.study == "lagged":
+        # the same stream under both statistics modes: Lemmas 2-3 evaluated from
+        # the exact Y_k, D_k (every slice's Y_k read twice per pass) against
+        # Algorithm 1's recursions of c_k, F, G (only the new rows read)
+        res_modes = {}
+        for shape in ("mid", "batch_r10"):
+            n = 24
+            for lagged in (False, True):
+                wl = make_workload(shape, n_steps=n, median=24, lo=11, hi=200)
+                g, out, spans, _ = stream(wl, wl.lam, n, lagged=lagged)
+                res_modes[(shape, lagged)] = ([o[0]["fit"] for o in out], np.array(spans[2:]) * 1e3,
+                                              [o[1] for o in out])
+                g.close()
+        rows = []
+        for shape in ("mid", "batch_r10"):
+            fe, se, me = res_modes[(shape, False)]
+            fl, sl, _ = res_modes[(shape, True)]
+            d = np.abs(np.array(fe) - np.array(fl))
+            rows.append({"workload": shape, "updates": len(fe),
+                         "exact_update_us_p50": float(np.median(se)), "lagged_update_us_p50": float(np.median(sl)),
+                         "rows_per_update": float(np.mean(me)),
+                         "fit_exact_last": fe[-1], "fit_lagged_last": fl[-1],
+                         "abs_dfit_first": float(d[0]), "abs_dfit_max": float(d.max()), "abs_dfit_last": float(d[-1])})
+        res["config"] = ("mid (J 88, R 10, K0 2000) and batching R 10 (J 128, K0 20000) shapes, initial slices "
+                         "median 24, 24 updates each, lambda 0.95, one ALS pass; the same inputs under the exact "
+                         "statistics and the lagged recursions; device span per update (p50 of updates 3..24); "
+                         "fit as each mode reports it")
         res["points"] = rows
     else:
         wl = make_workload("mid", n_steps=10, median=24, lo=11, hi=200)
