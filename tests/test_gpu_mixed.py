@@ -95,6 +95,7 @@ def test_precision_workload_error_table():
                         wl.W[: wl.K0], wl.V)
     gs = {"fp32": start(wl, PREC_FP32, ptr, X, U), "mixed": start(wl, PREC_MIXED, ptr, X, U)}
     worst = {p: {"V": 0.0, "W": 0.0, "U": 0.0, "US": 0.0, "fit": 0.0} for p in gs}
+    kappa_g, kappa_s = 0.0, 0.0
     for s in range(1, 6):
         b = wl.step(s)
         K_old = o.K
@@ -102,6 +103,12 @@ def test_precision_workload_error_table():
         ou = u_in_gpu_order(r, b)
         ids = slice_of_rows(b, K_old)
         ost = o.state()
+        # the conditioning the errors are read against: Lemma 3's G and the
+        # worst of Lemma 2's systems (V^T V) * D_k, from the oracle's state
+        Wd = ost["W"]
+        G = np.einsum("kr,krs,ks->rs", Wd, ost["D"], Wd)
+        kappa_g = max(kappa_g, float(np.linalg.cond(G)))
+        kappa_s = max(kappa_s, float(np.max(np.linalg.cond((ost["V"].T @ ost["V"])[None] * ost["D"]))))
         for p, g in gs.items():
             feed(g, b)
             rep = g.update()
@@ -117,6 +124,8 @@ def test_precision_workload_error_table():
           "US = U_new S_k):", flush=True)
     for p in gs:
         print(f"  {p:6s}", {k: f"{v:.2e}" for k, v in worst[p].items()}, flush=True)
+    print(f"  conditioning (largest over the 5 updates): kappa(G) = {kappa_g:.3e}, "
+          f"max_k kappa((V^T V) * D_k) = {kappa_s:.3e}", flush=True)
     assert worst["fp32"]["fit"] <= 1e-5
     assert worst["mixed"]["fit"] <= 1e-3
 
